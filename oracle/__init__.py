@@ -1,0 +1,232 @@
+"""CPU oracle of the per-segment plane-sweep matching cost volume.
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  The GPU library never loads it,
+and it shares no code, header or table with the GPU library.
+
+Two independent implementations live here:
+  * oracle.c  -- FP64 C with OpenMP, ray-plane intersection per pixel and
+    label (the paper's inter-view matching core, Sec. III-C Eq. (4), taken
+    over every pixel of a segment, minimum over target views);
+  * brute.py  -- pure-Python loops for tiny inputs, used to check oracle.c.
+
+Every function here is pinned by tests against closed forms, exact
+zero-cost scenes, invariants and hand-derived values (tests/test_oracle_*.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.c")
+
+# depth reference selectors (match the C convention)
+REF_RIG_CENTER = -1
+REF_OWN = -2
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                        "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra",
+                        "-o", tmp, SRC, "-lm"], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_views", ctypes.c_int32),
+        ("K", ctypes.POINTER(ctypes.c_double)),
+        ("R", ctypes.POINTER(ctypes.c_double)),
+        ("t", ctypes.POINTER(ctypes.c_double)),
+        ("width", ctypes.POINTER(ctypes.c_int32)),
+        ("height", ctypes.POINTER(ctypes.c_int32)),
+        ("planes", ctypes.POINTER(ctypes.c_void_p)),
+        ("pitch", ctypes.POINTER(ctypes.c_int64)),
+        ("bit_depth", ctypes.c_int32),
+        ("chroma_shift", ctypes.c_int32),
+        ("seg", ctypes.POINTER(ctypes.c_void_p)),
+        ("num_segments", ctypes.POINTER(ctypes.c_int32)),
+        ("z_near", ctypes.c_double),
+        ("z_far", ctypes.c_double),
+        ("num_labels", ctypes.c_int32),
+        ("depth_ref", ctypes.c_int32),
+        ("bilinear", ctypes.c_int32),
+        ("targets", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        lib = ctypes.CDLL(LIB)
+        lib.oracle_cost_rows.restype = ctypes.c_int
+        lib.oracle_cost_rows.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(load().oracle_num_threads())
+
+
+def target_matrix(n_views: int, targets="all", explicit=None) -> np.ndarray:
+    """n x n uint8 matrix; row c marks the target views of view c.
+
+    "all": every other view.  "nearest_lr": the nearest left and right views
+    by index (Sec. III-B: the two neighbouring views; the end views get one).
+    "explicit": the given matrix (the diagonal is ignored)."""
+    T = np.zeros((n_views, n_views), np.uint8)
+    if targets == "all":
+        T[:] = 1
+    elif targets == "nearest_lr":
+        for c in range(n_views):
+            if c > 0:
+                T[c, c - 1] = 1
+            if c + 1 < n_views:
+                T[c, c + 1] = 1
+    elif targets == "explicit":
+        T[:] = np.asarray(explicit, np.uint8) != 0
+    else:
+        raise ValueError(targets)
+    np.fill_diagonal(T, 0)
+    return T
+
+
+class Problem:
+    """Host-side description of one cost-volume problem for the oracle.
+
+    cams: objects with K, R, t (float64 arrays), width, height.
+    Y, U, V: per-view 2-D unsigned integer arrays (chroma subsampled by
+    chroma_shift).  seg: per-view int32 H x W maps; S: segment counts."""
+
+    def __init__(self, cams, Y, U, V, seg, S, bit_depth, chroma_shift, z_near, z_far,
+                 num_labels, bilinear, depth_ref=REF_RIG_CENTER, targets="all", target_explicit=None):
+        self.cams, self.Y, self.U, self.V = list(cams), list(Y), list(U), list(V)
+        self.seg, self.S = [np.ascontiguousarray(s, np.int32) for s in seg], [int(x) for x in S]
+        self.bit_depth, self.chroma_shift = int(bit_depth), int(chroma_shift)
+        self.z_near, self.z_far, self.num_labels = float(z_near), float(z_far), int(num_labels)
+        self.bilinear, self.depth_ref = bool(bilinear), int(depth_ref)
+        n = len(self.cams)
+        self.T = target_matrix(n, targets, target_explicit)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.cams, wl.Y, wl.U, wl.V, wl.seg, wl.S, wl.bit_depth, wl.chroma_shift,
+                   wl.z_near, wl.z_far, wl.num_labels, wl.bilinear, **kw)
+
+    @property
+    def n_views(self):
+        return len(self.cams)
+
+    def row_offsets(self):
+        return np.concatenate([[0], np.cumsum(self.S)]).astype(np.int64)
+
+
+def cost_rows(pb: Problem, views, segs, with_terms=False):
+    """C rows (float64, len(views) x L) for the (view, segment) pairs; with
+    with_terms also the per-target means m (NaN where nothing is valid) and
+    valid counts, both len(views) x n x L."""
+    lib = load()
+    n, L = pb.n_views, pb.num_labels
+    dt = np.uint8 if pb.bit_depth <= 8 else np.uint16
+    keep = []
+
+    def arr(a, dtype):
+        a = np.ascontiguousarray(a, dtype)
+        keep.append(a)
+        return a
+
+    K = arr(np.stack([c.K for c in pb.cams]), np.float64)
+    R = arr(np.stack([c.R for c in pb.cams]), np.float64)
+    t = arr(np.stack([c.t for c in pb.cams]), np.float64)
+    W = arr([c.width for c in pb.cams], np.int32)
+    H = arr([c.height for c in pb.cams], np.int32)
+    planes = (ctypes.c_void_p * (3 * n))()
+    pitch = arr(np.zeros(3 * n), np.int64)
+    for v in range(n):
+        for ch, P in enumerate((pb.Y[v], pb.U[v], pb.V[v])):
+            P = arr(P, dt)
+            planes[3 * v + ch] = P.ctypes.data
+            pitch[3 * v + ch] = P.shape[1]
+    segp = (ctypes.c_void_p * n)()
+    for v in range(n):
+        m = arr(pb.seg[v], np.int32)
+        if m.shape != (pb.cams[v].height, pb.cams[v].width):
+            raise ValueError("segment map shape does not match the camera")
+        segp[v] = m.ctypes.data
+    S = arr(pb.S, np.int32)
+    T = arr(pb.T, np.uint8)
+    prob = _Problem(n, K.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    R.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    W.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    H.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    ctypes.cast(planes, ctypes.POINTER(ctypes.c_void_p)),
+                    pitch.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                    pb.bit_depth, pb.chroma_shift,
+                    ctypes.cast(segp, ctypes.POINTER(ctypes.c_void_p)),
+                    S.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    pb.z_near, pb.z_far, L, pb.depth_ref, int(pb.bilinear),
+                    T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    rv = arr(views, np.int32)
+    rs = arr(segs, np.int32)
+    nr = len(rv)
+    cost = np.empty((nr, L), np.float64)
+    m = np.empty((nr, n, L), np.float64) if with_terms else None
+    nv = np.empty((nr, n, L), np.int64) if with_terms else None
+    rc = lib.oracle_cost_rows(ctypes.byref(prob), nr, rv.ctypes.data, rs.ctypes.data, cost.ctypes.data,
+                              m.ctypes.data if with_terms else None,
+                              nv.ctypes.data if with_terms else None)
+    if rc != 0:
+        raise ValueError(f"oracle_cost_rows failed with status {rc}")
+    return (cost, m, nv) if with_terms else cost
+
+
+def all_rows(pb: Problem):
+    views = np.concatenate([np.full(s, v, np.int32) for v, s in enumerate(pb.S)])
+    segs = np.concatenate([np.arange(s, dtype=np.int32) for s in pb.S])
+    return views, segs
+
+
+def cost_volume(pb: Problem, with_terms=False):
+    """The whole volume, rows in [view][segment] order, labels contiguous."""
+    return cost_rows(pb, *all_rows(pb), with_terms=with_terms)
+
+
+def argmin(C) -> np.ndarray:
+    """Lowest label attaining each row's minimum."""
+    return np.argmin(np.asarray(C), axis=-1).astype(np.int32)
+
+
+def served(prev, pb: Problem, changed):
+    """Frame cost after a temporal update: rows marked changed are
+    recomputed, the others keep the previous frame's cost (Sec. III-E:
+    unchanged segments adopt the earlier result).  prev None: every row."""
+    if prev is None:
+        return cost_volume(pb)
+    out = np.array(prev, np.float64, copy=True)
+    changed = np.asarray(changed, bool)
+    idx = np.nonzero(changed)[0]
+    if len(idx):
+        off = pb.row_offsets()
+        views = (np.searchsorted(off, idx, side="right") - 1).astype(np.int32)
+        segs = (idx - off[views]).astype(np.int32)
+        out[idx] = cost_rows(pb, views, segs)
+    return out

@@ -1,0 +1,112 @@
+"""Small seeded problems shared by the oracle pins and the GPU parity tests."""
+from __future__ import annotations
+
+import json
+import math
+import os
+from types import SimpleNamespace
+
+import numpy as np
+
+from paper_1909_02294_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def cam(K, R, t, w, h):
+    return synth.Camera(np.asarray(K, float), np.asarray(R, float), np.asarray(t, float), w, h)
+
+
+def rotation(axis, deg):
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    th = math.radians(deg)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * K @ K
+
+
+def random_images(rng, cams, bit_depth, chroma_shift):
+    hi = (1 << bit_depth) - 1
+    dt = np.uint8 if bit_depth <= 8 else np.uint16
+    Y, U, V = [], [], []
+    for c in cams:
+        w, h = c.width, c.height
+        wc, hc = (w + chroma_shift) >> chroma_shift, (h + chroma_shift) >> chroma_shift
+        Y.append(rng.integers(0, hi + 1, (h, w)).astype(dt))
+        U.append(rng.integers(0, hi + 1, (hc, wc)).astype(dt))
+        V.append(rng.integers(0, hi + 1, (hc, wc)).astype(dt))
+    return Y, U, V
+
+
+def random_segments(rng, w, h, n):
+    m, S = synth.voronoi(w, h, n, rng)
+    return m, S
+
+
+def tiny_problem(seed, n_views=3, width=12, height=8, n_seg=6, L=5, bit_depth=8,
+                 chroma_shift=0, bilinear=False, rotated=False, f=10.37):
+    """A few views of a tiny random image set with a rectified or a rotated
+    (converging) rig, for brute-force checks.  The default focal length keeps
+    rectified disparities away from exact half pixels, where nearest
+    sampling would depend on the last bit of the projection."""
+    rng = np.random.default_rng(seed)
+    if rotated:
+        cams = synth.arc_rig(n_views, radius=2.0, arc_deg=20.0, f=f, width=width, height=height)
+        # perturb every camera a little so no symmetry hides an index mistake
+        out = []
+        for c in cams:
+            Rp = rotation(rng.normal(size=3), rng.uniform(0.5, 2.0)) @ c.R
+            C = c.center + rng.normal(scale=0.01, size=3)
+            K = c.K.copy()
+            K[0, 0] *= rng.uniform(0.95, 1.05)
+            K[1, 1] *= rng.uniform(0.95, 1.05)
+            K[0, 1] = rng.uniform(-0.05, 0.05)
+            out.append(cam(K, Rp, -Rp @ C, width, height))
+        cams = out
+        z_near, z_far = 1.0, 4.0
+    else:
+        cams = synth.rectified_rig(n_views, 0.1, f, width, height)
+        z_near, z_far = 0.5, 3.0
+    Y, U, V = random_images(rng, cams, bit_depth, chroma_shift)
+    seg, S = [], []
+    for _ in cams:
+        m, s = random_segments(rng, width, height, n_seg)
+        seg.append(m)
+        S.append(s)
+    return SimpleNamespace(cams=cams, Y=Y, U=U, V=V, seg=seg, S=S, bit_depth=bit_depth,
+                           chroma_shift=chroma_shift, z_near=z_near, z_far=z_far,
+                           num_labels=L, bilinear=bilinear)
+
+
+def hand_case_problem(case_index):
+    with open(os.path.join(GOLDEN, "hand_two_view.json")) as fh:
+        g = json.load(fh)
+    w, h, f = g["width"], g["height"], g["f"]
+    K = [[f, 0, (w - 1) / 2], [0, f, (h - 1) / 2], [0, 0, 1]]
+    cams = [cam(K, np.eye(3), [-cx, 0, 0], w, h) for cx in g["centres_x"]]
+    Y = [np.array([v["Y"]], np.uint8) for v in g["views"]]
+    U = [np.array([v["U"]], np.uint8) for v in g["views"]]
+    V = [np.array([v["V"]], np.uint8) for v in g["views"]]
+    seg = [np.arange(w, dtype=np.int32)[None, :] for _ in cams]
+    c = g["cases"][case_index]
+    pb = SimpleNamespace(cams=cams, Y=Y, U=U, V=V, seg=seg, S=[w, w], bit_depth=g["bit_depth"],
+                         chroma_shift=0, z_near=c["z_near"], z_far=c["z_far"], num_labels=1,
+                         bilinear=c["sampling"] == "bilinear")
+    return pb, np.array(c["expected"])
+
+
+def fronto_plane_views(rng, cams, f, baseline_x, shifts, bit_depth=8, width=None, height=None):
+    """Views of one full-frame fronto-parallel textured plane whose disparity
+    between view c and the texture frame is the integer shifts[c]: view c
+    pixel (x, y) shows texture column x + shifts[c]."""
+    w = width or cams[0].width
+    h = height or cams[0].height
+    lo, hi = 16, (235 << (bit_depth - 8))
+    pad = int(max(abs(s) for s in shifts)) + 2
+    tex = rng.integers(lo, hi, (3, h, w + 2 * pad))
+    dt = np.uint8 if bit_depth <= 8 else np.uint16
+    Y, U, V = [], [], []
+    for s in shifts:
+        sl = tex[:, :, pad + s: pad + s + w]
+        Y.append(sl[0].astype(dt)); U.append(sl[1].astype(dt)); V.append(sl[2].astype(dt))
+    return Y, U, V

@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+* hand-derived two-view values (tests/golden/hand_two_view.json);
+* pure-Python brute force on tiny inputs (oracle/brute.py, separate code);
+* the rectified-rig closed form u' = u - f (b' - b) rho, v' = v;
+* an exact zero-cost fronto-parallel plane at integer disparities;
+* a smooth plane on the converging arc rig whose true label must win;
+* invariants: rigid motion, view permutation, 4:2:0 == replicated 4:4:4,
+  one-pixel segments and segment splits, constant images, bounds, depth
+  reference readings, reversed label range;
+* the FP16 storage bound and integer exactness of nearest sampling.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_1909_02294_amd import synth
+from tests import _problems as P
+
+
+def _pb(ns, **kw):
+    return oracle.Problem(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift,
+                          ns.z_near, ns.z_far, ns.num_labels, ns.bilinear, **kw)
+
+
+# ---------------------------------------------------------------- hand cases
+@pytest.mark.parametrize("case", [0, 1])
+def test_hand_derived_two_view(case):
+    ns, expected = P.hand_case_problem(case)
+    C = oracle.cost_volume(_pb(ns))
+    np.testing.assert_allclose(C[:, 0], expected, rtol=0, atol=1e-15)
+    T = oracle.target_matrix(2)
+    B = np.array(brute.cost_volume(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, 0,
+                                   ns.z_near, ns.z_far, 1, ns.bilinear, T))
+    np.testing.assert_allclose(B[:, 0], expected, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("bilinear", [False, True])
+@pytest.mark.parametrize("chroma_shift", [0, 1])
+def test_oracle_matches_brute_force(seed, bilinear, chroma_shift):
+    ns = P.tiny_problem(seed, n_views=3, bilinear=bilinear, chroma_shift=chroma_shift,
+                        rotated=seed % 2 == 1, bit_depth=8 if seed < 3 else 10)
+    for targets, ref, bref in (("all", oracle.REF_RIG_CENTER, "rig"),
+                               ("nearest_lr", oracle.REF_OWN, "own"),
+                               ("all", 1, 1)):
+        pb = _pb(ns, targets=targets, depth_ref=ref)
+        C = oracle.cost_volume(pb)
+        B = np.array(brute.cost_volume(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth,
+                                       ns.chroma_shift, ns.z_near, ns.z_far, ns.num_labels,
+                                       ns.bilinear, pb.T, depth_ref=bref))
+        np.testing.assert_allclose(C, B, rtol=0, atol=1e-12)
+        # the problems must exercise real matches, not only sentinels
+        assert (C < 1.0).mean() > 0.5
+
+
+# ---------------------------------------------------------------- rectified closed form
+def _rectified_closed_form(cams, Y, U, V, seg, S, bit_depth, z_near, z_far, L):
+    """Nearest-sampling cost on a rectified rig (R = I, centres on the x axis,
+    shared K): pixel x of view c lands at x - f (b_c' - b_c) rho_l, same row."""
+    n = len(cams)
+    f = cams[0].K[0, 0]
+    b = [c.center[0] for c in cams]
+    rho = 1 / z_far + np.arange(L) / max(L - 1, 1) * (1 / z_near - 1 / z_far)
+    norm = 3.0 * ((1 << bit_depth) - 1)
+    rows = []
+    for c in range(n):
+        h, w = seg[c].shape
+        ys, xs = np.mgrid[0:h, 0:w]
+        best = np.full((S[c], L), np.inf)
+        for c2 in range(n):
+            if c2 == c:
+                continue
+            for l in range(L):
+                u = xs - f * (b[c2] - b[c]) * rho[l]
+                xi = np.floor(u + 0.5).astype(np.int64)
+                ok = (xi >= 0) & (xi < w)
+                xc = np.clip(xi, 0, w - 1)
+                d = (np.abs(Y[c].astype(float) - Y[c2][ys, xc]) + np.abs(U[c].astype(float) - U[c2][ys, xc])
+                     + np.abs(V[c].astype(float) - V[c2][ys, xc]))
+                s = np.bincount(seg[c][ok], weights=d[ok], minlength=S[c])
+                k = np.bincount(seg[c][ok], minlength=S[c])
+                m = np.where(k > 0, s / np.maximum(k, 1) / norm, np.inf)
+                best[:, l] = np.minimum(best[:, l], m)
+        rows.append(np.where(np.isfinite(best), best, 1.0))
+    return np.concatenate(rows)
+
+
+def test_rectified_closed_form_cfg0():
+    wl = synth.make_cfg0()
+    pb = oracle.Problem.from_workload(wl)
+    C = oracle.cost_volume(pb)
+    R = _rectified_closed_form(wl.cams, wl.Y, wl.U, wl.V, wl.seg, wl.S, 8, wl.z_near, wl.z_far, 64)
+    np.testing.assert_allclose(C, R, rtol=0, atol=1e-12)
+
+
+def test_rectified_closed_form_uneven_baselines():
+    rng = np.random.default_rng(7)
+    xs_c = [-0.0713, 0.0, 0.0291, 0.1137]   # no disparity lands on a half pixel
+    cams = [P.cam(P.synth.intrinsics(251.3, 64, 40), np.eye(3), [-x, 0, 0], 64, 40) for x in xs_c]
+    Y, U, V = P.random_images(rng, cams, 8, 0)
+    seg, S = zip(*[P.random_segments(rng, 64, 40, 30) for _ in cams])
+    pb = oracle.Problem(cams, Y, U, V, seg, S, 8, 0, 0.8, 6.0, 20, False)
+    C = oracle.cost_volume(pb)
+    R = _rectified_closed_form(cams, Y, U, V, list(seg), list(S), 8, 0.8, 6.0, 20)
+    np.testing.assert_allclose(C, R, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- zero-cost plane
+@pytest.mark.parametrize("lstar", [0, 21, 42, 63])
+def test_zero_cost_fronto_plane_cfg0_rig(lstar):
+    """cfg0 rig: adjacent-view disparity at label l is 15 rho_l = 3 + 4 l / 21 px,
+    an integer for l in {0, 21, 42, 63}.  A plane at that depth rendered by
+    exact integer shifts must cost exactly 0 at l* for every segment that sees
+    a target, and labels that move the match by a pixel or more cost > 0."""
+    rng = np.random.default_rng(100 + lstar)
+    cams = synth.rectified_rig(3, 0.05, 300.0, 320, 240)
+    disp = 3 + 4 * lstar // 21
+    Y, U, V = P.fronto_plane_views(rng, cams, 300.0, 0.05, [-disp, 0, disp])
+    seg, S = zip(*[P.random_segments(rng, 320, 240, 1200) for _ in cams])
+    pb = oracle.Problem(cams, Y, U, V, seg, S, 8, 0, 1.0, 5.0, 64, False)
+    C, m, nv = oracle.cost_volume(pb, with_terms=True)
+    seen = nv[:, :, lstar].sum(1) > 0          # segments with a valid pixel at l*
+    assert seen.mean() > 0.97                 # only strips at the outer edges see nothing
+    assert np.all(C[seen, lstar] == 0.0)
+    assert np.all(C[~seen, lstar] == 1.0)      # the no-valid-target sentinel
+    # labels within 2 of l* shift adjacent views by less than half a pixel
+    # more, so nearest sampling reads the same pixels there: exact ties
+    near = np.abs(np.arange(64) - lstar) <= 2
+    assert np.all(np.abs(oracle.argmin(C[seen]) - lstar) <= 2)
+    assert (C[seen][:, ~near] > 0).mean() > 0.999
+
+
+def _smooth(s1, s2, base, amp, waves):
+    out = np.full(s1.shape, base, np.float64)
+    for (k1, k2, ph) in waves:
+        out += amp * np.sin(k1 * s1 + k2 * s2 + ph)
+    return out
+
+
+def test_smooth_plane_on_arc_rig_true_label_wins():
+    """Converging arc rig (cfg1 geometry, reduced size): a plane parallel to
+    the reference plane at z_l* carries a smooth analytic texture, ray-cast in
+    FP64.  With bilinear sampling the true label must be the argmin of at
+    least 99.9% of segments and its cost must stay within the bound from
+    quantisation (1/2 + 1/2 code value) plus bilinear error
+    (h^2/8 |f''| per axis, h = 1 px) on each channel."""
+    W, H, n, L = 240, 136, 8, 32
+    f = 1400.0 * W / 1920
+    cams = synth.arc_rig(n, 3.0, 30.0, f, W, H)
+    Cr, nr = synth.rig_reference(cams)
+    z_near, z_far = 1.5, 10.0
+    lstar = 13
+    rho = 1 / z_far + lstar / (L - 1) * (1 / z_near - 1 / z_far)
+    zs = 1 / rho
+    a1 = np.cross([0.0, 1.0, 0.0], nr); a1 /= np.linalg.norm(a1)
+    a2 = np.cross(nr, a1)
+    # wavelengths of about 60 px at this depth
+    px_m = zs / f
+    rng = np.random.default_rng(5)
+    amp = 120.0
+    waves = {ch: [(*(2 * math.pi / (rng.uniform(55, 90) * px_m) * np.array([math.cos(t), math.sin(t)])), rng.uniform(0, 6.28))
+                  for t in rng.uniform(0, math.pi, 3)] for ch in range(3)}
+    kmax = {ch: sum(math.hypot(a, b) for a, b, _ in waves[ch]) * px_m for ch in range(3)}
+    Y, U, V = [], [], []
+    for c in cams:
+        ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+        Kinv = np.linalg.inv(c.K)
+        dcam = np.stack([Kinv[0, 0] * xs + Kinv[0, 1] * ys + Kinv[0, 2], Kinv[1, 1] * ys + Kinv[1, 2], np.ones_like(xs)], -1)
+        d = dcam @ c.R
+        tt = (zs - (c.center - Cr) @ nr) / (d @ nr)
+        X = c.center + tt[..., None] * d
+        s1 = (X - Cr) @ a1
+        s2 = (X - Cr) @ a2
+        imgs = [np.rint(_smooth(s1, s2, 512.0, amp, waves[ch])).astype(np.uint16) for ch in range(3)]
+        Y.append(imgs[0]); U.append(imgs[1]); V.append(imgs[2])
+    seg, S = zip(*[P.random_segments(rng, W, H, 300) for _ in cams])
+    pb = oracle.Problem(cams, Y, U, V, seg, S, 10, 0, z_near, z_far, L, True)
+    C, m, nv = oracle.cost_volume(pb, with_terms=True)
+    seen = nv[:, :, lstar].sum(1) > 0
+    assert seen.mean() > 0.95
+    assert np.all(C[~seen, lstar] == 1.0)
+    # per-channel worst-case error in code values: both roundings plus the
+    # bilinear error of the target sample (3 waves, |f''| <= amp * k^2 per wave)
+    interp = sum(2 * amp * kmax[ch] ** 2 / 8 for ch in range(3))
+    bound = (3 * 1.0 + interp) / (3 * 1023)
+    assert C[seen, lstar].max() <= bound, (C[seen, lstar].max(), bound)
+    assert (oracle.argmin(C[seen]) == lstar).mean() >= 0.999
+
+
+# ---------------------------------------------------------------- invariants
+def _transform_rig(cams, G, g):
+    """World change X_new = G X + g applied to every camera."""
+    out = []
+    for c in cams:
+        Rn = c.R @ G.T
+        out.append(P.cam(c.K, Rn, c.t - Rn @ g, c.width, c.height))
+    return out
+
+
+def test_invariant_rigid_motion():
+    ns = P.tiny_problem(11, n_views=4, width=20, height=14, n_seg=10, L=7, bilinear=True, rotated=True, bit_depth=10)
+    C0 = oracle.cost_volume(_pb(ns))
+    G = P.rotation([0.3, -1.0, 0.4], 37.0)
+    ns.cams = _transform_rig(ns.cams, G, np.array([1.5, -0.2, 7.0]))
+    C1 = oracle.cost_volume(_pb(ns))
+    np.testing.assert_allclose(C1, C0, rtol=0, atol=1e-12)
+
+
+def test_invariant_view_permutation():
+    ns = P.tiny_problem(12, n_views=4, width=20, height=14, n_seg=10, L=6, bilinear=True, rotated=True)
+    pb = _pb(ns)
+    C = oracle.cost_volume(pb)
+    perm = [2, 0, 3, 1]
+    Cp = oracle.cost_volume(oracle.Problem([ns.cams[i] for i in perm], [ns.Y[i] for i in perm],
+                                           [ns.U[i] for i in perm], [ns.V[i] for i in perm],
+                                           [ns.seg[i] for i in perm], [ns.S[i] for i in perm],
+                                           ns.bit_depth, 0, ns.z_near, ns.z_far, ns.num_labels, True))
+    off = pb.row_offsets()
+    expect = np.concatenate([C[off[i]:off[i + 1]] for i in perm])
+    np.testing.assert_allclose(Cp, expect, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bilinear", [False, True])
+def test_invariant_420_equals_replicated_444(bilinear):
+    ns = P.tiny_problem(13, n_views=3, width=21, height=15, n_seg=9, L=6, chroma_shift=1,
+                        bilinear=bilinear, rotated=True, bit_depth=10)
+    C420 = oracle.cost_volume(_pb(ns))
+    up = lambda a, h, w: np.repeat(np.repeat(a, 2, 0), 2, 1)[:h, :w]
+    ns.U = [up(u, y.shape[0], y.shape[1]) for u, y in zip(ns.U, ns.Y)]
+    ns.V = [up(v, y.shape[0], y.shape[1]) for v, y in zip(ns.V, ns.Y)]
+    ns.chroma_shift = 0
+    C444 = oracle.cost_volume(_pb(ns))
+    assert np.array_equal(C420, C444)
+
+
+def test_invariant_one_pixel_segments_and_splits():
+    ns = P.tiny_problem(14, n_views=3, width=10, height=6, n_seg=4, L=5, bilinear=True, rotated=True)
+    pb = _pb(ns)
+    C, m, nv = oracle.cost_volume(pb, with_terms=True)
+    # one-pixel segments: per-pixel plane sweep
+    ns1 = P.tiny_problem(14, n_views=3, width=10, height=6, n_seg=4, L=5, bilinear=True, rotated=True)
+    ns1.seg = [np.arange(60, dtype=np.int32).reshape(6, 10) for _ in range(3)]
+    ns1.S = [60, 60, 60]
+    C1, m1, nv1 = oracle.cost_volume(_pb(ns1), with_terms=True)
+    # a segment's per-target mean is the valid-count-weighted mean of its pixels
+    for c in range(3):
+        off, off1 = pb.row_offsets()[c], 60 * c
+        for s in range(ns.S[c]):
+            pix = np.nonzero(ns.seg[c].ravel() == s)[0]
+            for c2 in range(3):
+                if c2 == c:
+                    continue
+                k = nv1[off1 + pix, c2, :]
+                tot = np.where(k > 0, np.nan_to_num(m1[off1 + pix, c2, :]) * k, 0).sum(0)
+                cnt = k.sum(0)
+                np.testing.assert_array_equal(cnt, nv[off + s, c2])
+                want = np.where(cnt > 0, tot / np.maximum(cnt, 1), np.nan)
+                np.testing.assert_allclose(m[off + s, c2], want, rtol=1e-12, atol=1e-14)
+
+
+def test_invariant_constant_images_cost_zero():
+    ns = P.tiny_problem(15, n_views=3, width=16, height=10, n_seg=8, L=6, bilinear=True, rotated=True, chroma_shift=1)
+    ns.Y = [np.full_like(y, 77) for y in ns.Y]
+    ns.U = [np.full_like(u, 130) for u in ns.U]
+    ns.V = [np.full_like(v, 3) for v in ns.V]
+    C, m, nv = oracle.cost_volume(_pb(ns), with_terms=True)
+    valid = nv.sum(1) > 0
+    assert np.all(C[valid] <= 1e-15)        # bilinear weights sum to 1 up to rounding
+    assert np.all(C[~valid] == 1.0)
+
+
+def test_invariant_bounds_and_min_over_views():
+    ns = P.tiny_problem(16, n_views=4, width=18, height=12, n_seg=9, L=8, bilinear=True, rotated=True)
+    C, m, nv = oracle.cost_volume(_pb(ns), with_terms=True)
+    assert np.all((C >= 0) & (C <= 1))
+    for c2 in range(4):
+        ok = nv[:, c2, :] > 0
+        assert np.all(C[ok] <= m[:, c2, :][ok])
+    some = (nv > 0).any(1)
+    np.testing.assert_array_equal(C[some], np.nanmin(np.where(nv > 0, m, np.nan), axis=1)[some])
+
+
+def test_invariant_own_equals_rig_centre_on_rectified_rig():
+    wl = synth.make_cfg0()
+    a = oracle.cost_volume(oracle.Problem.from_workload(wl, depth_ref=oracle.REF_RIG_CENTER))
+    b = oracle.cost_volume(oracle.Problem.from_workload(wl, depth_ref=oracle.REF_OWN))
+    c = oracle.cost_volume(oracle.Problem.from_workload(wl, depth_ref=0))
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_invariant_swapped_range_reverses_labels():
+    ns = P.tiny_problem(17, n_views=3, width=16, height=10, n_seg=8, L=9, bilinear=True, rotated=True)
+    C = oracle.cost_volume(_pb(ns))
+    ns.z_near, ns.z_far = ns.z_far, ns.z_near
+    Cs = oracle.cost_volume(_pb(ns))
+    np.testing.assert_allclose(Cs, C[:, ::-1], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- precision facts
+def test_fp16_storage_bound():
+    """Round-to-nearest FP16 of C in [0, 1] is within 2^-12 of C."""
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.uniform(0, 1, 200000), np.linspace(0, 1, 100001)])
+    err = np.abs(x.astype(np.float16).astype(np.float64) - x)
+    assert err.max() <= 2.0 ** -12
+    wl = synth.make_cfg0()
+    C = oracle.cost_volume(oracle.Problem.from_workload(wl))
+    assert np.abs(C.astype(np.float16).astype(np.float64) - C).max() <= 2.0 ** -12
+
+
+def test_nearest_sums_are_integers():
+    """Nearest sampling: mean * 3 (2^b - 1) * n_valid is an integer sum."""
+    wl = synth.make_cfg0()
+    C, m, nv = oracle.cost_volume(oracle.Problem.from_workload(wl), with_terms=True)
+    ok = nv > 0
+    tot = m[ok] * nv[ok] * 765.0
+    assert np.abs(tot - np.rint(tot)).max() < 1e-9
+
+
+def test_label_grid_matches_cfg0_disparities():
+    """15 rho_l = 3 + 4 l / 21 on cfg0 (f = 300 px, baseline 0.05 m, [1, 5] m)."""
+    L = 64
+    rho = 1 / 5.0 + np.arange(L) / (L - 1) * (1 / 1.0 - 1 / 5.0)
+    np.testing.assert_allclose(300 * 0.05 * rho, 3 + 4 * np.arange(L) / 21, rtol=0, atol=1e-12)
