@@ -1,0 +1,290 @@
+/*
+ * ivde.h -- C ABI of libivde, the MI355X (gfx950) per-segment plane-sweep
+ * matching-cost library.
+ *
+ * The method is the segment-based multiview depth estimator of Mieloch,
+ * Stankiewicz and Domanski, "Depth Map Estimation for Free-Viewpoint
+ * Television".  Its problem statement (Sec. I and Sec. III-A) takes
+ * any number of arbitrarily positioned views with intrinsic and extrinsic
+ * camera parameters, a segmentation of every view made independently per
+ * view, a range of depth levels, and (for video) the segments that changed
+ * since the previous frame (Sec. III-E).  This library computes the data
+ * term that the paper's graph-cut optimisation consumes: for every segment s
+ * of every view c and every depth level l, the mean YCbCr L1 distance
+ * (Sec. III-C, Eq. (4)) between the segment's pixels and their
+ * reprojections into the other views, minimum over the target views:
+ *
+ *     C[c][s][l] = min_{c' in D_c, n > 0}  (1 / n) sum_{p in s valid} e(p, c', l)
+ *     e = (|dY| + |dCb| + |dCr|) / (3 (2^b - 1))        in [0, 1]
+ *
+ * Eq. (4) averages over a small window at the segment centre (Sec. III-C,
+ * 3x3 in Sec. V-A); this library averages over every pixel of the segment,
+ * each reprojected at its own position.  The graph cut itself (Sec. III-B,
+ * IV-B) stays with the caller.
+ *
+ * Geometry conventions (fixed here because the paper only says the
+ * transform comes from intrinsic and extrinsic parameters, Sec. III-C):
+ *   - a camera maps a world point X to camera coordinates R X + t; K is
+ *     3x3 with third row (0, 0, 1); all three are row-major FP64;
+ *   - pixel centres are at integer (x, y), x to the right, y down;
+ *   - depth levels are planes parallel to a reference camera plane
+ *     (Sec. IV-A) at distances z_l, uniform in 1/z from z_far (label 0) to
+ *     z_near (label L-1); the reference plane is the rig centre's (Sec.
+ *     III-B: depth from the centre camera's plane): mean camera centre,
+ *     normalised mean optical axis.  IVDE_REF_OWN uses each view's own plane
+ *     and a camera index uses that camera's plane;
+ *   - a pixel is valid for a (target, label) if its 3-D point lies in front
+ *     of both cameras and its projection samples inside the target image:
+ *     nearest: round-half-up of (u, v) inside [0, W) x [0, H); bilinear:
+ *     (u, v) within 1/64 px of [0, W-1] x [0, H-1], clamped onto it.  Chroma
+ *     is sampled with the luma weights at taps (x >> k, y >> k), k the
+ *     chroma shift;
+ *   - a segment with no valid pixel in any target gets the cost 1.0.
+ *
+ * Memory and threading conventions:
+ *   - every image, segment map, cost volume, label output, workspace and
+ *     arena pointer is DEVICE memory owned by the caller; cameras, options
+ *     and target masks are host memory read during the call only;
+ *   - calls are asynchronous on the given stream (a hipStream_t passed as
+ *     ivde_stream; NULL is the null stream).  Argument errors are found
+ *     synchronously, before anything is enqueued, and set a thread-local
+ *     message for ivde_last_error().  Segment ids out of range are found on
+ *     the device: the offending pixels are skipped and ivde_workspace_status
+ *     reports IVDE_EINVAL after the stream has completed;
+ *   - no C++ exception crosses this interface;
+ *   - ivde_cost_volume and ivde_argmin are re-entrant as long as concurrent
+ *     calls use distinct workspaces; every ivde_server call is thread-safe.
+ */
+#ifndef IVDE_H
+#define IVDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ivde_status;
+#define IVDE_OK 0
+#define IVDE_EINVAL (-1)      /* invalid argument or segment id out of range */
+#define IVDE_ENOMEM (-2)      /* host allocation failed or workspace too small */
+#define IVDE_EBUDGET (-3)     /* request does not fit the server's HBM budget */
+#define IVDE_EHIP (-4)        /* a HIP runtime call failed */
+#define IVDE_EBUSY (-5)       /* result not ready yet */
+#define IVDE_ENOTFOUND (-6)   /* unknown rig or ticket */
+
+typedef void *ivde_stream;    /* hipStream_t */
+
+#define IVDE_REF_RIG_CENTER (-1)
+#define IVDE_REF_OWN (-2)
+
+#define IVDE_NEAREST 0
+#define IVDE_BILINEAR 1
+
+#define IVDE_F32 0
+#define IVDE_F16 1
+
+#define IVDE_TARGETS_ALL 0          /* every other view */
+#define IVDE_TARGETS_NEAREST_LR 1   /* views c-1 and c+1 (Sec. III-B's D) */
+#define IVDE_TARGETS_EXPLICIT 2     /* target_mask[c * n + c'] != 0 */
+
+/* One view's camera: intrinsics K and extrinsics (R, t), row-major FP64,
+ * host memory (Sec. III-C: the 3-D transform T[.] is built from them). */
+typedef struct {
+    double K[9];
+    double R[9];
+    double t[3];
+    int32_t width, height;
+} ivde_camera;
+
+/* One view's picture as Y, Cb, Cr planes (Sec. III-C uses YCbCr).
+ * plane[i] are device pointers to uint8 (bit_depth 8) or uint16 (9..16)
+ * samples; pitch[i] is the row pitch in samples.  chroma_shift 0 is 4:4:4,
+ * 1 is 4:2:0 with ceil(W/2) x ceil(H/2) chroma planes. */
+typedef struct {
+    const void *plane[3];
+    int64_t pitch[3];
+    int32_t bit_depth;
+    int32_t chroma_shift;
+} ivde_image;
+
+/* One view's segmentation (Sec. III-A: segmented independently per view):
+ * device int32 ids in [0, num_segments), row pitch in elements. */
+typedef struct {
+    const int32_t *seg_map;
+    int64_t pitch;
+    int32_t num_segments;
+} ivde_segmentation;
+
+/* Depth levels (Sec. IV-A: planes parallel to the reference camera plane;
+ * Sec. V-A uses 250).  Uniform in inverse depth, label 0 at z_far. */
+typedef struct {
+    double z_near, z_far;
+    int32_t num_labels;
+    int32_t depth_ref;        /* IVDE_REF_RIG_CENTER, IVDE_REF_OWN or a view index */
+} ivde_label_range;
+
+/* Options.  labels_per_lane (1, 2, 4 or 8) and waves_per_group (1, 2 or 4)
+ * are launch-shape knobs; 0 picks the tuned default.  They never change a
+ * result. */
+typedef struct {
+    int32_t sampling;         /* IVDE_NEAREST or IVDE_BILINEAR */
+    int32_t cost_dtype;       /* IVDE_F32 or IVDE_F16 storage */
+    int32_t targets;          /* IVDE_TARGETS_* */
+    const uint8_t *target_mask;   /* host n x n, for IVDE_TARGETS_EXPLICIT */
+    int32_t labels_per_lane;
+    int32_t waves_per_group;
+} ivde_options;
+
+/* ---------------------------------------------------------------- plain form */
+
+/* Sizes of the cost volume and of the workspace ivde_cost_volume needs for
+ * images of `bit_depth` bits.  The cost volume is [sum_c S_c][L] of float
+ * or half, rows in view order then segment order, labels contiguous.
+ * Either output pointer may be NULL.  Only sizes are read from cams and
+ * segs (their device pointers are not touched). */
+ivde_status ivde_cost_volume_size(int32_t n_views, const ivde_camera *cams,
+                                  const ivde_segmentation *segs,
+                                  const ivde_label_range *labels,
+                                  const ivde_options *opt, int32_t bit_depth,
+                                  size_t *cost_bytes, size_t *workspace_bytes);
+
+/* The cost volume C[view][segment][label] (Sec. III-C Eq. (4) over every
+ * pixel of the segment, minimum over the target views).
+ *   n_views     >= 1 views (a single view has no target: every row is 1.0)
+ *   cams        host array of n_views cameras
+ *   views       host array of n_views device images; all views share
+ *               bit_depth and chroma_shift
+ *   segs        host array of n_views device segment maps (W x H each)
+ *   labels, opt host structs
+ *   workspace   device buffer of at least the size ivde_cost_volume_size
+ *               returns (256-byte aligned); it holds the packed images, the
+ *               segment index and the task list until the stream completes
+ *   cost_out    device buffer of cost_bytes
+ * Returns IVDE_OK once every kernel is enqueued on `stream`. */
+ivde_status ivde_cost_volume(int32_t n_views, const ivde_camera *cams,
+                             const ivde_image *views, const ivde_segmentation *segs,
+                             const ivde_label_range *labels, const ivde_options *opt,
+                             void *workspace, size_t workspace_bytes,
+                             void *cost_out, ivde_stream stream);
+
+/* Winner-take-all labels: label_out[r] = the lowest l with
+ * cost[r][l] == min_l cost[r][l] (NaN never wins).  cost is device
+ * [rows][num_labels] of cost_dtype; label_out is device int32 [rows]. */
+ivde_status ivde_argmin(int64_t rows, int32_t num_labels, int32_t cost_dtype,
+                        const void *cost, int32_t *label_out, ivde_stream stream);
+
+/* After the stream that ran ivde_cost_volume with this workspace has
+ * completed: IVDE_EINVAL if a segment id was out of range, else IVDE_OK.
+ * Synchronises `stream`. */
+ivde_status ivde_workspace_status(const void *workspace, ivde_stream stream);
+
+/* ---------------------------------------------------------------- batched form */
+
+/* One frame of a batch: the same fields as one ivde_cost_volume call. */
+typedef struct {
+    int32_t n_views;
+    const ivde_camera *cams;
+    const ivde_image *views;
+    const ivde_segmentation *segs;
+    ivde_label_range labels;
+    void *cost_out;           /* device, ivde_cost_volume_size's cost_bytes */
+} ivde_frame;
+
+typedef struct ivde_batch ivde_batch;
+
+/* Plans a batch of frames with uneven view, segment and label counts: one
+ * persistent sweep kernel pulls (frame, view, segment, label-block) tasks,
+ * sorted by cost, from a shared queue.  The plan records every device
+ * pointer of `frames` and the workspace: they must stay valid while the
+ * plan is used.  Frames must share sampling and cost dtype (opt). */
+ivde_status ivde_batch_size(int32_t n_frames, const ivde_frame *frames, const ivde_options *opt,
+                            size_t *workspace_bytes);
+ivde_status ivde_batch_create(int32_t n_frames, const ivde_frame *frames, const ivde_options *opt,
+                              void *workspace, size_t workspace_bytes, ivde_batch **out);
+/* Runs the whole batch (image packing, segment index, task queue, one
+ * persistent sweep) on `stream`.  use_graph != 0 replays a hipGraph
+ * captured on first use. */
+ivde_status ivde_batch_run(ivde_batch *b, ivde_stream stream, int32_t use_graph);
+void ivde_batch_destroy(ivde_batch *b);
+
+/* ---------------------------------------------------------------- serving form */
+
+typedef struct ivde_server ivde_server;
+
+typedef struct {
+    void *arena;              /* device memory; its size is the HBM budget */
+    size_t arena_bytes;
+    int32_t max_slots;        /* requests in flight on the device at once (1..16) */
+} ivde_server_config;
+
+typedef struct {
+    uint64_t ticket;
+    int32_t rig_id;
+    int32_t status;           /* IVDE_OK or the failure */
+    int64_t rows_recomputed;  /* changed segments swept */
+    int64_t rows_total;
+    double submit_us;         /* host steady-clock times, microseconds */
+    double start_us;          /* admitted and enqueued */
+    double done_us;           /* device work observed complete */
+} ivde_frame_stats;
+
+/* A serving loop (Sec. III-E temporal scheme as a service): rigs are
+ * registered once, each keeps its previous frame's cost volume resident in
+ * the arena, and every submitted frame recomputes only the segments its
+ * changed mask marks, carrying the other rows over.  Requests are admitted
+ * while a slot and arena memory are free, and run concurrently on separate
+ * streams; frames of one rig run in submission order. */
+ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out);
+
+/* Registers a rig: its cameras, fixed segmentation (device maps, read
+ * during this call only), label range and options.  Reserves the rig's
+ * resident state in the arena; IVDE_EBUDGET if it does not fit. */
+ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_camera *cams,
+                              const ivde_segmentation *segs, const ivde_label_range *labels,
+                              const ivde_options *opt, int32_t *rig_id);
+
+/* Submits one frame of a rig.
+ *   views         host array of n_views device images, valid until done
+ *   changed_mask  device uint8 [sum_c S_c] (non-zero = recompute the row)
+ *                 or NULL: recompute every row (an I frame, Sec. III-E)
+ *   cost_out      device, optional: receives a copy of the frame's cost
+ *   label_out     device int32 [sum_c S_c], optional: argmin labels
+ * IVDE_EBUDGET if the request can never fit the arena. */
+ivde_status ivde_stream_submit(ivde_server *srv, int32_t rig_id, const ivde_image *views,
+                               const uint8_t *changed_mask, void *cost_out, int32_t *label_out,
+                               uint64_t *ticket);
+/* IVDE_EBUSY while pending; otherwise fills `st` and forgets the ticket. */
+ivde_status ivde_stream_poll(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st);
+ivde_status ivde_stream_wait(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st);
+/* Device pointer of a rig's resident cost volume (valid until destroy). */
+ivde_status ivde_rig_resident(ivde_server *srv, int32_t rig_id, const void **cost, int64_t *rows);
+/* Drops a rig's resident volume: its next frame is computed in full. */
+ivde_status ivde_rig_reset(ivde_server *srv, int32_t rig_id);
+void ivde_server_destroy(ivde_server *srv);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Times every (labels_per_lane, waves_per_group) launch shape on the given
+ * problem (which must already be valid for ivde_cost_volume) and writes the
+ * fastest into *opt_out.  Each candidate runs `reps` times; times in
+ * microseconds go to times_us[i] for candidate i if not NULL (capacity
+ * max_times).  Synchronises `stream`. */
+ivde_status ivde_autotune(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                          const ivde_segmentation *segs, const ivde_label_range *labels,
+                          const ivde_options *opt, void *workspace, size_t workspace_bytes,
+                          void *cost_out, ivde_stream stream, int32_t reps,
+                          ivde_options *opt_out, float *times_us, int32_t max_times);
+
+/* ---------------------------------------------------------------- misc */
+
+const char *ivde_status_string(ivde_status s);
+const char *ivde_last_error(void);     /* thread-local, "" if none */
+const char *ivde_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IVDE_H */

@@ -1,0 +1,561 @@
+// libivde host side: argument validation, FP64 camera composition, workspace
+// layout and the plain cost-volume / argmin entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ivde.h"
+#include "host_common.h"
+#include "ivde_internal.h"
+
+namespace ivde {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+ivde_status hip_fail(hipError_t e, const char *what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return IVDE_EHIP;
+}
+
+// ---------------------------------------------------------------- FP64 helpers
+static bool inv3(const double *a, double *o)
+{
+    const double c00 = a[4] * a[8] - a[5] * a[7];
+    const double c01 = a[5] * a[6] - a[3] * a[8];
+    const double c02 = a[3] * a[7] - a[4] * a[6];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+    const double r = 1.0 / det;
+    o[0] = c00 * r;
+    o[1] = (a[2] * a[7] - a[1] * a[8]) * r;
+    o[2] = (a[1] * a[5] - a[2] * a[4]) * r;
+    o[3] = c01 * r;
+    o[4] = (a[0] * a[8] - a[2] * a[6]) * r;
+    o[5] = (a[2] * a[3] - a[0] * a[5]) * r;
+    o[6] = c02 * r;
+    o[7] = (a[1] * a[6] - a[0] * a[7]) * r;
+    o[8] = (a[0] * a[4] - a[1] * a[3]) * r;
+    return true;
+}
+
+static void mul3(const double *a, const double *b, double *o)   // o = a b
+{
+    double t[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) t[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+    memcpy(o, t, sizeof(t));
+}
+
+static void transpose3(const double *a, double *o)
+{
+    double t[9] = {a[0], a[3], a[6], a[1], a[4], a[7], a[2], a[5], a[8]};
+    memcpy(o, t, sizeof(t));
+}
+
+static void mv3(const double *a, const double *v, double *o)
+{
+    double t[3];
+    for (int i = 0; i < 3; ++i) t[i] = a[3 * i] * v[0] + a[3 * i + 1] * v[1] + a[3 * i + 2] * v[2];
+    memcpy(o, t, sizeof(t));
+}
+
+// ---------------------------------------------------------------- validation
+ivde_status validate_problem(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                             const ivde_segmentation *segs, const ivde_label_range *labels,
+                             const ivde_options *opt, bool need_images)
+{
+    if (n < 1 || n > kMaxViews) {
+        set_error("n_views must be in [1, %d], got %d", kMaxViews, n);
+        return IVDE_EINVAL;
+    }
+    if (!cams || !segs || !labels || !opt || (need_images && !views)) {
+        set_error("null argument");
+        return IVDE_EINVAL;
+    }
+    for (int v = 0; v < n; ++v) {
+        const ivde_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384) {
+            set_error("view %d: image size %dx%d outside [1, 16384]", v, c.width, c.height);
+            return IVDE_EINVAL;
+        }
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(c.K[i]) || !std::isfinite(c.R[i])) {
+                set_error("view %d: non-finite camera matrix", v);
+                return IVDE_EINVAL;
+            }
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(c.t[i])) {
+                set_error("view %d: non-finite translation", v);
+                return IVDE_EINVAL;
+            }
+        if (c.K[6] != 0.0 || c.K[7] != 0.0 || c.K[8] != 1.0) {
+            set_error("view %d: K must have third row (0, 0, 1)", v);
+            return IVDE_EINVAL;
+        }
+        double ki[9];
+        if (!inv3(c.K, ki)) {
+            set_error("view %d: singular K", v);
+            return IVDE_EINVAL;
+        }
+        const ivde_segmentation &s = segs[v];
+        if (!s.seg_map || s.num_segments < 1 || s.pitch < c.width) {
+            set_error("view %d: segmentation needs a map, num_segments >= 1 and pitch >= width", v);
+            return IVDE_EINVAL;
+        }
+        if ((int64_t)c.width * c.height > (int64_t)1 << 28) {
+            set_error("view %d: too many pixels", v);
+            return IVDE_EINVAL;
+        }
+    }
+    if (need_images) {
+        const int b = views[0].bit_depth, k = views[0].chroma_shift;
+        if (b < 8 || b > 16 || k < 0 || k > 1) {
+            set_error("bit_depth must be 8..16 and chroma_shift 0 or 1");
+            return IVDE_EINVAL;
+        }
+        for (int v = 0; v < n; ++v) {
+            const ivde_image &im = views[v];
+            if (im.bit_depth != b || im.chroma_shift != k) {
+                set_error("view %d: all views must share bit_depth and chroma_shift", v);
+                return IVDE_EINVAL;
+            }
+            const int64_t cw = (cams[v].width + k) >> k;
+            for (int p = 0; p < 3; ++p)
+                if (!im.plane[p] || im.pitch[p] < (p ? cw : cams[v].width)) {
+                    set_error("view %d: plane %d is null or its pitch is too small", v, p);
+                    return IVDE_EINVAL;
+                }
+        }
+    }
+    const ivde_label_range &lr = *labels;
+    if (!(lr.z_near > 0.0) || !(lr.z_far > 0.0) || !std::isfinite(lr.z_near) || !std::isfinite(lr.z_far)) {
+        set_error("z_near and z_far must be finite and positive");
+        return IVDE_EINVAL;
+    }
+    if (lr.num_labels < 1 || lr.num_labels > 8192) {
+        set_error("num_labels must be in [1, 8192]");
+        return IVDE_EINVAL;
+    }
+    if (lr.depth_ref < IVDE_REF_OWN || lr.depth_ref >= n) {
+        set_error("depth_ref must be IVDE_REF_RIG_CENTER, IVDE_REF_OWN or a view index");
+        return IVDE_EINVAL;
+    }
+    if (opt->sampling != IVDE_NEAREST && opt->sampling != IVDE_BILINEAR) {
+        set_error("unknown sampling %d", opt->sampling);
+        return IVDE_EINVAL;
+    }
+    if (opt->cost_dtype != IVDE_F32 && opt->cost_dtype != IVDE_F16) {
+        set_error("unknown cost dtype %d", opt->cost_dtype);
+        return IVDE_EINVAL;
+    }
+    if (opt->targets < IVDE_TARGETS_ALL || opt->targets > IVDE_TARGETS_EXPLICIT ||
+        (opt->targets == IVDE_TARGETS_EXPLICIT && !opt->target_mask)) {
+        set_error("bad target selection");
+        return IVDE_EINVAL;
+    }
+    const int J = opt->labels_per_lane;
+    if (J != 0 && J != 1 && J != 2 && J != 4 && J != 8) {
+        set_error("labels_per_lane must be 0, 1, 2, 4 or 8");
+        return IVDE_EINVAL;
+    }
+    const int w = opt->waves_per_group;
+    if (w != 0 && w != 1 && w != 2 && w != 4) {
+        set_error("waves_per_group must be 0, 1, 2 or 4");
+        return IVDE_EINVAL;
+    }
+    return IVDE_OK;
+}
+
+int default_labels_per_lane(int L)
+{
+    if (L <= 64) return 1;
+    if (L <= 128) return 2;
+    return 4;
+}
+
+// ---------------------------------------------------------------- layout
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *segs, const ivde_label_range *labels,
+                   const ivde_options *opt, int bit_depth)
+{
+    Layout ly{};
+    ly.n = n;
+    ly.L = labels->num_labels;
+    ly.J = opt->labels_per_lane ? opt->labels_per_lane : default_labels_per_lane(ly.L);
+    ly.wpg = opt->waves_per_group ? opt->waves_per_group : 4;
+    ly.n_lblocks = (ly.L + 64 * ly.J - 1) / (64 * ly.J);
+    ly.tex_f32 = bit_depth > 11;
+    ly.f16 = opt->cost_dtype == IVDE_F16;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    ly.off_problem = take(sizeof(Problem));
+    ly.off_views = take(sizeof(ViewDesc) * n);
+    ly.off_pairs = take(sizeof(PairConst) * n * n);
+    ly.off_sigma = take(sizeof(float) * n * ly.L);
+    ly.off_flag = take(sizeof(int32_t) * 4);
+    ly.total_rows = 0;
+    ly.max_w = ly.max_h = ly.max_s = ly.max_bands = 0;
+    for (int v = 0; v < n; ++v) {
+        const int W = cams[v].width, H = cams[v].height, S = segs[v].num_segments;
+        ViewLayout &vl = ly.views[v];
+        vl.row0 = ly.total_rows;
+        ly.total_rows += S;
+        vl.n_bands = (H + kBand - 1) / kBand;
+        vl.tex_bytes = (int64_t)(W + 1) * (H + 1) * (ly.tex_f32 ? 16 : 8);
+        vl.off_tex = take((size_t)vl.tex_bytes + 16);
+        vl.off_counts = take(sizeof(int32_t) * S);
+        vl.off_offsets = take(sizeof(int32_t) * (S + 1));
+        vl.off_bbox = take(sizeof(int32_t) * 4 * S);
+        vl.off_pixrec = take(sizeof(float) * 8 * (size_t)W * H);
+        vl.off_bands = take(sizeof(int32_t) * 2 * vl.n_bands);
+        ly.max_w = W > ly.max_w ? W : ly.max_w;
+        ly.max_h = H > ly.max_h ? H : ly.max_h;
+        ly.max_s = S > ly.max_s ? S : ly.max_s;
+        ly.max_bands = vl.n_bands > ly.max_bands ? vl.n_bands : ly.max_bands;
+    }
+    ly.n_tasks = ly.total_rows * ly.n_lblocks;
+    ly.off_tasks = take(sizeof(Task) * (size_t)ly.n_tasks);
+    ly.workspace_bytes = off;
+    ly.cost_bytes = (size_t)ly.total_rows * ly.L * (ly.f16 ? 2 : 4);
+    return ly;
+}
+
+// ---------------------------------------------------------------- composition
+// Builds the host image of the device constants: per-view descriptors, the
+// pair projections (h = H p~ + sigma (g . p~) e) and the sigma table, all
+// composed in FP64 and cast to FP32.
+ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views, const ivde_segmentation *segs,
+                    const ivde_label_range *labels, const ivde_options *opt, const Layout &ly, char *ws_base,
+                    void *cost_out, HostConstants &hc)
+{
+    const int L = ly.L;
+    hc.views.assign(n, ViewDesc{});
+    hc.pairs.assign((size_t)n * n, PairConst{});
+    hc.sigma.assign((size_t)n * L, 0.f);
+
+    std::vector<double> Kinv(9 * n), M(9 * n), C(3 * n), axis(3 * n);
+    for (int v = 0; v < n; ++v) {
+        inv3(cams[v].K, &Kinv[9 * v]);
+        double Rt[9];
+        transpose3(cams[v].R, Rt);
+        mul3(Rt, &Kinv[9 * v], &M[9 * v]);            // ray direction d = M p~
+        double c[3];
+        mv3(Rt, cams[v].t, c);
+        for (int i = 0; i < 3; ++i) {
+            C[3 * v + i] = -c[i];
+            axis[3 * v + i] = cams[v].R[6 + i];
+        }
+    }
+    // reference plane(s): normal n_r through C_r
+    std::vector<double> Cr(3 * n), nr(3 * n);
+    for (int v = 0; v < n; ++v) {
+        if (labels->depth_ref == IVDE_REF_RIG_CENTER) {
+            double cm[3] = {0, 0, 0}, am[3] = {0, 0, 0};
+            for (int u = 0; u < n; ++u)
+                for (int i = 0; i < 3; ++i) {
+                    cm[i] += C[3 * u + i] / n;
+                    am[i] += axis[3 * u + i] / n;
+                }
+            const double len = std::sqrt(am[0] * am[0] + am[1] * am[1] + am[2] * am[2]);
+            if (!(len > 0.0)) {
+                set_error("the mean optical axis of the rig vanishes");
+                return IVDE_EINVAL;
+            }
+            for (int i = 0; i < 3; ++i) {
+                Cr[3 * v + i] = cm[i];
+                nr[3 * v + i] = am[i] / len;
+            }
+        } else {
+            const int rv = labels->depth_ref == IVDE_REF_OWN ? v : labels->depth_ref;
+            for (int i = 0; i < 3; ++i) {
+                Cr[3 * v + i] = C[3 * rv + i];
+                nr[3 * v + i] = axis[3 * rv + i];
+            }
+        }
+    }
+    std::vector<double> zl(L);
+    for (int l = 0; l < L; ++l) {
+        const double f = L > 1 ? (double)l / (double)(L - 1) : 0.0;
+        const double rho = 1.0 / labels->z_far + f * (1.0 / labels->z_near - 1.0 / labels->z_far);
+        zl[l] = 1.0 / rho;
+    }
+    // target sets
+    std::vector<uint8_t> T((size_t)n * n, 0);
+    for (int c = 0; c < n; ++c)
+        for (int c2 = 0; c2 < n; ++c2) {
+            if (c2 == c) continue;
+            if (opt->targets == IVDE_TARGETS_ALL) T[c * n + c2] = 1;
+            else if (opt->targets == IVDE_TARGETS_NEAREST_LR) T[c * n + c2] = (c2 == c - 1 || c2 == c + 1);
+            else T[c * n + c2] = opt->target_mask[c * n + c2] != 0;
+        }
+
+    for (int v = 0; v < n; ++v) {
+        ViewDesc &d = hc.views[v];
+        const ViewLayout &vl = ly.views[v];
+        for (int p = 0; p < 3; ++p) {
+            d.plane[p] = views ? views[v].plane[p] : nullptr;
+            d.pitch[p] = views ? views[v].pitch[p] : 0;
+        }
+        d.seg = segs[v].seg_map;
+        d.seg_pitch = segs[v].pitch;
+        d.tex = ws_base + vl.off_tex;
+        d.tex_bytes = vl.tex_bytes;
+        d.W = cams[v].width;
+        d.H = cams[v].height;
+        d.tex_pitch = cams[v].width + 1;
+        d.S = segs[v].num_segments;
+        d.row0 = vl.row0;
+        d.counts = reinterpret_cast<int32_t *>(ws_base + vl.off_counts);
+        d.offsets = reinterpret_cast<int32_t *>(ws_base + vl.off_offsets);
+        d.bbox = reinterpret_cast<int32_t *>(ws_base + vl.off_bbox);
+        d.pixrec = reinterpret_cast<float *>(ws_base + vl.off_pixrec);
+        d.band_count = reinterpret_cast<int32_t *>(ws_base + vl.off_bands);
+        d.n_bands = vl.n_bands;
+        d.n_targets = 0;
+        for (int c2 = 0; c2 < n; ++c2)
+            if (T[v * n + c2]) d.targets[d.n_targets++] = c2;
+        // g_c = M_c^T n_r, so g . p~ = n_r . (M_c p~) = n_r . d
+        const double *Mv = &M[9 * v], *nv = &nr[3 * v];
+        for (int i = 0; i < 3; ++i) d.g[i] = (float)(Mv[i] * nv[0] + Mv[3 + i] * nv[1] + Mv[6 + i] * nv[2]);
+        d.g[3] = 0.f;
+        const double delta = nv[0] * (C[3 * v] - Cr[3 * v]) + nv[1] * (C[3 * v + 1] - Cr[3 * v + 1]) +
+                             nv[2] * (C[3 * v + 2] - Cr[3 * v + 2]);
+        for (int l = 0; l < L; ++l) {
+            const double den = zl[l] - delta;
+            const double sg = den != 0.0 ? 1.0 / den : 0.0;
+            hc.sigma[(size_t)v * L + l] = std::isfinite(sg) ? (float)sg : 0.f;
+        }
+        // pairs: H = K2 R2 M_c, e = K2 (R2 C_c + t2)
+        for (int c2 = 0; c2 < n; ++c2) {
+            if (c2 == v) continue;
+            double KR[9], Hm[9], e[3], t1[3];
+            mul3(cams[c2].K, cams[c2].R, KR);
+            mul3(KR, Mv, Hm);
+            mv3(cams[c2].R, &C[3 * v], t1);
+            for (int i = 0; i < 3; ++i) t1[i] += cams[c2].t[i];
+            mv3(cams[c2].K, t1, e);
+            PairConst &pc = hc.pairs[(size_t)v * n + c2];
+            for (int i = 0; i < 9; ++i) pc.H[i] = (float)Hm[i];
+            for (int i = 0; i < 3; ++i) pc.e[i] = (float)e[i];
+        }
+    }
+    Problem &P = hc.problem;
+    memset(&P, 0, sizeof(P));
+    P.n_views = n;
+    P.L = L;
+    P.J = ly.J;
+    P.n_lblocks = ly.n_lblocks;
+    P.bilinear = opt->sampling == IVDE_BILINEAR;
+    P.f16out = ly.f16;
+    P.bit_depth = views ? views[0].bit_depth : 8;
+    P.chroma_shift = views ? views[0].chroma_shift : 0;
+    P.norm = (float)(3.0 * (double)((1 << P.bit_depth) - 1));
+    P.tex_f32 = ly.tex_f32;
+    P.total_rows = ly.total_rows;
+    P.views = reinterpret_cast<ViewDesc *>(ws_base + ly.off_views);
+    P.pairs = reinterpret_cast<PairConst *>(ws_base + ly.off_pairs);
+    P.sigma = reinterpret_cast<float *>(ws_base + ly.off_sigma);
+    P.cost = cost_out;
+    P.flag = reinterpret_cast<int32_t *>(ws_base + ly.off_flag);
+    return IVDE_OK;
+}
+
+hipError_t upload_constants(const HostConstants &hc, const Layout &ly, char *ws_base, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_upload(ws_base + ly.off_problem, &hc.problem, sizeof(Problem), s)) != hipSuccess) return e;
+    if ((e = launch_upload(ws_base + ly.off_views, hc.views.data(), sizeof(ViewDesc) * hc.views.size(), s)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_upload(ws_base + ly.off_pairs, hc.pairs.data(), sizeof(PairConst) * hc.pairs.size(), s)) !=
+        hipSuccess)
+        return e;
+    return launch_upload(ws_base + ly.off_sigma, hc.sigma.data(), sizeof(float) * hc.sigma.size(), s);
+}
+
+Extents extents_of(const Layout &ly)
+{
+    Extents x;
+    x.n_views = ly.n;
+    x.max_w = ly.max_w;
+    x.max_h = ly.max_h;
+    x.max_s = ly.max_s;
+    x.max_bands = ly.max_bands;
+    return x;
+}
+
+// Everything of one plain cost-volume call except the sweep itself.
+ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                          const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
+                          const Layout &ly, char *ws, void *cost_out, int problem_index, Task *tasks,
+                          hipStream_t s)
+{
+    HostConstants hc;
+    ivde_status st = compose(n, cams, views, segs, labels, opt, ly, ws, cost_out, hc);
+    if (st != IVDE_OK) return st;
+    hipError_t e = upload_constants(hc, ly, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "constant upload");
+    e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "flag reset");
+    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s);
+    if (e != hipSuccess) return hip_fail(e, "segment index");
+    e = launch_worklist(dp, extents_of(ly), problem_index, tasks, s);
+    if (e != hipSuccess) return hip_fail(e, "work list");
+    return IVDE_OK;
+}
+
+ivde_status check_workspace(const void *workspace, size_t have, size_t need)
+{
+    if (!workspace) {
+        set_error("null workspace");
+        return IVDE_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) {
+        set_error("workspace must be 256-byte aligned");
+        return IVDE_EINVAL;
+    }
+    if (have < need) {
+        set_error("workspace too small: %zu bytes given, %zu needed", have, need);
+        return IVDE_ENOMEM;
+    }
+    return IVDE_OK;
+}
+
+ivde_status check_tex_limits(const Layout &ly)
+{
+    for (int v = 0; v < ly.n; ++v)
+        if (ly.views[v].tex_bytes + 16 >= ((int64_t)1 << 31)) {
+            set_error("view %d: packed image exceeds 2 GiB", v);
+            return IVDE_EINVAL;
+        }
+    return IVDE_OK;
+}
+
+}  // namespace ivde
+
+using namespace ivde;
+
+extern "C" {
+
+ivde_status ivde_cost_volume_size(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
+                                  const ivde_label_range *labels, const ivde_options *opt, int32_t bit_depth,
+                                  size_t *cost_bytes, size_t *workspace_bytes)
+{
+    ivde_status st = validate_problem(n_views, cams, nullptr, segs, labels, opt, false);
+    if (st != IVDE_OK) return st;
+    if (bit_depth < 8 || bit_depth > 16) {
+        set_error("bit_depth must be 8..16");
+        return IVDE_EINVAL;
+    }
+    Layout ly = plan_layout(n_views, cams, segs, labels, opt, bit_depth);
+    if (cost_bytes) *cost_bytes = ly.cost_bytes;
+    if (workspace_bytes) *workspace_bytes = ly.workspace_bytes;
+    return IVDE_OK;
+}
+
+ivde_status ivde_cost_volume(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                             const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
+                             void *workspace, size_t workspace_bytes, void *cost_out, ivde_stream stream)
+{
+    ivde_status st = validate_problem(n_views, cams, views, segs, labels, opt, true);
+    if (st != IVDE_OK) return st;
+    if (!cost_out) {
+        set_error("null cost_out");
+        return IVDE_EINVAL;
+    }
+    const Layout ly = plan_layout(n_views, cams, segs, labels, opt, views[0].bit_depth);
+    if ((st = check_workspace(workspace, workspace_bytes, ly.workspace_bytes)) != IVDE_OK) return st;
+    if ((st = check_tex_limits(ly)) != IVDE_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
+    st = enqueue_front(n_views, cams, views, segs, labels, opt, ly, ws, cost_out, 0, tasks, s);
+    if (st != IVDE_OK) return st;
+    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    hipError_t e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, opt->sampling == IVDE_BILINEAR, ly.tex_f32, ly.f16,
+                                ly.wpg, s);
+    if (e != hipSuccess) return hip_fail(e, "sweep");
+    return IVDE_OK;
+}
+
+ivde_status ivde_argmin(int64_t rows, int32_t num_labels, int32_t cost_dtype, const void *cost, int32_t *label_out,
+                        ivde_stream stream)
+{
+    if (rows < 0 || num_labels < 1 || (cost_dtype != IVDE_F32 && cost_dtype != IVDE_F16)) {
+        set_error("argmin: rows >= 0, num_labels >= 1 and a known dtype are required");
+        return IVDE_EINVAL;
+    }
+    if (rows > 0 && (!cost || !label_out)) {
+        set_error("argmin: null pointer");
+        return IVDE_EINVAL;
+    }
+    hipError_t e = launch_argmin(cost, cost_dtype == IVDE_F16, rows, num_labels, label_out,
+                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "argmin");
+    return IVDE_OK;
+}
+
+ivde_status ivde_workspace_status(const void *workspace, ivde_stream stream)
+{
+    if (!workspace) {
+        set_error("null workspace");
+        return IVDE_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    // the problem header sits at the start of the workspace; its flag pointer
+    // locates the device error flag
+    Problem p;
+    e = hipMemcpy(&p, workspace, sizeof(p), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read problem header");
+    int32_t flag = 0;
+    e = hipMemcpy(&flag, p.flag, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read error flag");
+    if (flag) {
+        set_error("a segment id was outside [0, num_segments)");
+        return IVDE_EINVAL;
+    }
+    return IVDE_OK;
+}
+
+const char *ivde_status_string(ivde_status s)
+{
+    switch (s) {
+    case IVDE_OK: return "ok";
+    case IVDE_EINVAL: return "invalid argument";
+    case IVDE_ENOMEM: return "out of memory";
+    case IVDE_EBUDGET: return "over the HBM budget";
+    case IVDE_EHIP: return "HIP runtime error";
+    case IVDE_EBUSY: return "not ready";
+    case IVDE_ENOTFOUND: return "not found";
+    default: return "unknown status";
+    }
+}
+
+const char *ivde_last_error(void) { return ivde::last_error(); }
+
+const char *ivde_version(void) { return "ivde 0.1 gfx950"; }
+
+}  // extern "C"

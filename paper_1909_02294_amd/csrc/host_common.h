@@ -1,0 +1,60 @@
+// Host-side helpers shared by the plain, batched and serving entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/ivde.h"
+#include "ivde_internal.h"
+
+namespace ivde {
+
+struct ViewLayout {
+    int64_t row0;
+    int32_t n_bands;
+    int64_t tex_bytes;
+    size_t off_tex, off_counts, off_offsets, off_bbox, off_pixrec, off_bands;
+};
+
+// Byte offsets of everything one problem keeps in its workspace.
+struct Layout {
+    int n, L, J, wpg, n_lblocks, tex_f32, f16;
+    int max_w, max_h, max_s, max_bands;
+    int64_t total_rows, n_tasks;
+    size_t off_problem, off_views, off_pairs, off_sigma, off_flag, off_tasks;
+    size_t workspace_bytes, cost_bytes;
+    ViewLayout views[kMaxViews];
+};
+
+struct HostConstants {
+    Problem problem;
+    std::vector<ViewDesc> views;
+    std::vector<PairConst> pairs;
+    std::vector<float> sigma;
+};
+
+void set_error(const char *fmt, ...);
+const char *last_error();
+ivde_status hip_fail(hipError_t e, const char *what);
+
+ivde_status validate_problem(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                             const ivde_segmentation *segs, const ivde_label_range *labels,
+                             const ivde_options *opt, bool need_images);
+int default_labels_per_lane(int L);
+Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *segs, const ivde_label_range *labels,
+                   const ivde_options *opt, int bit_depth);
+ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views, const ivde_segmentation *segs,
+                    const ivde_label_range *labels, const ivde_options *opt, const Layout &ly, char *ws_base,
+                    void *cost_out, HostConstants &hc);
+hipError_t upload_constants(const HostConstants &hc, const Layout &ly, char *ws_base, hipStream_t s);
+Extents extents_of(const Layout &ly);
+ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                          const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
+                          const Layout &ly, char *ws, void *cost_out, int problem_index, Task *tasks,
+                          hipStream_t s);
+ivde_status check_workspace(const void *workspace, size_t have, size_t need);
+ivde_status check_tex_limits(const Layout &ly);
+
+}  // namespace ivde

@@ -1,0 +1,96 @@
+// Internal types shared by the host code and the gfx950 kernels of libivde.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ivde {
+
+constexpr int kMaxViews = 32;          // views per problem (pair table is n x n)
+constexpr int kBand = 32;              // rows per spatial band of the work list
+constexpr float kEdge = 1.0f / 64.0f;  // bilinear margin outside the outer pixel centres
+
+// Per-view device descriptor.  Everything a kernel needs about one view:
+// the caller's planes, the packed texels, the segment index and the
+// per-view constant of the reference plane.
+struct ViewDesc {
+    const void *plane[3];      // caller's Y, Cb, Cr planes (uint8 or uint16)
+    int64_t pitch[3];          // their row pitches in samples
+    const int32_t *seg;        // caller's segment map
+    int64_t seg_pitch;
+    void *tex;                 // packed texels, (W + 1) x (H + 1), zero border
+    int64_t tex_bytes;
+    int32_t W, H;
+    int32_t tex_pitch;         // texels per row = W + 1
+    int32_t S;                 // segments
+    int64_t row0;              // first cost-volume row of this view
+    int32_t *counts;           // [S] pixels per segment
+    int32_t *offsets;          // [S + 1] exclusive scan of counts
+    int32_t *bbox;             // [4 S] x0, y0, x1, y1 (inclusive)
+    float *pixrec;             // [W H][8] x, y, g.p, Y, Cb, Cr, 0, 0 in segment order
+    int32_t *band_count;       // [n_bands] segments per band, then band cursors
+    int32_t n_bands;
+    int32_t n_targets;
+    int32_t targets[kMaxViews];
+    float g[4];                // g_c = K_c^-T R_c n_r (g . p~ = n_r . ray direction)
+};
+
+// Projection of view c into target c2 (FP64 on the host, cast to FP32):
+// h = H p~ + sigma_{c,l} (g_c . p~) e,  u = h_x / h_z,  v = h_y / h_z.
+struct PairConst {
+    float H[9];
+    float e[3];
+};
+
+// One cost-volume problem in device memory.
+struct Problem {
+    int32_t n_views;
+    int32_t L;                 // labels
+    int32_t J;                 // labels per lane
+    int32_t n_lblocks;         // ceil(L / (64 J))
+    int32_t bilinear;
+    int32_t f16out;
+    int32_t bit_depth;
+    int32_t chroma_shift;
+    float norm;                // 3 (2^b - 1)
+    int32_t tex_f32;           // texels are float4 (bit depth > 11) instead of half4
+    int64_t total_rows;
+    ViewDesc *views;           // [n_views]
+    PairConst *pairs;          // [n_views * n_views], [c * n + c2]
+    float *sigma;              // [n_views * L], 1 / (z_l - delta_c) or 0 when undefined
+    void *cost;                // [total_rows * L] float or half
+    int32_t *flag;             // device error flag (segment id out of range)
+};
+
+// A unit of sweep work: one wave computes labels [64 J b, 64 J (b + 1)) of
+// one cost-volume row.
+struct Task {
+    int32_t problem;           // index into the problem table
+    int32_t view;
+    int32_t seg;
+    int32_t lblock;
+};
+
+// ---------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error.
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Sizes of the largest view of a problem, for grid shapes.
+struct Extents {
+    int n_views;
+    int max_w, max_h, max_s, max_bands;
+};
+hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
+hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem_index, Task *tasks,
+                           hipStream_t s);
+hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J,
+                        int bilinear, int tex_f32, int f16out, int waves_per_group, hipStream_t s);
+hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
+                                   int32_t *cursor, int64_t max_tasks, int J, int bilinear, int tex_f32,
+                                   int f16out, int waves_per_group, int n_groups, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s);
+hipError_t launch_compact_tasks(const Problem *dprob, const Task *all, int64_t n_all, const uint8_t *mask,
+                                Task *out, int32_t *n_out, hipStream_t s);
+hipError_t launch_copy_rows(const void *src, void *dst, int64_t bytes, hipStream_t s);
+
+}  // namespace ivde

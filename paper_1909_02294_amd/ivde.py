@@ -1,0 +1,272 @@
+"""Python binding of libivde (the C ABI in include/ivde.h).
+
+Argument marshalling only: torch provides device memory and streams, every
+computation runs in the library's gfx950 kernels.  There is no fallback:
+if libivde.so is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libivde.so")
+
+IVDE_OK, IVDE_EINVAL, IVDE_ENOMEM, IVDE_EBUDGET, IVDE_EHIP, IVDE_EBUSY, IVDE_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+REF_RIG_CENTER, REF_OWN = -1, -2
+NEAREST, BILINEAR = 0, 1
+F32, F16 = 0, 1
+TARGETS_ALL, TARGETS_NEAREST_LR, TARGETS_EXPLICIT = 0, 1, 2
+
+
+class IvdeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ivde status {status}: {msg}")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_double * 9), ("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("plane", ctypes.c_void_p * 3), ("pitch", ctypes.c_int64 * 3),
+                ("bit_depth", ctypes.c_int32), ("chroma_shift", ctypes.c_int32)]
+
+
+class Segmentation(ctypes.Structure):
+    _fields_ = [("seg_map", ctypes.c_void_p), ("pitch", ctypes.c_int64), ("num_segments", ctypes.c_int32)]
+
+
+class LabelRange(ctypes.Structure):
+    _fields_ = [("z_near", ctypes.c_double), ("z_far", ctypes.c_double),
+                ("num_labels", ctypes.c_int32), ("depth_ref", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("sampling", ctypes.c_int32), ("cost_dtype", ctypes.c_int32), ("targets", ctypes.c_int32),
+                ("target_mask", ctypes.c_void_p), ("labels_per_lane", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("cams", ctypes.POINTER(Camera)), ("views", ctypes.POINTER(Image)),
+                ("segs", ctypes.POINTER(Segmentation)), ("labels", LabelRange), ("cost_out", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32)]
+
+
+class FrameStats(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("rig_id", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rows_recomputed", ctypes.c_int64), ("rows_total", ctypes.c_int64),
+                ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+# every symbol include/ivde.h declares, with its ctypes signature
+_P = ctypes.c_void_p
+_I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+SIGNATURES = {
+    "ivde_cost_volume_size": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P]),
+    "ivde_cost_volume": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P]),
+    "ivde_argmin": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
+    "ivde_workspace_status": (_I32, [_P, _P]),
+    "ivde_batch_size": (_I32, [_I32, _P, _P, _P]),
+    "ivde_batch_create": (_I32, [_I32, _P, _P, _P, _SZ, _P]),
+    "ivde_batch_run": (_I32, [_P, _P, _I32]),
+    "ivde_batch_destroy": (None, [_P]),
+    "ivde_server_create": (_I32, [_P, _P]),
+    "ivde_rig_register": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
+    "ivde_stream_submit": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
+    "ivde_stream_poll": (_I32, [_P, ctypes.c_uint64, _P]),
+    "ivde_stream_wait": (_I32, [_P, ctypes.c_uint64, _P]),
+    "ivde_rig_resident": (_I32, [_P, _I32, _P, _P]),
+    "ivde_rig_reset": (_I32, [_P, _I32]),
+    "ivde_server_destroy": (None, [_P]),
+    "ivde_autotune": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _I32, _P, _P, _I32]),
+    "ivde_status_string": (ctypes.c_char_p, [_I32]),
+    "ivde_last_error": (ctypes.c_char_p, []),
+    "ivde_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libivde.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run __graft_entry__.build() (or python -m "
+                           f"paper_1909_02294_amd.build) first; there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != IVDE_OK:
+        lib = load()
+        raise IvdeError(status, lib.ivde_last_error().decode() or lib.ivde_status_string(status).decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libivde needs a GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_cameras(cams):
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].K[:] = [float(v) for v in np.asarray(c.K, np.float64).ravel()]
+        arr[i].R[:] = [float(v) for v in np.asarray(c.R, np.float64).ravel()]
+        arr[i].t[:] = [float(v) for v in np.asarray(c.t, np.float64).ravel()]
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+    return arr
+
+
+class DeviceViews:
+    """Device copies (torch tensors) of a rig's images and segment maps,
+    and the C descriptors pointing at them."""
+
+    def __init__(self, cams, Y, U, V, seg, S, bit_depth, chroma_shift, device="cuda"):
+        torch = _torch()
+        self.cams = list(cams)
+        self.n = len(self.cams)
+        self.bit_depth, self.chroma_shift = int(bit_depth), int(chroma_shift)
+        dt = torch.uint8 if bit_depth <= 8 else torch.int16   # uint16 bits carried in int16
+        npdt = np.uint8 if bit_depth <= 8 else np.uint16
+
+        def up(a, dtype, ndt):
+            a = np.ascontiguousarray(a, ndt)
+            if ndt == np.uint16:
+                a = a.view(np.int16)
+            return torch.from_numpy(a).to(device)
+
+        self.Y = [up(a, dt, npdt) for a in Y]
+        self.U = [up(a, dt, npdt) for a in U]
+        self.V = [up(a, dt, npdt) for a in V]
+        self.seg = [up(a, torch.int32, np.int32) for a in seg]
+        self.S = [int(s) for s in S]
+        self.c_cams = make_cameras(self.cams)
+        self.c_images = self._images()
+        self.c_segs = (Segmentation * self.n)()
+        for i in range(self.n):
+            self.c_segs[i].seg_map = self.seg[i].data_ptr()
+            self.c_segs[i].pitch = self.seg[i].shape[1]
+            self.c_segs[i].num_segments = self.S[i]
+
+    def _images(self):
+        imgs = (Image * self.n)()
+        for i in range(self.n):
+            for p, t in enumerate((self.Y[i], self.U[i], self.V[i])):
+                imgs[i].plane[p] = t.data_ptr()
+                imgs[i].pitch[p] = t.shape[1]
+            imgs[i].bit_depth, imgs[i].chroma_shift = self.bit_depth, self.chroma_shift
+        return imgs
+
+    def replace_images(self, Y, U, V):
+        """Copy a new frame's planes into the existing device buffers."""
+        torch = _torch()
+        for dst, src in ((self.Y, Y), (self.U, U), (self.V, V)):
+            for d, a in zip(dst, src):
+                a = np.ascontiguousarray(a)
+                if a.dtype == np.uint16:
+                    a = a.view(np.int16)
+                d.copy_(torch.from_numpy(a), non_blocking=False)
+
+    @classmethod
+    def from_workload(cls, wl, device="cuda"):
+        return cls(wl.cams, wl.Y, wl.U, wl.V, wl.seg, wl.S, wl.bit_depth, wl.chroma_shift, device)
+
+    @property
+    def rows(self):
+        return sum(self.S)
+
+
+def label_range(z_near, z_far, num_labels, depth_ref=REF_RIG_CENTER):
+    return LabelRange(float(z_near), float(z_far), int(num_labels), int(depth_ref))
+
+
+def options(sampling=BILINEAR, cost_dtype=F32, targets=TARGETS_ALL, target_mask=None,
+            labels_per_lane=0, waves_per_group=0):
+    o = Options(int(sampling), int(cost_dtype), int(targets), None, int(labels_per_lane), int(waves_per_group))
+    if target_mask is not None:
+        m = np.ascontiguousarray(target_mask, np.uint8)
+        o._mask = m          # keep alive
+        o.target_mask = m.ctypes.data
+    return o
+
+
+def sizes(dv: DeviceViews, lr: LabelRange, opt: Options):
+    lib = load()
+    cb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    check(lib.ivde_cost_volume_size(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt),
+                                    dv.bit_depth, ctypes.byref(cb), ctypes.byref(wb)))
+    return cb.value, wb.value
+
+
+def alloc_bytes(nbytes, device="cuda"):
+    """A 256-byte aligned device byte buffer from torch's allocator."""
+    torch = _torch()
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + max(int(nbytes), 1)]
+
+
+def cost_volume(dv: DeviceViews, lr: LabelRange, opt: Options, workspace=None, out=None, stream=None):
+    """ivde_cost_volume: returns the [rows, L] cost tensor (float32 or float16)."""
+    torch = _torch()
+    lib = load()
+    cb, wb = sizes(dv, lr, opt)
+    if workspace is None or workspace.numel() < wb:
+        workspace = alloc_bytes(wb)
+    L = lr.num_labels
+    dtype = torch.float16 if opt.cost_dtype == F16 else torch.float32
+    if out is None:
+        out = torch.empty((dv.rows, L), dtype=dtype, device="cuda")
+    assert out.dtype == dtype and out.is_contiguous() and out.numel() * out.element_size() >= cb
+    check(lib.ivde_cost_volume(dv.n, dv.c_cams, dv.c_images, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt),
+                               ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out, workspace
+
+
+def argmin(cost, stream=None, out=None):
+    torch = _torch()
+    lib = load()
+    rows, L = cost.shape
+    if out is None:
+        out = torch.empty(rows, dtype=torch.int32, device=cost.device)
+    dt = F16 if cost.dtype == torch.float16 else F32
+    check(lib.ivde_argmin(rows, L, dt, ctypes.c_void_p(cost.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          _stream_ptr(stream)))
+    return out
+
+
+def workspace_status(workspace, stream=None):
+    lib = load()
+    return lib.ivde_workspace_status(ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream))
+
+
+def last_error() -> str:
+    return load().ivde_last_error().decode()
