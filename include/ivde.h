@@ -127,7 +127,9 @@ typedef struct {
 
 /* Options.  labels_per_lane (1, 2, 4 or 8) and waves_per_group (1, 2 or 4)
  * are launch-shape knobs; 0 picks the tuned default.  They never change a
- * result. */
+ * result.  sweep_events, if both non-NULL, are hipEvent_t handles the call
+ * records on its stream immediately before and after the sweep kernel (for
+ * timing that kernel alone). */
 typedef struct {
     int32_t sampling;         /* IVDE_NEAREST or IVDE_BILINEAR */
     int32_t cost_dtype;       /* IVDE_F32 or IVDE_F16 storage */
@@ -135,6 +137,7 @@ typedef struct {
     const uint8_t *target_mask;   /* host n x n, for IVDE_TARGETS_EXPLICIT */
     int32_t labels_per_lane;
     int32_t waves_per_group;
+    void *sweep_events[2];
 } ivde_options;
 
 /* ---------------------------------------------------------------- plain form */
@@ -190,6 +193,7 @@ typedef struct {
     const ivde_segmentation *segs;
     ivde_label_range labels;
     void *cost_out;           /* device, ivde_cost_volume_size's cost_bytes */
+    int32_t *label_out;       /* device int32 [rows] for argmin labels, or NULL */
 } ivde_frame;
 
 typedef struct ivde_batch ivde_batch;
@@ -204,8 +208,11 @@ ivde_status ivde_batch_size(int32_t n_frames, const ivde_frame *frames, const iv
 ivde_status ivde_batch_create(int32_t n_frames, const ivde_frame *frames, const ivde_options *opt,
                               void *workspace, size_t workspace_bytes, ivde_batch **out);
 /* Runs the whole batch (image packing, segment index, task queue, one
- * persistent sweep) on `stream`.  use_graph != 0 replays a hipGraph
- * captured on first use. */
+ * persistent sweep, argmin for frames with label_out) on `stream`.
+ * use_graph != 0 replays a hipGraph captured on first use (on that first
+ * call the work is captured and then launched); the stream must not be the
+ * null stream then.  The sweep_events of `opt` given to ivde_batch_create
+ * bracket the persistent sweep in eager runs (use_graph == 0) only. */
 ivde_status ivde_batch_run(ivde_batch *b, ivde_stream stream, int32_t use_graph);
 void ivde_batch_destroy(ivde_batch *b);
 

@@ -87,6 +87,9 @@ hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_task
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
                                    int32_t *cursor, int64_t max_tasks, int J, int bilinear, int tex_f32,
                                    int f16out, int waves_per_group, int n_groups, hipStream_t s);
+// Resident groups per CU of the persistent sweep for this launch shape.
+hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16out, int waves_per_group,
+                                      int *groups_per_cu);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s);
 hipError_t launch_compact_tasks(const Problem *dprob, const Task *all, int64_t n_all, const uint8_t *mask,

@@ -665,6 +665,35 @@ hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_task
     }
 }
 
+template <int J, bool BIL, bool TEXF32, bool F16OUT>
+static hipError_t occ(int wpg, int *per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<J, BIL, TEXF32, F16OUT>,
+                                                        64 * wpg, 0);
+}
+
+hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16out, int wpg, int *per_cu)
+{
+    const int f16 = f16out;
+#define IVDE_OCC(JJ)                                                                                   \
+    do {                                                                                              \
+        if (bilinear) {                                                                               \
+            if (tex_f32) return f16 ? occ<JJ, true, true, true>(wpg, per_cu) : occ<JJ, true, true, false>(wpg, per_cu); \
+            return f16 ? occ<JJ, true, false, true>(wpg, per_cu) : occ<JJ, true, false, false>(wpg, per_cu); \
+        }                                                                                             \
+        if (tex_f32) return f16 ? occ<JJ, false, true, true>(wpg, per_cu) : occ<JJ, false, true, false>(wpg, per_cu); \
+        return f16 ? occ<JJ, false, false, true>(wpg, per_cu) : occ<JJ, false, false, false>(wpg, per_cu); \
+    } while (0)
+    switch (J) {
+    case 1: IVDE_OCC(1);
+    case 2: IVDE_OCC(2);
+    case 4: IVDE_OCC(4);
+    case 8: IVDE_OCC(8);
+    default: return hipErrorInvalidValue;
+    }
+#undef IVDE_OCC
+}
+
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
                                    int32_t *cursor, int64_t max_tasks, int J, int bilinear, int tex_f32,
                                    int f16out, int wpg, int n_groups, hipStream_t s)

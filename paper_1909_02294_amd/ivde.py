@@ -49,12 +49,13 @@ class LabelRange(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("sampling", ctypes.c_int32), ("cost_dtype", ctypes.c_int32), ("targets", ctypes.c_int32),
                 ("target_mask", ctypes.c_void_p), ("labels_per_lane", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32)]
+                ("waves_per_group", ctypes.c_int32), ("sweep_events", ctypes.c_void_p * 2)]
 
 
 class Frame(ctypes.Structure):
     _fields_ = [("n_views", ctypes.c_int32), ("cams", ctypes.POINTER(Camera)), ("views", ctypes.POINTER(Image)),
-                ("segs", ctypes.POINTER(Segmentation)), ("labels", LabelRange), ("cost_out", ctypes.c_void_p)]
+                ("segs", ctypes.POINTER(Segmentation)), ("labels", LabelRange), ("cost_out", ctypes.c_void_p),
+                ("label_out", ctypes.c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -208,8 +209,17 @@ def label_range(z_near, z_far, num_labels, depth_ref=REF_RIG_CENTER):
 
 
 def options(sampling=BILINEAR, cost_dtype=F32, targets=TARGETS_ALL, target_mask=None,
-            labels_per_lane=0, waves_per_group=0):
+            labels_per_lane=0, waves_per_group=0, sweep_events=None):
+    """sweep_events: optional pair of torch.cuda.Event(enable_timing=True),
+    recorded by the library around its sweep kernel."""
     o = Options(int(sampling), int(cost_dtype), int(targets), None, int(labels_per_lane), int(waves_per_group))
+    if sweep_events is not None:
+        torch = _torch()
+        for ev in sweep_events:           # make torch create the underlying events
+            ev.record(torch.cuda.current_stream())
+        o.sweep_events[0] = sweep_events[0].cuda_event
+        o.sweep_events[1] = sweep_events[1].cuda_event
+        o._events = sweep_events
     if target_mask is not None:
         m = np.ascontiguousarray(target_mask, np.uint8)
         o._mask = m          # keep alive
@@ -270,3 +280,151 @@ def workspace_status(workspace, stream=None):
 
 def last_error() -> str:
     return load().ivde_last_error().decode()
+
+
+# ---------------------------------------------------------------- batched form
+class Batch:
+    """ivde_batch: one persistent sweep over many frames (optionally replayed
+    from a hipGraph).  `frames` is a list of (DeviceViews, LabelRange,
+    cost tensor, label tensor or None); the tensors must outlive the batch."""
+
+    def __init__(self, frames, opt: Options):
+        torch = _torch()
+        lib = load()
+        self._keep = [frames, opt]
+        arr = (Frame * len(frames))()
+        for i, (dv, lr, cost, lab) in enumerate(frames):
+            arr[i].n_views = dv.n
+            arr[i].cams = ctypes.cast(dv.c_cams, ctypes.POINTER(Camera))
+            arr[i].views = ctypes.cast(dv.c_images, ctypes.POINTER(Image))
+            arr[i].segs = ctypes.cast(dv.c_segs, ctypes.POINTER(Segmentation))
+            arr[i].labels = lr
+            arr[i].cost_out = cost.data_ptr()
+            arr[i].label_out = lab.data_ptr() if lab is not None else None
+        self._frames = arr
+        wb = ctypes.c_size_t(0)
+        check(lib.ivde_batch_size(len(frames), arr, ctypes.byref(opt), ctypes.byref(wb)))
+        self.workspace = alloc_bytes(wb.value)
+        h = ctypes.c_void_p()
+        check(lib.ivde_batch_create(len(frames), arr, ctypes.byref(opt), ctypes.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace.numel(), ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None, use_graph=True):
+        check(load().ivde_batch_run(self.handle, _stream_ptr(stream), int(bool(use_graph))))
+
+    def close(self):
+        if self.handle:
+            load().ivde_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- serving form
+class Server:
+    """ivde_server over a torch-allocated arena (its size is the budget)."""
+
+    def __init__(self, arena_bytes, max_slots=4):
+        lib = load()
+        self.arena = alloc_bytes(arena_bytes)
+        cfg = ServerConfig(self.arena.data_ptr(), self.arena.numel(), int(max_slots))
+        h = ctypes.c_void_p()
+        check(lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._rigs = {}
+        self._inflight = {}
+
+    def register(self, dv: DeviceViews, lr: LabelRange, opt: Options) -> int:
+        rid = ctypes.c_int32(-1)
+        check(load().ivde_rig_register(self.handle, dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr),
+                                       ctypes.byref(opt), ctypes.byref(rid)))
+        self._rigs[rid.value] = (dv.n, sum(dv.S), lr.num_labels, opt.cost_dtype)
+        return rid.value
+
+    def submit(self, rig: int, images, mask=None, cost_out=None, label_out=None) -> int:
+        """images: a ctypes Image array (DeviceViews.c_images of the frame);
+        mask: device uint8 tensor [rows] or None (recompute every row)."""
+        t = ctypes.c_uint64(0)
+        check(load().ivde_stream_submit(self.handle, int(rig), images,
+                                        ctypes.c_void_p(mask.data_ptr()) if mask is not None else None,
+                                        ctypes.c_void_p(cost_out.data_ptr()) if cost_out is not None else None,
+                                        ctypes.c_void_p(label_out.data_ptr()) if label_out is not None else None,
+                                        ctypes.byref(t)))
+        self._inflight[t.value] = (images, mask, cost_out, label_out)   # keep alive
+        return t.value
+
+    @staticmethod
+    def _stats(st):
+        return dict(ticket=st.ticket, rig=st.rig_id, status=st.status, rows_recomputed=st.rows_recomputed,
+                    rows_total=st.rows_total, submit_us=st.submit_us, start_us=st.start_us, done_us=st.done_us,
+                    latency_ms=(st.done_us - st.submit_us) / 1e3)
+
+    def wait(self, ticket: int):
+        st = FrameStats()
+        rc = load().ivde_stream_wait(self.handle, ctypes.c_uint64(ticket), ctypes.byref(st))
+        self._inflight.pop(ticket, None)
+        check(rc)
+        return self._stats(st)
+
+    def poll(self, ticket: int):
+        st = FrameStats()
+        rc = load().ivde_stream_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(st))
+        if rc == IVDE_EBUSY:
+            return None
+        self._inflight.pop(ticket, None)
+        check(rc)
+        return self._stats(st)
+
+    def resident(self, rig: int):
+        """The rig's resident cost volume as a torch tensor view (copy it)."""
+        torch = _torch()
+        p, rows = ctypes.c_void_p(), ctypes.c_int64()
+        check(load().ivde_rig_resident(self.handle, int(rig), ctypes.byref(p), ctypes.byref(rows)))
+        n, R, L, dt = self._rigs[rig]
+        dtype = torch.float16 if dt == F16 else torch.float32
+        esz = 2 if dt == F16 else 4
+        base = self.arena.data_ptr()
+        off = p.value - base
+        flat = self.arena[off: off + R * L * esz]
+        return flat.view(dtype).view(R, L)
+
+    def reset(self, rig: int):
+        check(load().ivde_rig_reset(self.handle, int(rig)))
+
+    def close(self):
+        if self.handle:
+            load().ivde_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- tuning
+AUTOTUNE_SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4)]
+
+
+def autotune(dv: DeviceViews, lr: LabelRange, opt: Options, reps=2, stream=None):
+    """ivde_autotune: returns (best Options, {(J, wpg): microseconds or None})."""
+    torch = _torch()
+    lib = load()
+    probe = Options(opt.sampling, opt.cost_dtype, opt.targets, opt.target_mask, 1, 1)
+    cb, wb = sizes(dv, lr, probe)             # one label per lane needs the longest task list
+    ws = alloc_bytes(wb)
+    dtype = torch.float16 if opt.cost_dtype == F16 else torch.float32
+    out = torch.empty((dv.rows, lr.num_labels), dtype=dtype, device="cuda")
+    best = Options()
+    times = (ctypes.c_float * len(AUTOTUNE_SHAPES))()
+    check(lib.ivde_autotune(dv.n, dv.c_cams, dv.c_images, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
+                            _stream_ptr(stream), int(reps), ctypes.byref(best), times, len(AUTOTUNE_SHAPES)))
+    table = {s: (float(t) if t >= 0 else None) for s, t in zip(AUTOTUNE_SHAPES, times)}
+    return best, table

@@ -1,0 +1,191 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, its struct layouts match the Python binding, and argument
+errors come back synchronously without touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1909_02294_amd import ivde
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ivde.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ivde_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ivde.LIB_PATH):
+        from paper_1909_02294_amd import build
+        build.build()
+    return ivde.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", ivde.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s(ivde_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(names) == set(ivde.SIGNATURES), set(names) ^ set(ivde.SIGNATURES)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "ivde.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ivde_camera), sizeof(ivde_image),
+         sizeof(ivde_segmentation), sizeof(ivde_label_range), sizeof(ivde_options), sizeof(ivde_frame),
+         sizeof(ivde_server_config), sizeof(ivde_frame_stats));
+  printf("%zu %zu %zu %zu\\n", offsetof(ivde_options, target_mask), offsetof(ivde_options, sweep_events),
+         offsetof(ivde_frame, labels), offsetof(ivde_frame_stats, submit_us));
+  return 0;
+}
+""")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    want = [ctypes.sizeof(t) for t in (ivde.Camera, ivde.Image, ivde.Segmentation, ivde.LabelRange,
+                                       ivde.Options, ivde.Frame, ivde.ServerConfig, ivde.FrameStats)]
+    want += [ivde.Options.target_mask.offset, ivde.Options.sweep_events.offset, ivde.Frame.labels.offset,
+             ivde.FrameStats.submit_us.offset]
+    assert [int(x) for x in got] == want
+
+
+def _segs(n, S, w, h):
+    arr = (ivde.Segmentation * n)()
+    for i in range(n):
+        arr[i].seg_map = 0x1000     # sizes only: the pointer is never dereferenced
+        arr[i].pitch = w
+        arr[i].num_segments = S
+    return arr
+
+
+def _cams(n, w, h):
+    from paper_1909_02294_amd import synth
+    return ivde.make_cameras(synth.arc_rig(n, 3.0, 30.0, 100.0, w, h))
+
+
+def test_size_query(lib):
+    n, w, h, S, L = 3, 40, 30, 17, 100
+    cb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    lr = ivde.label_range(1.0, 5.0, L)
+    st = lib.ivde_cost_volume_size(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
+                                   ctypes.byref(ivde.options(ivde.BILINEAR, ivde.F32)), 10, ctypes.byref(cb),
+                                   ctypes.byref(wb))
+    assert st == ivde.IVDE_OK
+    assert cb.value == n * S * L * 4
+    assert wb.value > (w + 1) * (h + 1) * 8 * n
+    lib.ivde_cost_volume_size(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
+                              ctypes.byref(ivde.options(ivde.BILINEAR, ivde.F16)), 10, ctypes.byref(cb), None)
+    assert cb.value == n * S * L * 2
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_views", 0), ("n_views", 33), ("z_near", -1.0), ("z_far", float("nan")), ("num_labels", 0),
+    ("depth_ref", 7), ("sampling", 5), ("cost_dtype", 9), ("labels_per_lane", 3), ("waves_per_group", 8),
+    ("bit_depth", 7), ("bit_depth", 17), ("width", 0), ("segments", 0),
+])
+def test_invalid_arguments_are_rejected(lib, field, value):
+    n, w, h, S, L = 3, 40, 30, 17, 64
+    cams, segs = _cams(n, w, h), _segs(n, S, w, h)
+    lr = ivde.label_range(1.0, 5.0, L)
+    opt = ivde.options(ivde.BILINEAR, ivde.F32)
+    bd = 10
+    if field == "n_views":
+        n = value
+    elif field in ("z_near", "z_far", "num_labels", "depth_ref"):
+        setattr(lr, field, value)
+    elif field in ("sampling", "cost_dtype", "labels_per_lane", "waves_per_group"):
+        setattr(opt, field, value)
+    elif field == "bit_depth":
+        bd = value
+    elif field == "width":
+        cams[1].width = value
+    elif field == "segments":
+        segs[2].num_segments = value
+    cb = ctypes.c_size_t()
+    st = lib.ivde_cost_volume_size(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), bd, ctypes.byref(cb), None)
+    assert st == ivde.IVDE_EINVAL
+    assert lib.ivde_last_error().decode()
+
+
+def test_singular_or_projective_k_rejected(lib):
+    cams = _cams(2, 20, 10)
+    cams[0].K[6] = 0.1
+    cb = ctypes.c_size_t()
+    lr = ivde.label_range(1.0, 5.0, 8)
+    assert lib.ivde_cost_volume_size(2, cams, _segs(2, 4, 20, 10), ctypes.byref(lr),
+                                     ctypes.byref(ivde.options()), 8, ctypes.byref(cb), None) == ivde.IVDE_EINVAL
+    cams = _cams(2, 20, 10)
+    cams[1].K[0] = 0.0
+    cams[1].K[1] = 0.0
+    assert lib.ivde_cost_volume_size(2, cams, _segs(2, 4, 20, 10), ctypes.byref(lr),
+                                     ctypes.byref(ivde.options()), 8, ctypes.byref(cb), None) == ivde.IVDE_EINVAL
+
+
+def test_argmin_argument_checks(lib):
+    assert lib.ivde_argmin(-1, 4, ivde.F32, None, None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_argmin(5, 0, ivde.F32, None, None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_argmin(5, 4, 7, None, None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_argmin(5, 4, ivde.F32, None, None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_argmin(0, 4, ivde.F32, None, None, None) == ivde.IVDE_OK   # nothing to do
+
+
+def test_cost_volume_rejects_bad_workspace(lib):
+    n, w, h, S, L = 2, 16, 8, 3, 8
+    cams, segs = _cams(n, w, h), _segs(n, S, w, h)
+    imgs = (ivde.Image * n)()
+    for i in range(n):
+        for p in range(3):
+            imgs[i].plane[p] = 0x2000
+            imgs[i].pitch[p] = w
+        imgs[i].bit_depth, imgs[i].chroma_shift = 8, 0
+    lr = ivde.label_range(1.0, 5.0, L)
+    opt = ivde.options(ivde.NEAREST)
+    # null workspace, misaligned workspace, too small: all before any device work
+    assert lib.ivde_cost_volume(n, cams, imgs, segs, ctypes.byref(lr), ctypes.byref(opt), None, 0,
+                                ctypes.c_void_p(0x4000), None) == ivde.IVDE_EINVAL
+    assert lib.ivde_cost_volume(n, cams, imgs, segs, ctypes.byref(lr), ctypes.byref(opt), ctypes.c_void_p(0x1010),
+                                1 << 30, ctypes.c_void_p(0x4000), None) == ivde.IVDE_EINVAL
+    assert lib.ivde_cost_volume(n, cams, imgs, segs, ctypes.byref(lr), ctypes.byref(opt), ctypes.c_void_p(0x10000),
+                                16, ctypes.c_void_p(0x4000), None) == ivde.IVDE_ENOMEM
+    # mixed bit depths
+    imgs[1].bit_depth = 10
+    assert lib.ivde_cost_volume(n, cams, imgs, segs, ctypes.byref(lr), ctypes.byref(opt), ctypes.c_void_p(0x10000),
+                                1 << 30, ctypes.c_void_p(0x4000), None) == ivde.IVDE_EINVAL
+
+
+def test_batch_and_server_argument_checks(lib):
+    wb = ctypes.c_size_t()
+    assert lib.ivde_batch_size(0, None, ctypes.byref(ivde.options()), ctypes.byref(wb)) == ivde.IVDE_EINVAL
+    frames = (ivde.Frame * 1)()
+    opt = ivde.options(targets=ivde.TARGETS_EXPLICIT, target_mask=np.zeros((2, 2), np.uint8))
+    assert lib.ivde_batch_size(1, frames, ctypes.byref(opt), ctypes.byref(wb)) == ivde.IVDE_EINVAL
+    h = ctypes.c_void_p()
+    cfg = ivde.ServerConfig(None, 0, 4)
+    assert lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ivde.IVDE_EINVAL
+    cfg = ivde.ServerConfig(0x10000, 1 << 20, 99)
+    assert lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ivde.IVDE_EINVAL
+    st = ivde.FrameStats()
+    assert lib.ivde_stream_poll(None, 1, ctypes.byref(st)) == ivde.IVDE_EINVAL
+    assert lib.ivde_batch_run(None, None, 0) == ivde.IVDE_EINVAL
+
+
+def test_status_strings(lib):
+    for s in range(-6, 1):
+        assert lib.ivde_status_string(s)
+    assert b"gfx950" in lib.ivde_version()
