@@ -223,7 +223,7 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
         vl.row0 = ly.total_rows;
         ly.total_rows += S;
         vl.n_bands = (H + kBand - 1) / kBand;
-        vl.tex_bytes = (int64_t)(W + 1) * (H + 1) * (ly.tex_f32 ? 16 : 8);
+        vl.tex_bytes = (int64_t)(W + 2) * (H + 2) * (ly.tex_f32 ? 16 : 8);
         vl.off_tex = take((size_t)vl.tex_bytes + 16);
         vl.off_counts = take(sizeof(int32_t) * S);
         vl.off_offsets = take(sizeof(int32_t) * (S + 1));
@@ -324,7 +324,7 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
         d.tex_bytes = vl.tex_bytes;
         d.W = cams[v].width;
         d.H = cams[v].height;
-        d.tex_pitch = cams[v].width + 1;
+        d.tex_pitch = cams[v].width + 2;
         d.S = segs[v].num_segments;
         d.row0 = vl.row0;
         d.counts = reinterpret_cast<int32_t *>(ws_base + vl.off_counts);
@@ -342,12 +342,30 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
         d.g[3] = 0.f;
         const double delta = nv[0] * (C[3 * v] - Cr[3 * v]) + nv[1] * (C[3 * v + 1] - Cr[3 * v + 1]) +
                              nv[2] * (C[3 * v + 2] - Cr[3 * v + 2]);
+        bool sig_pos = true;
         for (int l = 0; l < L; ++l) {
             const double den = zl[l] - delta;
             const double sg = den != 0.0 ? 1.0 / den : 0.0;
             hc.sigma[(size_t)v * L + l] = std::isfinite(sg) ? (float)sg : 0.f;
+            sig_pos &= std::isfinite(sg) && (float)sg > 0.f;
         }
-        // pairs: H = K2 R2 M_c, e = K2 (R2 C_c + t2)
+        // g . p~ is affine in the pixel: its minimum over the image is at a
+        // corner.  With a margin for the FP32 evaluation, g . p~ > 0 and
+        // sigma > 0 everywhere mean every 3-D point is in front of camera v.
+        double gmin = INFINITY, gmax = 0.0;
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                const double x = cx ? cams[v].width - 1 : 0, y = cy ? cams[v].height - 1 : 0;
+                const double gpv = (Mv[0] * nv[0] + Mv[3] * nv[1] + Mv[6] * nv[2]) * x +
+                                   (Mv[1] * nv[0] + Mv[4] * nv[1] + Mv[7] * nv[2]) * y +
+                                   (Mv[2] * nv[0] + Mv[5] * nv[1] + Mv[8] * nv[2]);
+                gmin = std::fmin(gmin, gpv);
+                gmax = std::fmax(gmax, std::fabs(gpv));
+            }
+        d.front_all = sig_pos && gmin > 1e-4 * gmax;
+        // pairs: H = K2 R2 M_c, e = K2 (R2 C_c + t2), both shifted by one
+        // pixel in x and y (rows 0 and 1 gain row 2) to address the target's
+        // bordered texel image, whose texel (x + 1, y + 1) is pixel (x, y)
         for (int c2 = 0; c2 < n; ++c2) {
             if (c2 == v) continue;
             double KR[9], Hm[9], e[3], t1[3];
@@ -356,6 +374,12 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
             mv3(cams[c2].R, &C[3 * v], t1);
             for (int i = 0; i < 3; ++i) t1[i] += cams[c2].t[i];
             mv3(cams[c2].K, t1, e);
+            for (int i = 0; i < 3; ++i) {
+                Hm[i] += Hm[6 + i];
+                Hm[3 + i] += Hm[6 + i];
+            }
+            e[0] += e[2];
+            e[1] += e[2];
             PairConst &pc = hc.pairs[(size_t)v * n + c2];
             for (int i = 0; i < 9; ++i) pc.H[i] = (float)Hm[i];
             for (int i = 0; i < 3; ++i) pc.e[i] = (float)e[i];

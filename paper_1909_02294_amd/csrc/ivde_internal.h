@@ -18,10 +18,10 @@ struct ViewDesc {
     int64_t pitch[3];          // their row pitches in samples
     const int32_t *seg;        // caller's segment map
     int64_t seg_pitch;
-    void *tex;                 // packed texels, (W + 1) x (H + 1), zero border
+    void *tex;                 // packed texels, (W + 2) x (H + 2), edge-replicating border
     int64_t tex_bytes;
     int32_t W, H;
-    int32_t tex_pitch;         // texels per row = W + 1
+    int32_t tex_pitch;         // texels per row = W + 2
     int32_t S;                 // segments
     int64_t row0;              // first cost-volume row of this view
     int32_t *counts;           // [S] pixels per segment
@@ -30,13 +30,15 @@ struct ViewDesc {
     float *pixrec;             // [W H][8] x, y, g.p, Y, Cb, Cr, 0, 0 in segment order
     int32_t *band_count;       // [n_bands] segments per band, then band cursors
     int32_t n_bands;
+    int32_t front_all;         // every pixel at every label lies in front of this camera
     int32_t n_targets;
     int32_t targets[kMaxViews];
     float g[4];                // g_c = K_c^-T R_c n_r (g . p~ = n_r . ray direction)
 };
 
 // Projection of view c into target c2 (FP64 on the host, cast to FP32):
-// h = H p~ + sigma_{c,l} (g_c . p~) e,  u = h_x / h_z,  v = h_y / h_z.
+// h = H p~ + sigma_{c,l} (g_c . p~) e,  u = h_x / h_z,  v = h_y / h_z, in the
+// target's bordered texel coordinates (pixel coordinates plus one).
 struct PairConst {
     float H[9];
     float e[3];

@@ -24,6 +24,11 @@ namespace ivde {
 namespace {
 
 constexpr int kWave = 64;
+// gathers each wave keeps in flight in the sweep's inner loop
+#ifndef IVDE_INFLIGHT
+#define IVDE_INFLIGHT 4
+#endif
+
 constexpr uint32_t kRsrcWord3 = 0x00020000u;   // raw buffer, gfx9 family
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
@@ -75,24 +80,24 @@ __global__ void k_index_init(const Problem *__restrict__ P)
     if (i < 2 * v.n_bands) v.band_count[i] = 0;
 }
 
-// Packed texels: (W + 1) x (H + 1) of {Y, Cb, Cr, 0}, chroma replicated to
-// full resolution (pixel (x, y) owns chroma (x >> k, y >> k)), zero border
-// column and row so a bilinear pair read at x0 = W - 1 stays in bounds.
+// Packed texels: (W + 2) x (H + 2) of {Y, Cb, Cr, 0}, chroma replicated to
+// full resolution (pixel (x, y) owns chroma (x >> k, y >> k)).  Texel
+// (X, Y) holds pixel (clamp(X - 1), clamp(Y - 1)): a one-texel border that
+// repeats the edge, so a bilinear sample up to one pixel outside the image
+// reads the edge value, which is the clamped sample.
 template <typename TexT>
 __global__ void k_pack(const Problem *__restrict__ P)
 {
     const ViewDesc &v = P->views[blockIdx.z];
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x > v.W || y > v.H) return;
+    const int X = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (X > v.W + 1 || Y > v.H + 1) return;
+    const int x = min(max(X - 1, 0), v.W - 1), y = min(max(Y - 1, 0), v.H - 1);
     const int k = P->chroma_shift, b = P->bit_depth;
-    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    if (x < v.W && y < v.H) {
-        c0 = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
-        c1 = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
-        c2 = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
-    }
-    TexT *t = static_cast<TexT *>(v.tex) + (int64_t)y * v.tex_pitch + x;
+    const float c0 = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
+    const float c1 = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
+    const float c2 = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+    TexT *t = static_cast<TexT *>(v.tex) + (int64_t)Y * v.tex_pitch + X;
     if constexpr (sizeof(TexT) == 8) {
         __half2 a = __floats2half2_rn(c0, c1);
         __half2 bb = __floats2half2_rn(c2, 0.f);
@@ -297,11 +302,197 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
+// Target samples of one evaluation, as loaded.
+template <bool BIL, bool TEXF32>
+struct Sample;
+template <>
+struct Sample<true, false> {   // half texels (x0, y0), (x0 + 1, y0) and the row below
+    uint4 a, b;
+};
+template <>
+struct Sample<true, true> {
+    float4 a0, a1, b0, b1;
+};
+template <>
+struct Sample<false, false> {
+    uint2 a;
+};
+template <>
+struct Sample<false, true> {
+    float4 a;
+};
+
+struct Weights {
+    float w00, w01, w10, w11;
+};
+
+// Per-target constants of the projection h = q + w e.  Coordinates are in
+// the bordered texel frame (pixel + 1).  Bilinear samples are valid in
+// [1 - edge, W + edge] x [1 - edge, H + edge]; nearest ones when the rounded
+// position is a pixel, [1, W] x [1, H].
+struct Target {
+    __amdgpu_buffer_rsrc_t rs;
+    float lo, hi_x, hi_y;
+    uint32_t tp;
+    int rowB;
+    float e0, e1, e2;
+};
+
+// Projects one (pixel, label) into the target, decides validity and issues
+// the texel loads: h = q + w e with w = sigma (g . p~) = 1 / tau.  When the
+// host has shown that every pixel and label of the view lies in front of
+// the source camera (FRONT), the w > 0 test is skipped.  Out-of-image
+// coordinates are clamped, so every load is in bounds; the buffer
+// descriptor bounds them again.
+template <bool BIL, bool TEXF32, bool FRONT>
+__device__ __forceinline__ void project_issue(const Target &T, float qx, float qy, float qz, float w,
+                                              Sample<BIL, TEXF32> &smp, Weights &wt, bool &valid)
+{
+    constexpr int kTexB = TEXF32 ? 16 : 8;
+    const float hx = fmaf(w, T.e0, qx);
+    const float hy = fmaf(w, T.e1, qy);
+    const float hz = fmaf(w, T.e2, qz);
+    const float r = __builtin_amdgcn_rcpf(hz);
+    const float u = hx * r, v = hy * r;
+    valid = FRONT ? (hz > 0.f) : ((w > 0.f) & (hz > 0.f));
+    if constexpr (BIL) {
+        // clamp into the valid band; the sample is valid iff nothing moved.
+        // Clamped coordinates are positive (truncation is floor) and keep
+        // invalid lanes' reads next to the image border.
+        const float uc = __builtin_amdgcn_fmed3f(u, T.lo, T.hi_x);
+        const float vc = __builtin_amdgcn_fmed3f(v, T.lo, T.hi_y);
+        valid &= (uc == u) & (vc == v);
+        const uint32_t x0 = (uint32_t)(int)uc, y0 = (uint32_t)(int)vc;
+        const float ax = __builtin_amdgcn_fractf(uc), ay = __builtin_amdgcn_fractf(vc);
+        wt.w11 = ax * ay;
+        wt.w01 = ax - wt.w11;
+        wt.w10 = ay - wt.w11;
+        wt.w00 = (1.f - ax) - wt.w10;
+        const int off = (int)(mad_u24(y0, T.tp, x0) * kTexB);
+        if constexpr (!TEXF32) {
+            smp.a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
+            smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, T.rowB, 0));
+        } else {
+            smp.a0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
+            smp.a1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, 0, 0));
+            smp.b0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, T.rowB, 0));
+            smp.b1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, T.rowB, 0));
+        }
+    } else {
+        const float fx = floorf(u + 0.5f), fy = floorf(v + 0.5f);
+        valid &= (fx >= 1.f) & (fx <= T.hi_x - kEdge) & (fy >= 1.f) & (fy <= T.hi_y - kEdge);
+        const uint32_t xi = (uint32_t)(int)fx, yi = (uint32_t)(int)fy;
+        const int off = valid ? (int)(mad_u24(yi, T.tp, xi) * kTexB) : 0;
+        if constexpr (!TEXF32)
+            smp.a = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(T.rs, off, 0, 0));
+        else
+            smp.a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
+    }
+}
+
+// |dY| + |dCb| + |dCr| of one evaluation in code values.
+template <bool BIL, bool TEXF32>
+__device__ __forceinline__ float consume(const Sample<BIL, TEXF32> &smp, const Weights &wt, float ry, float ru,
+                                         float rv)
+{
+    float tY, tU, tV;
+    if constexpr (BIL) {
+        if constexpr (!TEXF32) {
+            tY = fmaf(h_lo(smp.a.x), wt.w00, -ry);
+            tU = fmaf(h_hi(smp.a.x), wt.w00, -ru);
+            tV = fmaf(h_lo(smp.a.y), wt.w00, -rv);
+            tY = fmaf(h_lo(smp.a.z), wt.w01, tY);
+            tU = fmaf(h_hi(smp.a.z), wt.w01, tU);
+            tV = fmaf(h_lo(smp.a.w), wt.w01, tV);
+            tY = fmaf(h_lo(smp.b.x), wt.w10, tY);
+            tU = fmaf(h_hi(smp.b.x), wt.w10, tU);
+            tV = fmaf(h_lo(smp.b.y), wt.w10, tV);
+            tY = fmaf(h_lo(smp.b.z), wt.w11, tY);
+            tU = fmaf(h_hi(smp.b.z), wt.w11, tU);
+            tV = fmaf(h_lo(smp.b.w), wt.w11, tV);
+        } else {
+            tY = fmaf(smp.a0.x, wt.w00, -ry);
+            tU = fmaf(smp.a0.y, wt.w00, -ru);
+            tV = fmaf(smp.a0.z, wt.w00, -rv);
+            tY = fmaf(smp.a1.x, wt.w01, tY);
+            tU = fmaf(smp.a1.y, wt.w01, tU);
+            tV = fmaf(smp.a1.z, wt.w01, tV);
+            tY = fmaf(smp.b0.x, wt.w10, tY);
+            tU = fmaf(smp.b0.y, wt.w10, tU);
+            tV = fmaf(smp.b0.z, wt.w10, tV);
+            tY = fmaf(smp.b1.x, wt.w11, tY);
+            tU = fmaf(smp.b1.y, wt.w11, tU);
+            tV = fmaf(smp.b1.z, wt.w11, tV);
+        }
+    } else {
+        if constexpr (!TEXF32) {
+            tY = h_lo(smp.a.x) - ry;
+            tU = h_hi(smp.a.x) - ru;
+            tV = h_lo(smp.a.y) - rv;
+        } else {
+            tY = smp.a.x - ry;
+            tU = smp.a.y - ru;
+            tV = smp.a.z - rv;
+        }
+    }
+    return fabsf(tY) + fabsf(tU) + fabsf(tV);
+}
+
+// PU pixels x J labels per step: all gathers of the step are issued before
+// the first is consumed, so a wave keeps PU J of them in flight.  The
+// accumulation order per label is the pixel order either way.
+template <int J, int PU, bool BIL, bool TEXF32, bool FRONT>
+__device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int i0, int i1, const float (&H)[9],
+                                             const Target &T, const float (&sig)[J], float (&acc)[J],
+                                             uint64_t (&acci)[J], int (&cnt)[J])
+{
+    int i = i0;
+    for (; i + PU <= i1; i += PU) {
+        Sample<BIL, TEXF32> smp[PU][J];
+        Weights wt[PU][J];
+        bool val[PU][J];
+        float ry[PU], ru[PU], rv[PU];
+#pragma unroll
+        for (int p = 0; p < PU; ++p) {
+            const f32x4 r0 = ldu4(pix + 8 * (int64_t)(i + p));
+            const f32x4 r1 = ldu4(pix + 8 * (int64_t)(i + p) + 4);
+            const float x = r0.x, y = r0.y, gp = r0.z;
+            ry[p] = r0.w;
+            ru[p] = r1.x;
+            rv[p] = r1.y;
+            const float qx = fmaf(H[0], x, fmaf(H[1], y, H[2]));
+            const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5]));
+            const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8]));
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                project_issue<BIL, TEXF32, FRONT>(T, qx, qy, qz, sig[j] * gp, smp[p][j], wt[p][j], val[p][j]);
+        }
+        // keep the scheduler from sinking the loads back next to their uses
+        if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = 0; p < PU; ++p) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const float d = consume<BIL, TEXF32>(smp[p][j], wt[p][j], ry[p], ru[p], rv[p]);
+                if constexpr (BIL) {
+                    acc[j] += val[p][j] ? d : 0.f;
+                } else {
+                    // integer code-value differences: exact in FP32, summed exactly
+                    acci[j] += val[p][j] ? (uint32_t)d : 0u;
+                }
+                cnt[j] += val[p][j] ? 1 : 0;
+            }
+        }
+    }
+    if constexpr (PU > 1) sweep_pixels<J, 1, BIL, TEXF32, FRONT>(pix, i, i1, H, T, sig, acc, acci, cnt);
+}
+
 // One task: labels [64 J b, 64 J (b + 1)) of row (view, seg).
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
 __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const Task task)
 {
     constexpr int kTexB = TEXF32 ? 16 : 8;
+    constexpr int PU = IVDE_INFLIGHT / J > 0 ? IVDE_INFLIGHT / J : 1;
     const int lane = lane_id();
     const int c = task.view, s = task.seg;
     const int L = ldu(&P->L), n = ldu(&P->n_views);
@@ -317,6 +508,8 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
     const int nt = ldu(&vc->n_targets);
     const int64_t row0 = ldu(&vc->row0);
 
+    const int front_all = ldu(&vc->front_all);
+
     int lab[J];
     float sig[J], best[J];
 #pragma unroll
@@ -329,16 +522,19 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
     for (int ti = 0; ti < nt; ++ti) {
         const int c2 = ldu(&vc->targets[ti]);
         const ViewDesc *vt = views + c2;
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(ldu(&vt->tex), ldu(&vt->tex_bytes));
-        const int tW = ldu(&vt->W), tH = ldu(&vt->H);
-        const float Wm1 = (float)(tW - 1), Hm1 = (float)(tH - 1);
-        const uint32_t tp = (uint32_t)ldu(&vt->tex_pitch);
-        const int rowB = (int)tp * kTexB;
+        Target T;
+        T.rs = make_rsrc(ldu(&vt->tex), ldu(&vt->tex_bytes));
+        T.lo = 1.f - kEdge;
+        T.hi_x = (float)ldu(&vt->W) + kEdge;
+        T.hi_y = (float)ldu(&vt->H) + kEdge;
+        T.tp = (uint32_t)ldu(&vt->tex_pitch);
+        T.rowB = (int)T.tp * kTexB;
         const float *pc = reinterpret_cast<const float *>(pairs + c * n + c2);
         const f32x4 ha = ldu4(pc), hb = ldu4(pc + 4), hc = ldu4(pc + 8);
-        const float H0 = ha.x, H1 = ha.y, H2 = ha.z, H3 = ha.w;
-        const float H4 = hb.x, H5 = hb.y, H6 = hb.z, H7 = hb.w;
-        const float H8 = hc.x, e0 = hc.y, e1 = hc.z, e2 = hc.w;
+        const float H[9] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w, hc.x};
+        T.e0 = hc.y;
+        T.e1 = hc.z;
+        T.e2 = hc.w;
 
         float acc[J];
         uint64_t acci[J];
@@ -349,95 +545,10 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
             acci[j] = 0;
             cnt[j] = 0;
         }
-
-        for (int i = p0; i < p1; ++i) {
-            const f32x4 r0 = ldu4(pix + 8 * (int64_t)i);
-            const f32x4 r1 = ldu4(pix + 8 * (int64_t)i + 4);
-            const float x = r0.x, y = r0.y, gp = r0.z;
-            const float ry = r0.w, ru = r1.x, rv = r1.y;
-            const float qx = fmaf(H0, x, fmaf(H1, y, H2));
-            const float qy = fmaf(H3, x, fmaf(H4, y, H5));
-            const float qz = fmaf(H6, x, fmaf(H7, y, H8));
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const float w = sig[j] * gp;          // 1 / tau: positive in front of view c
-                const float hx = fmaf(w, e0, qx);
-                const float hy = fmaf(w, e1, qy);
-                const float hz = fmaf(w, e2, qz);
-                const float r = __builtin_amdgcn_rcpf(hz);
-                const float u = hx * r, v = hy * r;
-                bool valid = (w > 0.f) & (hz > 0.f);
-                if constexpr (BIL) {
-                    const float uc = __builtin_amdgcn_fmed3f(u, 0.f, Wm1);
-                    const float vc2 = __builtin_amdgcn_fmed3f(v, 0.f, Hm1);
-                    valid &= (fabsf(u - uc) <= kEdge) & (fabsf(v - vc2) <= kEdge);
-                    const uint32_t x0 = (uint32_t)(int)uc, y0 = (uint32_t)(int)vc2;
-                    const float ax = __builtin_amdgcn_fractf(uc), ay = __builtin_amdgcn_fractf(vc2);
-                    const float bx = 1.f - ax, by = 1.f - ay;
-                    const float w00 = bx * by, w01 = ax * by, w10 = bx * ay, w11 = ax * ay;
-                    const int off = (int)(mad_u24(y0, tp, x0) * kTexB);
-                    float tY, tU, tV;
-                    if constexpr (!TEXF32) {
-                        // texels (x0, y0), (x0 + 1, y0) and the row below
-                        const uint4 a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-                        const uint4 bq = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, rowB, 0));
-                        tY = fmaf(h_lo(a.x), w00, -ry);
-                        tU = fmaf(h_hi(a.x), w00, -ru);
-                        tV = fmaf(h_lo(a.y), w00, -rv);
-                        tY = fmaf(h_lo(a.z), w01, tY);
-                        tU = fmaf(h_hi(a.z), w01, tU);
-                        tV = fmaf(h_lo(a.w), w01, tV);
-                        tY = fmaf(h_lo(bq.x), w10, tY);
-                        tU = fmaf(h_hi(bq.x), w10, tU);
-                        tV = fmaf(h_lo(bq.y), w10, tV);
-                        tY = fmaf(h_lo(bq.z), w11, tY);
-                        tU = fmaf(h_hi(bq.z), w11, tU);
-                        tV = fmaf(h_lo(bq.w), w11, tV);
-                    } else {
-                        const float4 a0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-                        const float4 a1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
-                        const float4 b0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, rowB, 0));
-                        const float4 b1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, rowB, 0));
-                        tY = fmaf(a0.x, w00, -ry);
-                        tU = fmaf(a0.y, w00, -ru);
-                        tV = fmaf(a0.z, w00, -rv);
-                        tY = fmaf(a1.x, w01, tY);
-                        tU = fmaf(a1.y, w01, tU);
-                        tV = fmaf(a1.z, w01, tV);
-                        tY = fmaf(b0.x, w10, tY);
-                        tU = fmaf(b0.y, w10, tU);
-                        tV = fmaf(b0.z, w10, tV);
-                        tY = fmaf(b1.x, w11, tY);
-                        tU = fmaf(b1.y, w11, tU);
-                        tV = fmaf(b1.z, w11, tV);
-                    }
-                    const float d = fabsf(tY) + fabsf(tU) + fabsf(tV);
-                    acc[j] += valid ? d : 0.f;
-                    cnt[j] += valid ? 1 : 0;
-                } else {
-                    const float fx = floorf(u + 0.5f), fy = floorf(v + 0.5f);
-                    valid &= (fx >= 0.f) & (fx <= Wm1) & (fy >= 0.f) & (fy <= Hm1);
-                    const uint32_t xi = (uint32_t)(int)fx, yi = (uint32_t)(int)fy;
-                    const int off = (int)(mad_u24(yi, tp, xi) * kTexB);
-                    float dY, dU, dV;
-                    if constexpr (!TEXF32) {
-                        const uint2 a = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-                        dY = h_lo(a.x) - ry;
-                        dU = h_hi(a.x) - ru;
-                        dV = h_lo(a.y) - rv;
-                    } else {
-                        const float4 a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-                        dY = a.x - ry;
-                        dU = a.y - ru;
-                        dV = a.z - rv;
-                    }
-                    // integer code-value differences: exact in FP32, summed exactly
-                    const uint32_t d = (uint32_t)(fabsf(dY) + fabsf(dU) + fabsf(dV));
-                    acci[j] += valid ? d : 0u;
-                    cnt[j] += valid ? 1 : 0;
-                }
-            }
-        }
+        if (front_all)
+            sweep_pixels<J, PU, BIL, TEXF32, true>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+        else
+            sweep_pixels<J, PU, BIL, TEXF32, false>(pix, p0, p1, H, T, sig, acc, acci, cnt);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (cnt[j] > 0) {
@@ -465,8 +576,8 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
 // remapping gives each XCD a contiguous stretch of the spatially ordered
 // task list, so its L2 holds the image bands those tasks gather from.
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
-__global__ __launch_bounds__(256) void k_sweep(const Problem *__restrict__ probs, const Task *__restrict__ tasks,
-                                               int64_t n_tasks, int per_xcd)
+__device__ __forceinline__ void sweep_plain_body(const Problem *__restrict__ probs, const Task *__restrict__ tasks,
+                                                 int64_t n_tasks, int per_xcd)
 {
     const int wpg = blockDim.x / kWave;
     const int b = blockIdx.x;
@@ -475,6 +586,23 @@ __global__ __launch_bounds__(256) void k_sweep(const Problem *__restrict__ probs
     if (t >= n_tasks) return;
     const Task task = ldu_task(tasks + t);
     sweep_task<J, BIL, TEXF32, F16OUT>(probs + task.problem, task);
+}
+
+template <int J, bool BIL, bool TEXF32, bool F16OUT>
+__global__ __launch_bounds__(256) void k_sweep(const Problem *__restrict__ probs, const Task *__restrict__ tasks,
+                                               int64_t n_tasks, int per_xcd)
+{
+    sweep_plain_body<J, BIL, TEXF32, F16OUT>(probs, tasks, n_tasks, per_xcd);
+}
+
+// One label per lane with half texels fits 64 VGPRs without spilling; at 8
+// waves per SIMD it hides gather latency best (measured on the 8-view 1080p
+// workload).
+template <bool BIL, bool F16OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_j1(
+    const Problem *__restrict__ probs, const Task *__restrict__ tasks, int64_t n_tasks, int per_xcd)
+{
+    sweep_plain_body<1, BIL, false, F16OUT>(probs, tasks, n_tasks, per_xcd);
 }
 
 // Persistent launch: waves pull tasks from a shared cursor until the device
@@ -590,7 +718,7 @@ hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32,
     }
     {
         dim3 blk(64, 4);
-        dim3 grd((unsigned)((ext.max_w + 1 + 63) / 64), (unsigned)((ext.max_h + 1 + 3) / 4), nv);
+        dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + 3) / 4), nv);
         if (tex_f32)
             hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
         else
@@ -624,8 +752,12 @@ static hipError_t sweep_plain(const Problem *dprobs, const Task *tasks, int64_t 
     const int64_t per_xcd = (groups + 7) / 8;
     const int64_t grid = per_xcd * 8;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sweep<J, BIL, TEXF32, F16OUT>), dim3((unsigned)grid), dim3(64 * wpg), 0, s, dprobs,
-                       tasks, n_tasks, (int)per_xcd);
+    if constexpr (J == 1 && !TEXF32)
+        hipLaunchKernelGGL((k_sweep_j1<BIL, F16OUT>), dim3((unsigned)grid), dim3(64 * wpg), 0, s, dprobs, tasks,
+                           n_tasks, (int)per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep<J, BIL, TEXF32, F16OUT>), dim3((unsigned)grid), dim3(64 * wpg), 0, s, dprobs,
+                           tasks, n_tasks, (int)per_xcd);
     return hipGetLastError();
 }
 
