@@ -226,6 +226,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--served-seconds", type=float, default=4.0)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--gop", type=int, default=0, help="served: every GOP-th frame of a rig is an I frame")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
