@@ -14,6 +14,7 @@ Inputs are resident in HBM before the timed region.  Prints one JSON line.
                   against 16 sequential plain launches
   --mode served   the serving loop on a Poisson stream from three rigs
   --mode copycal  a device copy of known size (calibrates HBM counters)
+  --mode window   the paper's own 3x3 centre-window term
 """
 from __future__ import annotations
 
@@ -196,6 +197,41 @@ def bench_plain(args):
     return out
 
 
+def bench_window(args):
+    """The paper's own window term (3x3 at the segment centre, nearest
+    left/right views) on the 8-view 1080p workload: one step is image
+    packing, segment index, segment statistics and the window kernel."""
+    import torch
+    from paper_1909_02294_amd import ivde, synth
+
+    wl = synth.make_cfg1()
+    dv = ivde.DeviceViews.from_workload(wl)
+    lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
+    for _ in range(args.warmup):
+        m, hit, ws = ivde.window_cost(dv, lr, 1)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        m, hit, ws = ivde.window_cost(dv, lr, 1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    lat = [a.elapsed_time(b) for a, b in ev]
+    pairs = sum(S * (int(c > 0) + int(c + 1 < wl.n_views)) for c, S in enumerate(wl.S))
+    evals = pairs * wl.num_labels
+    return {"metric": "window evaluations/s (segment x neighbour view x label, 3x3 taps)",
+            "value": evals / elapsed, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": elapsed * 1e3, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "8-view 1920x1080 YUV420 10-bit arc rig, 20000 segments per view, 256 labels, "
+                                   "3x3 window at the segment centre, nearest left and right views",
+                       "evals_per_step": evals,
+                       "step": "pack + segment index + segment statistics + window kernel"},
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}}
+
+
 def copy_calibration(args):
     """A plain device copy of known size (read n bytes, write n bytes per
     dispatch): what the HBM counters read for it scales the sweep's counts."""
@@ -218,7 +254,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window"], default="plain")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--labels-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
@@ -241,6 +277,8 @@ def main():
         out = bench_plain(args)
     elif args.mode == "copycal":
         out = copy_calibration(args)
+    elif args.mode == "window":
+        out = bench_window(args)
     elif args.mode == "batched":
         from paper_1909_02294_amd import benchforms
         out = benchforms.bench_batched(args)

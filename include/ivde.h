@@ -271,6 +271,43 @@ ivde_status ivde_rig_resident(ivde_server *srv, int32_t rig_id, const void **cos
 ivde_status ivde_rig_reset(ivde_server *srv, int32_t rig_id);
 void ivde_server_destroy(ivde_server *srv);
 
+/* ---------------------------------------------------------------- the paper's window term */
+
+/* Output and workspace sizes of ivde_window_cost (out_bytes is the size of
+ * each of m_out and hit_out). */
+ivde_status ivde_window_cost_size(int32_t n_views, const ivde_camera *cams,
+                                  const ivde_segmentation *segs,
+                                  const ivde_label_range *labels, int32_t bit_depth,
+                                  size_t *out_bytes, size_t *workspace_bytes);
+
+/* The paper's inter-view matching core as printed (Sec. III-C, Eq. (4)):
+ * for every segment s of view c, each neighbouring view c' of Sec. III-B
+ * (slot 0: c - 1, slot 1: c + 1; views ordered along the rig) and each
+ * label l, the centre mu_s of s (the centroid of its pixels rounded half
+ * up) is lifted to level l and transformed into c'; the target window is
+ * centred on the nearest pixel of the projection.
+ *   m_out    device float [rows][2][L]: mean over the (2 radius + 1)^2 taps
+ *            of |dY| + |dCb| + |dCr| in 8-bit code values (taps outside an
+ *            image are clamped to its edge); NaN where c' does not exist or
+ *            the projection is behind a camera or outside c'
+ *   hit_out  device int32 [rows][2][L]: the segment s' of c' under the
+ *            projected centre, as its row of the volume (row offset of c'
+ *            plus its id), or -1 where m is NaN
+ * Rows are ordered as in ivde_cost_volume.  radius 0..8 (the paper uses a
+ * 3x3 window, radius 1, Sec. V-A). */
+ivde_status ivde_window_cost(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                             const ivde_segmentation *segs, const ivde_label_range *labels,
+                             int32_t radius, void *workspace, size_t workspace_bytes,
+                             float *m_out, int32_t *hit_out, ivde_stream stream);
+
+/* Eq. (5) summed over the neighbouring views for a fixed labelling d of
+ * all rows (device int32 [rows]):
+ *   out[r][l] = sum over slots with hit >= 0 of [d[hit] == l] min(0, m - K)
+ * m and hit as written by ivde_window_cost; the paper uses K = 30. */
+ivde_status ivde_window_energy(int64_t rows, int32_t num_labels, const float *m,
+                               const int32_t *hit, const int32_t *labelling, float K,
+                               float *out, ivde_stream stream);
+
 /* ---------------------------------------------------------------- tuning */
 
 /* Times every (labels_per_lane, waves_per_group) launch shape on the given

@@ -78,6 +78,13 @@ def load():
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_segment_stats.restype = ctypes.c_int
+        lib.oracle_segment_stats.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_window_rows.restype = ctypes.c_int
+        lib.oracle_window_rows.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -139,11 +146,8 @@ class Problem:
         return np.concatenate([[0], np.cumsum(self.S)]).astype(np.int64)
 
 
-def cost_rows(pb: Problem, views, segs, with_terms=False):
-    """C rows (float64, len(views) x L) for the (view, segment) pairs; with
-    with_terms also the per-target means m (NaN where nothing is valid) and
-    valid counts, both len(views) x n x L."""
-    lib = load()
+def _c_problem(pb: Problem):
+    """The C view of a Problem; returns (struct, keep-alive list)."""
     n, L = pb.n_views, pb.num_labels
     dt = np.uint8 if pb.bit_depth <= 8 else np.uint16
     keep = []
@@ -185,6 +189,23 @@ def cost_rows(pb: Problem, views, segs, with_terms=False):
                     S.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                     pb.z_near, pb.z_far, L, pb.depth_ref, int(pb.bilinear),
                     T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    keep.extend([planes, segp])
+    return prob, keep
+
+
+def cost_rows(pb: Problem, views, segs, with_terms=False):
+    """C rows (float64, len(views) x L) for the (view, segment) pairs; with
+    with_terms also the per-target means m (NaN where nothing is valid) and
+    valid counts, both len(views) x n x L."""
+    lib = load()
+    n, L = pb.n_views, pb.num_labels
+    prob, keep = _c_problem(pb)
+
+    def arr(a, dtype):
+        a = np.ascontiguousarray(a, dtype)
+        keep.append(a)
+        return a
+
     rv = arr(views, np.int32)
     rs = arr(segs, np.int32)
     nr = len(rv)
@@ -230,3 +251,54 @@ def served(prev, pb: Problem, changed):
         segs = (idx - off[views]).astype(np.int32)
         out[idx] = cost_rows(pb, views, segs)
     return out
+
+
+def segment_stats(pb: Problem, view: int):
+    """(count [S], centre [S, 2] int, mean YCbCr [S, 3]) of one view: the
+    segment centre mu_s of Sec. III-C is the centroid rounded half up."""
+    lib = load()
+    prob, keep = _c_problem(pb)
+    S = pb.S[view]
+    cnt = np.empty(S, np.int64)
+    cen = np.empty((S, 2), np.int32)
+    mean = np.empty((S, 3), np.float64)
+    rc = lib.oracle_segment_stats(ctypes.byref(prob), int(view), cnt.ctypes.data, cen.ctypes.data, mean.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_segment_stats failed with status {rc}")
+    return cnt, cen, mean
+
+
+def window_rows(pb: Problem, views, segs, radius=1, with_uv=False):
+    """Eq. (4) of Sec. III-C at the segment centre towards views c - 1 (slot 0)
+    and c + 1 (slot 1): m [n, 2, L] in 8-bit code values (NaN where there is
+    no match), hit [n, 2, L] the matched segment's volume row (-1), and with
+    with_uv the projected centre [n, 2, L, 2]."""
+    lib = load()
+    prob, keep = _c_problem(pb)
+    rv = np.ascontiguousarray(views, np.int32)
+    rs = np.ascontiguousarray(segs, np.int32)
+    nr, L = len(rv), pb.num_labels
+    m = np.empty((nr, 2, L), np.float64)
+    hit = np.empty((nr, 2, L), np.int64)
+    uv = np.empty((nr, 2, L, 2), np.float64) if with_uv else None
+    rc = lib.oracle_window_rows(ctypes.byref(prob), nr, rv.ctypes.data, rs.ctypes.data, int(radius), m.ctypes.data,
+                                hit.ctypes.data, uv.ctypes.data if with_uv else None)
+    if rc != 0:
+        raise ValueError(f"oracle_window_rows failed with status {rc}")
+    return (m, hit, uv) if with_uv else (m, hit)
+
+
+def window_energy(m, hit, labelling, K=30.0):
+    """Eq. (5) summed over the neighbouring views for a fixed labelling of all
+    segments: E[r, l] = sum over slots with a match of
+    [labelling[hit] == l] * min(0, m - K)."""
+    m = np.asarray(m, np.float64)
+    hit = np.asarray(hit)
+    lab = np.asarray(labelling)
+    L = m.shape[2]
+    E = np.zeros((m.shape[0], L))
+    ok = hit >= 0
+    d_hit = np.where(ok, lab[np.where(ok, hit, 0)], -1)
+    same = d_hit == np.arange(L)[None, None, :]
+    E += np.where(ok & same, np.minimum(0.0, m - K), 0.0).sum(axis=1)
+    return E

@@ -138,3 +138,84 @@ def cost_volume(cams, Y, U, V, seg, S, bit_depth, chroma_shift, z_near, z_far, L
                 row.append(1.0 if best is None else best)
             rows.append(row)
     return rows
+
+
+def segment_centres(seg, S):
+    """Centroid of each segment's pixel coordinates, rounded half up."""
+    sx, sy, n = [0] * S, [0] * S, [0] * S
+    for y, row in enumerate(seg):
+        for x, s in enumerate(row):
+            s = int(s)
+            sx[s] += x
+            sy[s] += y
+            n[s] += 1
+    return [(math.floor(sx[s] / n[s] + 0.5), math.floor(sy[s] / n[s] + 0.5)) if n[s] else None for s in range(S)]
+
+
+def window_cost(cams, Y, U, V, seg, S, bit_depth, chroma_shift, z_near, z_far, L, radius, depth_ref="rig"):
+    """Eq. (4) at each segment centre towards the views c - 1 and c + 1:
+    returns (m, hit) as nested lists [row][slot][label]; m in 8-bit code
+    values or None, hit the matched segment's volume row or -1."""
+    n = len(cams)
+    k = chroma_shift
+    scale = float(1 << (bit_depth - 8))
+    Ks = [_mat(c.K) for c in cams]
+    Rs = [_mat(c.R) for c in cams]
+    ts = [_vec(c.t) for c in cams]
+    centres = [[-v for v in _mtv(Rs[i], ts[i])] for i in range(n)]
+    axes = [list(Rs[i][2]) for i in range(n)]
+    row0 = [sum(S[:i]) for i in range(n)]
+    if depth_ref == "rig":
+        Cr = [sum(centres[i][j] for i in range(n)) / n for j in range(3)]
+        a = [sum(axes[i][j] for i in range(n)) / n for j in range(3)]
+        ln = math.sqrt(_dot(a, a))
+        nr = [v / ln for v in a]
+    depths = [1.0 / (1.0 / z_far + (l / (L - 1) if L > 1 else 0.0) * (1.0 / z_near - 1.0 / z_far)) for l in range(L)]
+
+    def pix(luma, plane, sh, x, y):
+        # clamp to the image (luma size), then read the plane at its resolution
+        h, w = len(luma), len(luma[0])
+        x = min(max(x, 0), w - 1)
+        y = min(max(y, 0), h - 1)
+        return float(plane[y >> sh][x >> sh])
+
+    ms, hits = [], []
+    for c in range(n):
+        if depth_ref != "rig":
+            i = c if depth_ref == "own" else int(depth_ref)
+            Cr, nr = centres[i], axes[i]
+        mus = segment_centres(seg[c], S[c])
+        for s in range(S[c]):
+            mrow, hrow = [], []
+            for c2 in (c - 1, c + 1):
+                mm, hh = [None] * L, [-1] * L
+                if 0 <= c2 < n and mus[s] is not None:
+                    mx, my = mus[s]
+                    d = _mtv(Rs[c], _k_inverse_pixel(Ks[c], mx, my))
+                    for l in range(L):
+                        tau = (depths[l] - _dot(nr, [centres[c][j] - Cr[j] for j in range(3)])) / _dot(nr, d)
+                        if not tau > 0:
+                            continue
+                        X = [centres[c][j] + tau * d[j] for j in range(3)]
+                        Xc = [a + b for a, b in zip(_mv(Rs[c2], X), ts[c2])]
+                        if not Xc[2] > 0:
+                            continue
+                        h = _mv(Ks[c2], Xc)
+                        tx, ty = math.floor(h[0] / h[2] + 0.5), math.floor(h[1] / h[2] + 0.5)
+                        if not (0 <= tx < cams[c2].width and 0 <= ty < cams[c2].height):
+                            continue
+                        tot = 0.0
+                        for dy in range(-radius, radius + 1):
+                            for dx in range(-radius, radius + 1):
+                                for plane, sh in ((0, 0), (1, k), (2, k)):
+                                    src = (Y, U, V)[plane]
+                                    a_ = pix(Y[c], src[c], sh, mx + dx, my + dy)
+                                    b_ = pix(Y[c2], src[c2], sh, tx + dx, ty + dy)
+                                    tot += abs(a_ - b_)
+                        mm[l] = tot / ((2 * radius + 1) ** 2 * scale)
+                        hh[l] = row0[c2] + int(seg[c2][ty][tx])
+                mrow.append(mm)
+                hrow.append(hh)
+            ms.append(mrow)
+            hits.append(hrow)
+    return ms, hits

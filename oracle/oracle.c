@@ -33,6 +33,10 @@
  *
  * Loops run view -> segment -> pixel -> label -> target, with OpenMP over the
  * requested (view, segment) rows.  Every sum is FP64.
+ *
+ * Also here: per-segment statistics (count, centre, mean colour) and the
+ * paper's own window matching core of Eq. (4) towards the neighbouring views
+ * (oracle_segment_stats, oracle_window_rows, at the end of the file).
  */
 #include <math.h>
 #include <stdint.h>
@@ -297,5 +301,185 @@ done:
     free(Kinv);
     free(Cc);
     free(zl);
+    return rc;
+}
+
+/*
+ * Per-segment statistics of view v: pixel count, centre (the centroid of the
+ * pixel coordinates rounded half up, the segment centre mu_s of Sec. III-C)
+ * and mean Y, Cb, Cr (the segment colour of Sec. III-D and III-E).
+ *   count  S      centre  2 S (x, y)      mean  3 S
+ */
+int oracle_segment_stats(const oracle_problem *pb, int v, int64_t *count, int32_t *centre, double *mean)
+{
+    if (v < 0 || v >= pb->n_views) return -1;
+    const int64_t W = pb->width[v], H = pb->height[v], S = pb->num_segments[v];
+    const int k = pb->chroma_shift;
+    double *sx = (double *)calloc((size_t)S, sizeof(double));
+    double *sy = (double *)calloc((size_t)S, sizeof(double));
+    if (!sx || !sy) { free(sx); free(sy); return -2; }
+    for (int64_t s = 0; s < S; ++s) { count[s] = 0; mean[3 * s] = mean[3 * s + 1] = mean[3 * s + 2] = 0.0; }
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            const int32_t s = pb->seg[v][y * W + x];
+            if (s < 0 || s >= S) { free(sx); free(sy); return -1; }
+            count[s]++;
+            sx[s] += (double)x;
+            sy[s] += (double)y;
+            mean[3 * s] += sample_at(pb, v, 0, x, y);
+            mean[3 * s + 1] += sample_at(pb, v, 1, x >> k, y >> k);
+            mean[3 * s + 2] += sample_at(pb, v, 2, x >> k, y >> k);
+        }
+    for (int64_t s = 0; s < S; ++s) {
+        if (count[s] == 0) { centre[2 * s] = centre[2 * s + 1] = -1; continue; }
+        const double n = (double)count[s];
+        centre[2 * s] = (int32_t)floor(sx[s] / n + 0.5);
+        centre[2 * s + 1] = (int32_t)floor(sy[s] / n + 0.5);
+        for (int c = 0; c < 3; ++c) mean[3 * s + c] /= n;
+    }
+    free(sx);
+    free(sy);
+    return 0;
+}
+
+/*
+ * The paper's window matching core (Sec. III-C, Eq. (4)) for the requested
+ * rows, towards the neighbouring views of Sec. III-B: slot 0 is view c - 1,
+ * slot 1 view c + 1 (views ordered along the rig).  For label l the centre
+ * mu_s is lifted to the level plane and transformed into c' (the same T[.]
+ * as oracle_cost_rows); the target window is centred on the nearest pixel
+ * of the projection.  Window taps outside an image are clamped to its edge.
+ *   m    n_rows x 2 x L   mean over the (2r+1)^2 taps of |dY| + |dCb| + |dCr|
+ *                         in 8-bit code values (divided by 2^(b-8));
+ *                         NaN where there is no neighbour or the projection
+ *                         is behind a camera or outside c'
+ *   hit  n_rows x 2 x L   the segment of c' under the projected centre, as a
+ *                         row of the volume (row offset of c' plus its id),
+ *                         or -1 where m is NaN
+ *   uv   n_rows x 2 x L x 2 (optional) the projected centre in pixels of c'
+ */
+int oracle_window_rows(const oracle_problem *pb, int64_t n_rows, const int32_t *row_view, const int32_t *row_seg,
+                       int32_t radius, double *m, int64_t *hit, double *uv)
+{
+    const int n = pb->n_views, L = pb->num_labels;
+    if (n <= 0 || L <= 0 || radius < 0 || radius > 8) return -1;
+    if (pb->depth_ref < -2 || pb->depth_ref >= n) return -1;
+    double *Kinv = (double *)malloc(sizeof(double) * 9 * n);
+    double *Cc = (double *)malloc(sizeof(double) * 3 * n);
+    double *zl = (double *)malloc(sizeof(double) * L);
+    int64_t *row0 = (int64_t *)malloc(sizeof(int64_t) * (n + 1));
+    int32_t **centres = (int32_t **)calloc((size_t)n, sizeof(int32_t *));
+    int rc = 0;
+    if (!Kinv || !Cc || !zl || !row0 || !centres) { rc = -2; goto done; }
+    row0[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        if (inv3(pb->K + 9 * v, Kinv + 9 * v)) { rc = -1; goto done; }
+        camera_centre(pb, v, Cc + 3 * v);
+        row0[v + 1] = row0[v] + pb->num_segments[v];
+    }
+    for (int l = 0; l < L; ++l) {
+        const double frac = L > 1 ? (double)l / (double)(L - 1) : 0.0;
+        zl[l] = 1.0 / (1.0 / pb->z_far + frac * (1.0 / pb->z_near - 1.0 / pb->z_far));
+    }
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int v = row_view[r];
+        if (v < 0 || v >= n || row_seg[r] < 0 || row_seg[r] >= pb->num_segments[v]) { rc = -1; goto done; }
+        if (!centres[v]) {
+            const int64_t S = pb->num_segments[v];
+            int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * S);
+            double *mean = (double *)malloc(sizeof(double) * 3 * S);
+            centres[v] = (int32_t *)malloc(sizeof(int32_t) * 2 * S);
+            if (!cnt || !mean || !centres[v]) { free(cnt); free(mean); rc = -2; goto done; }
+            rc = oracle_segment_stats(pb, v, cnt, centres[v], mean);
+            free(cnt);
+            free(mean);
+            if (rc) goto done;
+        }
+    }
+    {
+        const double scale = (double)(1 << (pb->bit_depth - 8));
+        const int k = pb->chroma_shift;
+        const int taps = (2 * radius + 1) * (2 * radius + 1);
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t r = 0; r < n_rows; ++r) {
+            const int c = row_view[r], s = row_seg[r];
+            const int64_t Wc = pb->width[c], Hc = pb->height[c];
+            const int32_t mx = centres[c][2 * s], my = centres[c][2 * s + 1];
+            /* reference plane */
+            double Cr[3], nr[3];
+            if (pb->depth_ref == -1) {
+                double a[3] = {0, 0, 0};
+                Cr[0] = Cr[1] = Cr[2] = 0.0;
+                for (int v = 0; v < n; ++v)
+                    for (int i = 0; i < 3; ++i) {
+                        Cr[i] += Cc[3 * v + i] / n;
+                        a[i] += pb->R[9 * v + 6 + i] / n;
+                    }
+                const double len = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+                for (int i = 0; i < 3; ++i) nr[i] = a[i] / len;
+            } else {
+                const int rv = pb->depth_ref == -2 ? c : pb->depth_ref;
+                for (int i = 0; i < 3; ++i) { Cr[i] = Cc[3 * rv + i]; nr[i] = pb->R[9 * rv + 6 + i]; }
+            }
+            for (int slot = 0; slot < 2; ++slot) {
+                const int c2 = slot == 0 ? c - 1 : c + 1;
+                for (int l = 0; l < L; ++l) {
+                    const int64_t o = (r * 2 + slot) * L + l;
+                    m[o] = NAN;
+                    hit[o] = -1;
+                    if (uv) uv[2 * o] = uv[2 * o + 1] = NAN;
+                }
+                if (c2 < 0 || c2 >= n || mx < 0) continue;
+                const double *Ki = Kinv + 9 * c, *Rc = pb->R + 9 * c, *C = Cc + 3 * c;
+                double kp[3], d[3];
+                for (int i = 0; i < 3; ++i) kp[i] = Ki[3 * i] * mx + Ki[3 * i + 1] * my + Ki[3 * i + 2];
+                for (int i = 0; i < 3; ++i) d[i] = Rc[i] * kp[0] + Rc[3 + i] * kp[1] + Rc[6 + i] * kp[2];
+                const double nd = nr[0] * d[0] + nr[1] * d[1] + nr[2] * d[2];
+                const double offs = nr[0] * (C[0] - Cr[0]) + nr[1] * (C[1] - Cr[1]) + nr[2] * (C[2] - Cr[2]);
+                const int64_t W2 = pb->width[c2], H2 = pb->height[c2];
+                for (int l = 0; l < L; ++l) {
+                    const int64_t o = (r * 2 + slot) * L + l;
+                    const double tau = (zl[l] - offs) / nd;
+                    if (!(tau > 0.0) || !isfinite(tau)) continue;
+                    const double X[3] = {C[0] + tau * d[0], C[1] + tau * d[1], C[2] + tau * d[2]};
+                    const double *R2 = pb->R + 9 * c2, *t2 = pb->t + 3 * c2, *K2 = pb->K + 9 * c2;
+                    double Xc[3], h[3];
+                    for (int i = 0; i < 3; ++i)
+                        Xc[i] = R2[3 * i] * X[0] + R2[3 * i + 1] * X[1] + R2[3 * i + 2] * X[2] + t2[i];
+                    if (!(Xc[2] > 0.0)) continue;
+                    for (int i = 0; i < 3; ++i) h[i] = K2[3 * i] * Xc[0] + K2[3 * i + 1] * Xc[1] + K2[3 * i + 2] * Xc[2];
+                    if (!(h[2] > 0.0)) continue;
+                    const double u = h[0] / h[2], vv = h[1] / h[2];
+                    if (uv) { uv[2 * o] = u; uv[2 * o + 1] = vv; }
+                    const double fx = floor(u + 0.5), fy = floor(vv + 0.5);
+                    if (!(fx >= 0.0 && fx < (double)W2 && fy >= 0.0 && fy < (double)H2)) continue;
+                    const int64_t tx = (int64_t)fx, ty = (int64_t)fy;
+                    double sum = 0.0;
+                    for (int dy = -radius; dy <= radius; ++dy)
+                        for (int dx = -radius; dx <= radius; ++dx) {
+                            int64_t ax = mx + dx, ay = my + dy, bx = tx + dx, by = ty + dy;
+                            ax = ax < 0 ? 0 : (ax >= Wc ? Wc - 1 : ax);
+                            ay = ay < 0 ? 0 : (ay >= Hc ? Hc - 1 : ay);
+                            bx = bx < 0 ? 0 : (bx >= W2 ? W2 - 1 : bx);
+                            by = by < 0 ? 0 : (by >= H2 ? H2 - 1 : by);
+                            sum += fabs(sample_at(pb, c, 0, ax, ay) - sample_at(pb, c2, 0, bx, by));
+                            sum += fabs(sample_at(pb, c, 1, ax >> k, ay >> k) - sample_at(pb, c2, 1, bx >> k, by >> k));
+                            sum += fabs(sample_at(pb, c, 2, ax >> k, ay >> k) - sample_at(pb, c2, 2, bx >> k, by >> k));
+                        }
+                    m[o] = sum / ((double)taps * scale);
+                    hit[o] = row0[c2] + pb->seg[c2][ty * W2 + tx];
+                }
+            }
+        }
+    }
+done:
+    if (centres) {
+        for (int v = 0; v < n; ++v) free(centres[v]);
+        free(centres);
+    }
+    free(Kinv);
+    free(Cc);
+    free(zl);
+    free(row0);
     return rc;
 }

@@ -15,7 +15,7 @@ struct ViewLayout {
     int64_t row0;
     int32_t n_bands;
     int64_t tex_bytes;
-    size_t off_tex, off_counts, off_offsets, off_bbox, off_pixrec, off_bands;
+    size_t off_tex, off_counts, off_offsets, off_bbox, off_pixrec, off_bands, off_centre, off_mean;
 };
 
 // Byte offsets of everything one problem keeps in its workspace.

@@ -29,6 +29,8 @@ struct ViewDesc {
     int32_t *bbox;             // [4 S] x0, y0, x1, y1 (inclusive)
     float *pixrec;             // [W H][8] x, y, g.p, Y, Cb, Cr, 0, 0 in segment order
     int32_t *band_count;       // [n_bands] segments per band, then band cursors
+    int32_t *centre;           // [2 S] segment centre (centroid rounded half up), -1 if empty
+    float *mean;               // [4 S] mean Y, Cb, Cr of the segment, 0
     int32_t n_bands;
     int32_t front_all;         // every pixel at every label lies in front of this camera
     int32_t n_targets;
@@ -97,5 +99,12 @@ hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t
 hipError_t launch_compact_tasks(const Problem *dprob, const Task *all, int64_t n_all, const uint8_t *mask,
                                 Task *out, int32_t *n_out, hipStream_t s);
 hipError_t launch_copy_rows(const void *src, void *dst, int64_t bytes, hipStream_t s);
+// Per-segment count, centre and mean colour (needs the segment index).
+hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, hipStream_t s);
+// Window matching core towards views c - 1 and c + 1 for every task.
+hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
+                         float *m_out, int32_t *hit_out, hipStream_t s);
+hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32_t *hit, const int32_t *labelling,
+                                float K, float *out, hipStream_t s);
 
 }  // namespace ivde

@@ -1,0 +1,90 @@
+// The paper's own data term (Sec. III-C, Eqs. (4) and (5)): the window
+// matching core at each segment centre towards the neighbouring views, and
+// the inter-view cost under a labelling.
+#include <hip/hip_runtime.h>
+
+#include "../../include/ivde.h"
+#include "host_common.h"
+#include "ivde_internal.h"
+
+using namespace ivde;
+
+namespace {
+
+ivde_options window_options()
+{
+    ivde_options o{};
+    o.sampling = IVDE_NEAREST;
+    o.cost_dtype = IVDE_F32;
+    o.targets = IVDE_TARGETS_NEAREST_LR;
+    o.labels_per_lane = 1;     // one 64-label block per wave
+    o.waves_per_group = 4;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+ivde_status ivde_window_cost_size(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
+                                  const ivde_label_range *labels, int32_t bit_depth, size_t *out_bytes,
+                                  size_t *workspace_bytes)
+{
+    const ivde_options o = window_options();
+    ivde_status st = validate_problem(n_views, cams, nullptr, segs, labels, &o, false);
+    if (st != IVDE_OK) return st;
+    if (bit_depth < 8 || bit_depth > 16) {
+        set_error("bit_depth must be 8..16");
+        return IVDE_EINVAL;
+    }
+    const Layout ly = plan_layout(n_views, cams, segs, labels, &o, bit_depth);
+    if (out_bytes) *out_bytes = (size_t)ly.total_rows * 2 * ly.L * 4;
+    if (workspace_bytes) *workspace_bytes = ly.workspace_bytes;
+    return IVDE_OK;
+}
+
+ivde_status ivde_window_cost(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                             const ivde_segmentation *segs, const ivde_label_range *labels, int32_t radius,
+                             void *workspace, size_t workspace_bytes, float *m_out, int32_t *hit_out,
+                             ivde_stream stream)
+{
+    const ivde_options o = window_options();
+    ivde_status st = validate_problem(n_views, cams, views, segs, labels, &o, true);
+    if (st != IVDE_OK) return st;
+    if (radius < 0 || radius > 8 || !m_out || !hit_out) {
+        set_error("window_cost: radius must be 0..8 and both outputs given");
+        return IVDE_EINVAL;
+    }
+    const Layout ly = plan_layout(n_views, cams, segs, labels, &o, views[0].bit_depth);
+    if (ly.total_rows >= ((int64_t)1 << 31)) {
+        set_error("window_cost: too many segments");
+        return IVDE_EINVAL;
+    }
+    if ((st = check_workspace(workspace, workspace_bytes, ly.workspace_bytes)) != IVDE_OK) return st;
+    if ((st = check_tex_limits(ly)) != IVDE_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
+    st = enqueue_front(n_views, cams, views, segs, labels, &o, ly, ws, nullptr, 0, tasks, s);
+    if (st != IVDE_OK) return st;
+    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    hipError_t e = launch_segment_stats(dp, extents_of(ly), s);
+    if (e != hipSuccess) return hip_fail(e, "segment statistics");
+    e = launch_window(dp, tasks, ly.n_tasks, radius, ly.tex_f32, m_out, hit_out, s);
+    if (e != hipSuccess) return hip_fail(e, "window matching");
+    return IVDE_OK;
+}
+
+ivde_status ivde_window_energy(int64_t rows, int32_t num_labels, const float *m, const int32_t *hit,
+                               const int32_t *labelling, float K, float *out, ivde_stream stream)
+{
+    if (rows < 0 || num_labels < 1 || (rows > 0 && (!m || !hit || !labelling || !out))) {
+        set_error("window_energy: rows >= 0, num_labels >= 1 and non-null buffers are required");
+        return IVDE_EINVAL;
+    }
+    hipError_t e = launch_window_energy(rows, num_labels, m, hit, labelling, K, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "window energy");
+    return IVDE_OK;
+}
+
+}  // extern "C"

@@ -89,6 +89,9 @@ SIGNATURES = {
     "ivde_rig_reset": (_I32, [_P, _I32]),
     "ivde_server_destroy": (None, [_P]),
     "ivde_autotune": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _I32, _P, _P, _I32]),
+    "ivde_window_cost_size": (_I32, [_I32, _P, _P, _P, _I32, _P, _P]),
+    "ivde_window_cost": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
+    "ivde_window_energy": (_I32, [_I64, _I32, _P, _P, _P, ctypes.c_float, _P, _P]),
     "ivde_status_string": (ctypes.c_char_p, [_I32]),
     "ivde_last_error": (ctypes.c_char_p, []),
     "ivde_version": (ctypes.c_char_p, []),
@@ -428,3 +431,32 @@ def autotune(dv: DeviceViews, lr: LabelRange, opt: Options, reps=2, stream=None)
                             _stream_ptr(stream), int(reps), ctypes.byref(best), times, len(AUTOTUNE_SHAPES)))
     table = {s: (float(t) if t >= 0 else None) for s, t in zip(AUTOTUNE_SHAPES, times)}
     return best, table
+
+
+# ---------------------------------------------------------------- the paper's window term
+def window_cost(dv: DeviceViews, lr: LabelRange, radius=1, stream=None):
+    """ivde_window_cost: (m [rows, 2, L] float32, hit [rows, 2, L] int32)."""
+    torch = _torch()
+    lib = load()
+    ob, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib.ivde_window_cost_size(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), dv.bit_depth, ctypes.byref(ob),
+                                    ctypes.byref(wb)))
+    ws = alloc_bytes(wb.value)
+    L = lr.num_labels
+    m = torch.empty((dv.rows, 2, L), dtype=torch.float32, device="cuda")
+    hit = torch.empty((dv.rows, 2, L), dtype=torch.int32, device="cuda")
+    check(lib.ivde_window_cost(dv.n, dv.c_cams, dv.c_images, dv.c_segs, ctypes.byref(lr), int(radius),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(m.data_ptr()),
+                               ctypes.c_void_p(hit.data_ptr()), _stream_ptr(stream)))
+    return m, hit, ws
+
+
+def window_energy(m, hit, labelling, K=30.0, stream=None):
+    """ivde_window_energy: [rows, L] float32."""
+    torch = _torch()
+    rows, _, L = m.shape
+    out = torch.empty((rows, L), dtype=torch.float32, device=m.device)
+    check(load().ivde_window_energy(rows, L, ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(hit.data_ptr()),
+                                    ctypes.c_void_p(labelling.data_ptr()), float(K), ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)))
+    return out
