@@ -231,6 +231,7 @@ typedef struct {
     int32_t rig_id;
     int32_t status;           /* IVDE_OK or the failure */
     int64_t rows_recomputed;  /* changed segments swept */
+    int64_t rows_from_iframe; /* rule mode: unchanged rows that adopted the I frame's result */
     int64_t rows_total;
     double submit_us;         /* host steady-clock times, microseconds */
     double start_us;          /* admitted and enqueued */
@@ -244,6 +245,14 @@ typedef struct {
  * while a slot and arena memory are free, and run concurrently on separate
  * streams; frames of one rig run in submission order. */
 ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out);
+
+/* Arena bytes a rig holds while registered (resident) and one of its
+ * frames holds while admitted (per_request), for images of bit_depth bits:
+ * an arena of resident + k per_request bytes runs k of its frames at once. */
+ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams,
+                                  const ivde_segmentation *segs, const ivde_label_range *labels,
+                                  const ivde_options *opt, int32_t bit_depth, size_t *resident,
+                                  size_t *per_request);
 
 /* Registers a rig: its cameras, fixed segmentation (device maps, read
  * during this call only), label range and options.  Reserves the rig's
@@ -262,6 +271,19 @@ ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_came
 ivde_status ivde_stream_submit(ivde_server *srv, int32_t rig_id, const ivde_image *views,
                                const uint8_t *changed_mask, void *cost_out, int32_t *label_out,
                                uint64_t *ticket);
+/* Submits one frame whose changed segments the server decides itself by
+ * the paper's temporal rule (Sec. III-E): with the frame's mean Y, Cb, Cr
+ * per segment (same segment id under the rig's fixed segmentation), a row
+ * adopts the latest I frame's result when every component moved by less
+ * than t_i since that frame, else keeps the previous frame's row when every
+ * component moved by less than t_p, else it is recomputed.  Thresholds are
+ * in 8-bit code values (scaled by 2^(b-8)); defaults t_p = 3, t_i = 1.
+ * iframe != 0 (or a rig without an I frame yet) recomputes every row and
+ * makes this frame the I frame. */
+ivde_status ivde_stream_submit_rule(ivde_server *srv, int32_t rig_id, const ivde_image *views,
+                                    int32_t iframe, void *cost_out, int32_t *label_out,
+                                    uint64_t *ticket);
+ivde_status ivde_rig_set_temporal(ivde_server *srv, int32_t rig_id, float t_p, float t_i);
 /* IVDE_EBUSY while pending; otherwise fills `st` and forgets the ticket. */
 ivde_status ivde_stream_poll(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st);
 ivde_status ivde_stream_wait(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st);
@@ -307,6 +329,27 @@ ivde_status ivde_window_cost(int32_t n_views, const ivde_camera *cams, const ivd
 ivde_status ivde_window_energy(int64_t rows, int32_t num_labels, const float *m,
                                const int32_t *hit, const int32_t *labelling, float K,
                                float *out, ivde_stream stream);
+
+/* ---------------------------------------------------------------- segment statistics, temporal rule */
+
+ivde_status ivde_segment_stats_size(int32_t n_views, const ivde_camera *cams,
+                                    const ivde_segmentation *segs, int32_t bit_depth,
+                                    size_t *workspace_bytes);
+/* Per segment, rows ordered as in ivde_cost_volume: pixel count
+ * (device int32 [rows]), centre (the centroid rounded half up, Sec. III-C's
+ * mu_s; int32 [rows][2], -1 for an empty segment) and mean colour (float
+ * [rows][4]: Y, Cb, Cr, 0; Sec. III-D and III-E).  Any output may be NULL. */
+ivde_status ivde_segment_stats(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                               const ivde_segmentation *segs, void *workspace,
+                               size_t workspace_bytes, int32_t *count_out, int32_t *centre_out,
+                               float *mean_out, ivde_stream stream);
+/* The temporal rule of Sec. III-E on mean colours ([rows][4] as above):
+ * source_out[r] = 2 when every component moved by less than t_i against
+ * mean_iframe (skipped if NULL), else 1 when by less than t_p against
+ * mean_prev, else 0 (recompute).  Thresholds in 8-bit code values. */
+ivde_status ivde_temporal_rule(int64_t rows, const float *mean, const float *mean_prev,
+                               const float *mean_iframe, float t_p, float t_i, int32_t bit_depth,
+                               uint8_t *source_out, ivde_stream stream);
 
 /* ---------------------------------------------------------------- tuning */
 

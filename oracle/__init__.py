@@ -302,3 +302,42 @@ def window_energy(m, hit, labelling, K=30.0):
     same = d_hit == np.arange(L)[None, None, :]
     E += np.where(ok & same, np.minimum(0.0, m - K), 0.0).sum(axis=1)
     return E
+
+
+def temporal_rule(mean, mean_prev, mean_iframe=None, t_p=3.0, t_i=1.0, bit_depth=8):
+    """Sec. III-E: a segment is unchanged when every component of its mean
+    Y, Cb, Cr moved by less than T_I against the I frame (source 2: adopt the
+    I frame's result) or by less than T_P against the previous frame (source
+    1: keep the previous result); else it is recomputed (0).  Thresholds are
+    in 8-bit code values, scaled by 2^(b - 8).  The stricter I-frame test is
+    taken first."""
+    s = float(1 << (bit_depth - 8))
+    mean = np.asarray(mean, np.float64)[:, :3]
+    dp = np.abs(mean - np.asarray(mean_prev, np.float64)[:, :3]).max(axis=1)
+    src = np.where(dp < t_p * s, 1, 0)
+    if mean_iframe is not None:
+        di = np.abs(mean - np.asarray(mean_iframe, np.float64)[:, :3]).max(axis=1)
+        src = np.where(di < t_i * s, 2, src)
+    return src.astype(np.uint8)
+
+
+def served_rule(prev, iframe_cost, pb: Problem, source):
+    """One temporally updated frame: rows with source 0 are recomputed, 1
+    keep prev, 2 take the I frame's row (Sec. III-E: unchanged segments adopt
+    the earlier depth)."""
+    out = np.array(prev, np.float64, copy=True)
+    source = np.asarray(source)
+    out[source == 2] = np.asarray(iframe_cost, np.float64)[source == 2]
+    idx = np.nonzero(source == 0)[0]
+    if len(idx):
+        off = pb.row_offsets()
+        views = (np.searchsorted(off, idx, side="right") - 1).astype(np.int32)
+        out[idx] = cost_rows(pb, views, (idx - off[views]).astype(np.int32))
+    return out
+
+
+def all_segment_stats(pb: Problem):
+    """Counts, centres and mean colours of every row, in volume order."""
+    parts = [segment_stats(pb, v) for v in range(pb.n_views)]
+    return (np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
+            np.concatenate([p[2] for p in parts]))

@@ -230,8 +230,6 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
         vl.off_bbox = take(sizeof(int32_t) * 4 * S);
         vl.off_pixrec = take(sizeof(float) * 8 * (size_t)W * H);
         vl.off_bands = take(sizeof(int32_t) * 2 * vl.n_bands);
-        vl.off_centre = take(sizeof(int32_t) * 2 * S);
-        vl.off_mean = take(sizeof(float) * 4 * S);
         ly.max_w = W > ly.max_w ? W : ly.max_w;
         ly.max_h = H > ly.max_h ? H : ly.max_h;
         ly.max_s = S > ly.max_s ? S : ly.max_s;
@@ -239,6 +237,8 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
     }
     ly.n_tasks = ly.total_rows * ly.n_lblocks;
     ly.off_tasks = take(sizeof(Task) * (size_t)ly.n_tasks);
+    ly.off_centre = take(sizeof(int32_t) * 2 * (size_t)ly.total_rows);
+    ly.off_mean = take(sizeof(float) * 4 * (size_t)ly.total_rows);
     ly.workspace_bytes = off;
     ly.cost_bytes = (size_t)ly.total_rows * ly.L * (ly.f16 ? 2 : 4);
     return ly;
@@ -334,8 +334,8 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
         d.bbox = reinterpret_cast<int32_t *>(ws_base + vl.off_bbox);
         d.pixrec = reinterpret_cast<float *>(ws_base + vl.off_pixrec);
         d.band_count = reinterpret_cast<int32_t *>(ws_base + vl.off_bands);
-        d.centre = reinterpret_cast<int32_t *>(ws_base + vl.off_centre);
-        d.mean = reinterpret_cast<float *>(ws_base + vl.off_mean);
+        d.centre = reinterpret_cast<int32_t *>(ws_base + ly.off_centre) + 2 * vl.row0;
+        d.mean = reinterpret_cast<float *>(ws_base + ly.off_mean) + 4 * vl.row0;
         d.n_bands = vl.n_bands;
         d.n_targets = 0;
         for (int c2 = 0; c2 < n; ++c2)

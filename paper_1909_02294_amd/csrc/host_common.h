@@ -15,7 +15,7 @@ struct ViewLayout {
     int64_t row0;
     int32_t n_bands;
     int64_t tex_bytes;
-    size_t off_tex, off_counts, off_offsets, off_bbox, off_pixrec, off_bands, off_centre, off_mean;
+    size_t off_tex, off_counts, off_offsets, off_bbox, off_pixrec, off_bands;
 };
 
 // Byte offsets of everything one problem keeps in its workspace.
@@ -24,6 +24,7 @@ struct Layout {
     int max_w, max_h, max_s, max_bands;
     int64_t total_rows, n_tasks;
     size_t off_problem, off_views, off_pairs, off_sigma, off_flag, off_tasks;
+    size_t off_centre, off_mean;       // [rows][2] int32 and [rows][4] float over all views
     size_t workspace_bytes, cost_bytes;
     ViewLayout views[kMaxViews];
 };

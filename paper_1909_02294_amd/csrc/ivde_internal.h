@@ -99,8 +99,13 @@ hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t
 hipError_t launch_compact_tasks(const Problem *dprob, const Task *all, int64_t n_all, const uint8_t *mask,
                                 Task *out, int32_t *n_out, hipStream_t s);
 hipError_t launch_copy_rows(const void *src, void *dst, int64_t bytes, hipStream_t s);
-// Per-segment count, centre and mean colour (needs the segment index).
-hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, hipStream_t s);
+// Per-segment count, centre and mean colour (needs the segment index);
+// count_flat [rows] may be null.
+hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, int32_t *count_flat, hipStream_t s);
+hipError_t launch_temporal_rule(int64_t rows, const float *mean, const float *prev, const float *iframe, float t_p,
+                                float t_i, uint8_t *source, uint8_t *changed, int32_t *counts, hipStream_t s);
+hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *source, int which, const void *from,
+                                  void *to, hipStream_t s);
 // Window matching core towards views c - 1 and c + 1 for every task.
 hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
                          float *m_out, int32_t *hit_out, hipStream_t s);

@@ -629,7 +629,7 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restr
 // Count, centre (centroid rounded half up) and mean colour of every segment,
 // one wave per segment over its pixel records; integer sums, so the result
 // does not depend on the summation order.
-__global__ void k_seg_stats(const Problem *__restrict__ P)
+__global__ void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__ count_flat)
 {
     const ViewDesc &v = P->views[blockIdx.y];
     const int lane = lane_id();
@@ -653,6 +653,7 @@ __global__ void k_seg_stats(const Problem *__restrict__ P)
     }
     if (lane == 0) {
         const int n = p1 - p0;
+        if (count_flat) count_flat[v.row0 + s] = n;
         if (n == 0) {
             v.centre[2 * s] = v.centre[2 * s + 1] = -1;
             for (int c = 0; c < 4; ++c) v.mean[4 * s + c] = 0.f;
@@ -777,6 +778,54 @@ __global__ void k_window_energy(int64_t rows, int L, const float *__restrict__ m
     out[i] = e;
 }
 
+// ------------------------------------------------------------------ temporal rule
+// Sec. III-E: a segment is unchanged when every mean colour component moved
+// by less than t_i since the I frame (it then adopts the I frame's result,
+// source 2) or by less than t_p since the previous frame (source 1);
+// otherwise it is recomputed (source 0).  The stricter I-frame test is taken
+// first.  counts: [0] recomputed, [1] from the I frame, [2] from the previous
+// frame.
+__global__ void k_temporal_rule(int64_t rows, const float *__restrict__ mean, const float *__restrict__ prev,
+                                const float *__restrict__ iframe, float t_p, float t_i, uint8_t *__restrict__ source,
+                                uint8_t *__restrict__ changed, int32_t *__restrict__ counts)
+{
+    const int lane = lane_id();
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int src = -1;
+    if (r < rows) {
+        const float4 m = reinterpret_cast<const float4 *>(mean)[r];
+        const float4 p = reinterpret_cast<const float4 *>(prev)[r];
+        const float dp = fmaxf(fabsf(m.x - p.x), fmaxf(fabsf(m.y - p.y), fabsf(m.z - p.z)));
+        bool from_i = false;
+        if (iframe) {
+            const float4 q = reinterpret_cast<const float4 *>(iframe)[r];
+            const float di = fmaxf(fabsf(m.x - q.x), fmaxf(fabsf(m.y - q.y), fabsf(m.z - q.z)));
+            from_i = di < t_i;
+        }
+        src = from_i ? 2 : (dp < t_p ? 1 : 0);
+        source[r] = (uint8_t)src;
+        if (changed) changed[r] = src == 0;
+    }
+    if (counts) {
+        for (int k = 0; k < 3; ++k) {
+            const uint64_t b = __ballot(src == k);
+            if (lane == 0 && b) atomicAdd(&counts[k], __builtin_popcountll(b));
+        }
+    }
+}
+
+// Copy the rows whose source is `which` from one volume to another.
+__global__ void k_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *__restrict__ source, int which,
+                                  const uint8_t *__restrict__ from, uint8_t *__restrict__ to)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one 4-byte word per thread
+    const int words = row_bytes / 4;
+    if (i >= rows * words) return;
+    const int64_t r = i / words;
+    if (source[r] != which) return;
+    reinterpret_cast<uint32_t *>(to)[i] = reinterpret_cast<const uint32_t *>(from)[i];
+}
+
 // ------------------------------------------------------------------ argmin
 template <bool F16>
 __global__ void k_argmin(const void *__restrict__ cost, int64_t rows, int L, int32_t *__restrict__ out)
@@ -826,6 +875,12 @@ __global__ void k_compact_tasks(const Problem *__restrict__ P, const Task *__res
     if (lane == 0 && bal) base = atomicAdd(n_out, __builtin_popcountll(bal));
     base = __shfl(base, 0);
     if (keep) out[base + __builtin_popcountll(bal & ((1ull << lane) - 1))] = t;
+}
+
+__global__ void k_copy_words(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int64_t n4)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 __global__ void k_copy_bytes(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16)
@@ -1016,19 +1071,51 @@ hipError_t launch_compact_tasks(const Problem *dprob, const Task *all, int64_t n
 hipError_t launch_copy_rows(const void *src, void *dst, int64_t bytes, hipStream_t s)
 {
     if (bytes <= 0) return hipSuccess;
-    if (bytes % 16) return hipErrorInvalidValue;
-    const int64_t n16 = bytes / 16;
-    int64_t blocks = (n16 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint4 *>(src),
-                       static_cast<uint4 *>(dst), n16);
+    if (bytes % 4) return hipErrorInvalidValue;
+    if (bytes % 16 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0) {
+        const int64_t n16 = bytes / 16;
+        int64_t blocks = (n16 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint4 *>(src),
+                           static_cast<uint4 *>(dst), n16);
+    } else {
+        const int64_t n4 = bytes / 4;
+        int64_t blocks = (n4 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint32_t *>(src),
+                           static_cast<uint32_t *>(dst), n4);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, hipStream_t s)
+hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, int32_t *count_flat, hipStream_t s)
 {
     hipLaunchKernelGGL(k_seg_stats, dim3((unsigned)((ext.max_s + 3) / 4), (unsigned)ext.n_views), dim3(256), 0, s,
-                       dprob);
+                       dprob, count_flat);
+    return hipGetLastError();
+}
+
+hipError_t launch_temporal_rule(int64_t rows, const float *mean, const float *prev, const float *iframe, float t_p,
+                                float t_i, uint8_t *source, uint8_t *changed, int32_t *counts, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    const int64_t blocks = (rows + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_temporal_rule, dim3((unsigned)blocks), dim3(256), 0, s, rows, mean, prev, iframe, t_p, t_i,
+                       source, changed, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *source, int which, const void *from,
+                                  void *to, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    if (row_bytes % 4) return hipErrorInvalidValue;
+    const int64_t n = rows * (row_bytes / 4);
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy_rows_where, dim3((unsigned)blocks), dim3(256), 0, s, rows, row_bytes, source, which,
+                       static_cast<const uint8_t *>(from), static_cast<uint8_t *>(to));
     return hipGetLastError();
 }
 

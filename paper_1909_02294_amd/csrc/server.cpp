@@ -101,10 +101,15 @@ struct Rig {
     ivde_label_range labels{};
     ivde_options opt{};
     Layout ly{};                           // rows, tasks and cost layout (bit-depth independent)
-    size_t res_off = 0, res_bytes = 0;     // resident: seg maps + cost volume
-    char *cost = nullptr;                  // resident cost volume
+    size_t res_off = 0, res_bytes = 0;     // resident: seg maps, volumes, mean colours
+    char *cost = nullptr;                  // resident cost volume (the latest frame)
+    char *cost_i = nullptr;                // the latest I frame's volume
+    float *mean_prev = nullptr;            // [rows][4] mean colours of the latest frame
+    float *mean_i = nullptr;               // [rows][4] mean colours of the latest I frame
     size_t cost_bytes = 0;
+    float t_p = 3.f, t_i = 1.f;            // temporal thresholds in 8-bit code values
     bool has_prev = false;                 // resident volume holds a frame
+    bool has_i = false;                    // cost_i and mean_i hold an I frame
     hipEvent_t last = nullptr;             // completion of the rig's latest enqueued frame
     bool last_valid = false;
     int pending = 0;                       // requests queued or in flight
@@ -115,6 +120,8 @@ struct Request {
     int rig = -1;
     std::vector<ivde_image> views;
     const uint8_t *mask = nullptr;
+    bool rule = false;                     // derive the mask by the temporal rule
+    bool iframe = false;                   // rule mode: compute every row and make this the I frame
     void *cost_out = nullptr;
     int32_t *label_out = nullptr;
     ivde_frame_stats st{};
@@ -125,15 +132,31 @@ struct Request {
     bool done = false;
 };
 
+// workspace, counters, the compacted task list, and the rule's per-row
+// source and changed flags
+// A rig's resident state: its segment maps, the latest and the I-frame
+// cost volumes, and two mean-colour tables.
+size_t resident_bytes(int n_views, const ivde_camera *cams, const Layout &ly, size_t *seg_off, size_t *seg_total)
+{
+    size_t seg_bytes = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (seg_off) seg_off[v] = seg_bytes;
+        seg_bytes = align_up(seg_bytes + sizeof(int32_t) * (size_t)cams[v].width * cams[v].height, 256);
+    }
+    if (seg_total) *seg_total = seg_bytes;
+    return seg_bytes + 2 * align_up(ly.cost_bytes, 256) + 2 * align_up((size_t)ly.total_rows * 16, 256);
+}
+
 size_t working_set(const Layout &ly)
 {
-    return align_up(ly.workspace_bytes, 256) + 256 + sizeof(Task) * (size_t)ly.n_tasks;
+    return align_up(ly.workspace_bytes, 256) + 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256) +
+           2 * align_up((size_t)ly.total_rows, 256);
 }
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    int32_t *count_host = nullptr;         // pinned: compacted task count
+    int32_t *count_host = nullptr;         // pinned [8]: compacted tasks, cursor, rule counts
     uint64_t ticket = 0;
     bool busy = false;
 };
@@ -246,17 +269,46 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
                                    ws, rig.cost, 0, tasks, s);
     if (st != IVDE_OK) return st;
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
-    const bool full = !r.mask || !rig.has_prev;
     const int bil = rig.opt.sampling == IVDE_BILINEAR;
-    int32_t *counters = reinterpret_cast<int32_t *>(ws + align_up(ly.workspace_bytes, 256));
-    Task *changed = reinterpret_cast<Task *>(ws + align_up(ly.workspace_bytes, 256) + 256);
+    char *extra = ws + align_up(ly.workspace_bytes, 256);
+    int32_t *counters = reinterpret_cast<int32_t *>(extra);   // [0] tasks kept, [1] cursor, [2..4] rule counts
+    Task *changed = reinterpret_cast<Task *>(extra + 256);
+    uint8_t *source = reinterpret_cast<uint8_t *>(extra + 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256));
+    uint8_t *rule_mask = source + align_up((size_t)ly.total_rows, 256);
+    float *mean = reinterpret_cast<float *>(ws + ly.off_mean);
+    const size_t mean_bytes = (size_t)ly.total_rows * 16;
+    const bool full = r.rule ? (r.iframe || !rig.has_prev || !rig.has_i) : (!r.mask || !rig.has_prev);
+    const uint8_t *mask = r.mask;
+    for (int k = 0; k < 8; ++k) sl.count_host[k] = 0;
+    if (r.rule && (e = launch_segment_stats(dp, extents_of(ly), nullptr, s)) != hipSuccess)
+        return hip_fail(e, "serve segment statistics");
     if (full) {
         if ((e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16, ly.wpg, s)) != hipSuccess)
             return hip_fail(e, "serve sweep");
-        *sl.count_host = (int32_t)ly.n_tasks;
+        sl.count_host[0] = (int32_t)ly.n_tasks;
+        if (r.rule) {
+            // this frame becomes the I frame of the rule
+            if ((e = launch_copy_rows(rig.cost, rig.cost_i, (int64_t)rig.cost_bytes, s)) != hipSuccess ||
+                (e = launch_copy_rows(mean, rig.mean_i, (int64_t)mean_bytes, s)) != hipSuccess ||
+                (e = launch_copy_rows(mean, rig.mean_prev, (int64_t)mean_bytes, s)) != hipSuccess)
+                return hip_fail(e, "serve I frame state");
+            rig.has_i = true;
+        }
     } else {
-        if ((e = launch_fill_i32(counters, 0, 2, s)) != hipSuccess) return hip_fail(e, "serve counters");
-        if ((e = launch_compact_tasks(dp, tasks, ly.n_tasks, r.mask, changed, counters, s)) != hipSuccess)
+        if ((e = launch_fill_i32(counters, 0, 5, s)) != hipSuccess) return hip_fail(e, "serve counters");
+        if (r.rule) {
+            const float scale = (float)(1 << (r.views[0].bit_depth - 8));
+            if ((e = launch_temporal_rule(ly.total_rows, mean, rig.mean_prev, rig.mean_i, rig.t_p * scale,
+                                          rig.t_i * scale, source, rule_mask, counters + 2, s)) != hipSuccess)
+                return hip_fail(e, "serve temporal rule");
+            // rows unchanged since the I frame adopt its result; rows
+            // unchanged since the previous frame keep the resident row
+            if ((e = launch_copy_rows_where(ly.total_rows, ly.L * (ly.f16 ? 2 : 4), source, 2, rig.cost_i, rig.cost,
+                                            s)) != hipSuccess)
+                return hip_fail(e, "serve I-frame rows");
+            mask = rule_mask;
+        }
+        if ((e = launch_compact_tasks(dp, tasks, ly.n_tasks, mask, changed, counters, s)) != hipSuccess)
             return hip_fail(e, "serve compaction");
         int per_cu = 0, cus = 0;
         if ((e = sweep_persistent_occupancy(ly.J, bil, ly.tex_f32, ly.f16, ly.wpg, &per_cu)) != hipSuccess)
@@ -266,8 +318,11 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
         if ((e = launch_sweep_persistent(dp, changed, counters, counters + 1, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16,
                                          ly.wpg, std::max(1, per_cu) * std::max(1, cus), s)) != hipSuccess)
             return hip_fail(e, "serve sweep");
-        if ((e = hipMemcpyAsync(sl.count_host, counters, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        if ((e = hipMemcpyAsync(sl.count_host, counters, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
             return hip_fail(e, "serve count");
+        if (r.rule && (e = launch_copy_rows(mean, rig.mean_prev, (int64_t)mean_bytes, s)) != hipSuccess)
+            return hip_fail(e, "serve mean colours");
     }
     if (r.label_out &&
         (e = launch_argmin(rig.cost, ly.f16, ly.total_rows, rig.labels.num_labels, r.label_out, s)) != hipSuccess)
@@ -291,7 +346,10 @@ void ivde_server::complete(Slot &sl)
         const hipError_t q = hipEventQuery(sl.done);
         if (q != hipSuccess) r.st.status = IVDE_EHIP;
     }
-    if (r.st.status == IVDE_OK) r.st.rows_recomputed = (int64_t)*sl.count_host / std::max(1, r.ly.n_lblocks);
+    if (r.st.status == IVDE_OK) {
+        r.st.rows_recomputed = (int64_t)sl.count_host[0] / std::max(1, r.ly.n_lblocks);
+        r.st.rows_from_iframe = sl.count_host[4];   // rule counts: [2] recompute, [3] keep, [4] I frame
+    }
     arena.release(r.work_off, r.work_bytes);
     sl.busy = false;
     r.done = true;
@@ -337,12 +395,12 @@ ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out)
     for (Slot &sl : s->slots) {
         if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipHostMalloc(reinterpret_cast<void **>(&sl.count_host), sizeof(int32_t), hipHostMallocDefault)) !=
+            (e = hipHostMalloc(reinterpret_cast<void **>(&sl.count_host), 8 * sizeof(int32_t), hipHostMallocDefault)) !=
                 hipSuccess) {
             ivde_server_destroy(s);
             return hip_fail(e, "server resources");
         }
-        *sl.count_host = 0;
+        for (int k = 0; k < 8; ++k) sl.count_host[k] = 0;
     }
     s->thread = std::thread([s] { s->run(); });
     *out = s;
@@ -372,13 +430,10 @@ ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_came
     rig.ly = plan_layout(n_views, cams, segs, labels, &rig.opt, 16);
     if ((st = check_tex_limits(rig.ly)) != IVDE_OK) return st;
     rig.cost_bytes = rig.ly.cost_bytes;
-    size_t seg_bytes = 0;
     std::vector<size_t> seg_off(n_views);
-    for (int v = 0; v < n_views; ++v) {
-        seg_off[v] = seg_bytes;
-        seg_bytes = align_up(seg_bytes + sizeof(int32_t) * (size_t)cams[v].width * cams[v].height, 256);
-    }
-    rig.res_bytes = seg_bytes + align_up(rig.cost_bytes, 256);
+    size_t seg_bytes = 0;
+    rig.res_bytes = resident_bytes(n_views, cams, rig.ly, seg_off.data(), &seg_bytes);
+    const size_t mean_bytes = align_up((size_t)rig.ly.total_rows * 16, 256);
     std::lock_guard<std::mutex> lk(srv->mu);
     if (!srv->arena.alloc(rig.res_bytes, &rig.res_off)) {
         set_error("rig_register: the rig's resident state (%zu bytes) does not fit the arena", rig.res_bytes);
@@ -386,6 +441,9 @@ ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_came
     }
     char *base = srv->arena_base + rig.res_off;
     rig.cost = base + seg_bytes;
+    rig.cost_i = rig.cost + align_up(rig.cost_bytes, 256);
+    rig.mean_prev = reinterpret_cast<float *>(rig.cost_i + align_up(rig.cost_bytes, 256));
+    rig.mean_i = reinterpret_cast<float *>(reinterpret_cast<char *>(rig.mean_prev) + mean_bytes);
     rig.segs.resize(n_views);
     hipError_t e = hipSuccess;
     for (int v = 0; v < n_views && e == hipSuccess; ++v) {
@@ -407,8 +465,59 @@ ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_came
     return IVDE_OK;
 }
 
+static ivde_status submit(ivde_server *srv, int32_t rig_id, const ivde_image *views, const uint8_t *changed_mask,
+                          bool rule, bool iframe, void *cost_out, int32_t *label_out, uint64_t *ticket);
+
+ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
+                                  const ivde_label_range *labels, const ivde_options *opt, int32_t bit_depth,
+                                  size_t *resident, size_t *per_request)
+{
+    ivde_status st = validate_problem(n_views, cams, nullptr, segs, labels, opt, false);
+    if (st != IVDE_OK) return st;
+    if (bit_depth < 8 || bit_depth > 16) {
+        set_error("bit_depth must be 8..16");
+        return IVDE_EINVAL;
+    }
+    ivde_options o = *opt;
+    o.sweep_events[0] = o.sweep_events[1] = nullptr;
+    const Layout ly = plan_layout(n_views, cams, segs, labels, &o, bit_depth);
+    if (resident) *resident = align_up(resident_bytes(n_views, cams, ly, nullptr, nullptr), 256);
+    if (per_request) *per_request = align_up(working_set(ly), 256);
+    return IVDE_OK;
+}
+
 ivde_status ivde_stream_submit(ivde_server *srv, int32_t rig_id, const ivde_image *views, const uint8_t *changed_mask,
                                void *cost_out, int32_t *label_out, uint64_t *ticket)
+{
+    return submit(srv, rig_id, views, changed_mask, false, false, cost_out, label_out, ticket);
+}
+
+ivde_status ivde_stream_submit_rule(ivde_server *srv, int32_t rig_id, const ivde_image *views, int32_t iframe,
+                                    void *cost_out, int32_t *label_out, uint64_t *ticket)
+{
+    return submit(srv, rig_id, views, nullptr, true, iframe != 0, cost_out, label_out, ticket);
+}
+
+ivde_status ivde_rig_set_temporal(ivde_server *srv, int32_t rig_id, float t_p, float t_i)
+{
+    if (!srv || !(t_p >= 0.f) || !(t_i >= 0.f)) {
+        set_error("rig_set_temporal: thresholds must be >= 0");
+        return IVDE_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (rig_id < 0 || rig_id >= (int)srv->rigs.size()) {
+        set_error("rig_set_temporal: unknown rig");
+        return IVDE_ENOTFOUND;
+    }
+    srv->rigs[rig_id].t_p = t_p;
+    srv->rigs[rig_id].t_i = t_i;
+    return IVDE_OK;
+}
+
+}  // extern "C"
+
+static ivde_status submit(ivde_server *srv, int32_t rig_id, const ivde_image *views, const uint8_t *changed_mask,
+                          bool rule, bool iframe, void *cost_out, int32_t *label_out, uint64_t *ticket)
 {
     if (!srv || !views || !ticket) {
         set_error("stream_submit: null argument");
@@ -434,6 +543,8 @@ ivde_status ivde_stream_submit(ivde_server *srv, int32_t rig_id, const ivde_imag
     r.rig = rig_id;
     r.views.assign(views, views + rig.n);
     r.mask = changed_mask;
+    r.rule = rule;
+    r.iframe = iframe;
     r.cost_out = cost_out;
     r.label_out = label_out;
     r.st.ticket = r.ticket;
@@ -447,6 +558,8 @@ ivde_status ivde_stream_submit(ivde_server *srv, int32_t rig_id, const ivde_imag
     srv->cv_sched.notify_one();
     return IVDE_OK;
 }
+
+extern "C" {
 
 ivde_status ivde_stream_poll(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st)
 {
@@ -514,6 +627,7 @@ ivde_status ivde_rig_reset(ivde_server *srv, int32_t rig_id)
         return IVDE_ENOTFOUND;
     }
     srv->rigs[rig_id].has_prev = false;   // the next admitted frame sweeps every row
+    srv->rigs[rig_id].has_i = false;
     return IVDE_OK;
 }
 

@@ -64,7 +64,8 @@ class ServerConfig(ctypes.Structure):
 
 class FrameStats(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("rig_id", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("rows_recomputed", ctypes.c_int64), ("rows_total", ctypes.c_int64),
+                ("rows_recomputed", ctypes.c_int64), ("rows_from_iframe", ctypes.c_int64),
+                ("rows_total", ctypes.c_int64),
                 ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double), ("done_us", ctypes.c_double)]
 
 
@@ -89,6 +90,12 @@ SIGNATURES = {
     "ivde_rig_reset": (_I32, [_P, _I32]),
     "ivde_server_destroy": (None, [_P]),
     "ivde_autotune": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _I32, _P, _P, _I32]),
+    "ivde_stream_submit_rule": (_I32, [_P, _I32, _P, _I32, _P, _P, _P]),
+    "ivde_server_footprint": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P]),
+    "ivde_rig_set_temporal": (_I32, [_P, _I32, ctypes.c_float, ctypes.c_float]),
+    "ivde_segment_stats_size": (_I32, [_I32, _P, _P, _I32, _P]),
+    "ivde_segment_stats": (_I32, [_I32, _P, _P, _P, _P, _SZ, _P, _P, _P, _P]),
+    "ivde_temporal_rule": (_I32, [_I64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _I32, _P, _P]),
     "ivde_window_cost_size": (_I32, [_I32, _P, _P, _P, _I32, _P, _P]),
     "ivde_window_cost": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
     "ivde_window_energy": (_I32, [_I64, _I32, _P, _P, _P, ctypes.c_float, _P, _P]),
@@ -329,6 +336,14 @@ class Batch:
 
 
 # ---------------------------------------------------------------- serving form
+def server_footprint(dv: DeviceViews, lr: LabelRange, opt: Options):
+    """(resident bytes, per-request bytes) a rig needs in a server arena."""
+    r, q = ctypes.c_size_t(), ctypes.c_size_t()
+    check(load().ivde_server_footprint(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt), dv.bit_depth,
+                                       ctypes.byref(r), ctypes.byref(q)))
+    return r.value, q.value
+
+
 class Server:
     """ivde_server over a torch-allocated arena (its size is the budget)."""
 
@@ -361,11 +376,24 @@ class Server:
         self._inflight[t.value] = (images, mask, cost_out, label_out)   # keep alive
         return t.value
 
+    def submit_rule(self, rig: int, images, iframe=False, cost_out=None, label_out=None) -> int:
+        """A frame whose changed rows the server derives by the temporal rule."""
+        t = ctypes.c_uint64(0)
+        check(load().ivde_stream_submit_rule(
+            self.handle, int(rig), images, int(bool(iframe)),
+            ctypes.c_void_p(cost_out.data_ptr()) if cost_out is not None else None,
+            ctypes.c_void_p(label_out.data_ptr()) if label_out is not None else None, ctypes.byref(t)))
+        self._inflight[t.value] = (images, cost_out, label_out)
+        return t.value
+
+    def set_temporal(self, rig: int, t_p=3.0, t_i=1.0):
+        check(load().ivde_rig_set_temporal(self.handle, int(rig), float(t_p), float(t_i)))
+
     @staticmethod
     def _stats(st):
         return dict(ticket=st.ticket, rig=st.rig_id, status=st.status, rows_recomputed=st.rows_recomputed,
-                    rows_total=st.rows_total, submit_us=st.submit_us, start_us=st.start_us, done_us=st.done_us,
-                    latency_ms=(st.done_us - st.submit_us) / 1e3)
+                    rows_from_iframe=st.rows_from_iframe, rows_total=st.rows_total, submit_us=st.submit_us,
+                    start_us=st.start_us, done_us=st.done_us, latency_ms=(st.done_us - st.submit_us) / 1e3)
 
     def wait(self, ticket: int):
         st = FrameStats()
@@ -458,5 +486,35 @@ def window_energy(m, hit, labelling, K=30.0, stream=None):
     out = torch.empty((rows, L), dtype=torch.float32, device=m.device)
     check(load().ivde_window_energy(rows, L, ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(hit.data_ptr()),
                                     ctypes.c_void_p(labelling.data_ptr()), float(K), ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- segment statistics, temporal rule
+def segment_stats(dv: DeviceViews, stream=None):
+    """ivde_segment_stats: (count [rows] int32, centre [rows, 2] int32, mean [rows, 4] float32)."""
+    torch = _torch()
+    lib = load()
+    wb = ctypes.c_size_t()
+    check(lib.ivde_segment_stats_size(dv.n, dv.c_cams, dv.c_segs, dv.bit_depth, ctypes.byref(wb)))
+    ws = alloc_bytes(wb.value)
+    R = dv.rows
+    cnt = torch.empty(R, dtype=torch.int32, device="cuda")
+    cen = torch.empty((R, 2), dtype=torch.int32, device="cuda")
+    mean = torch.empty((R, 4), dtype=torch.float32, device="cuda")
+    check(lib.ivde_segment_stats(dv.n, dv.c_cams, dv.c_images, dv.c_segs, ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(cen.data_ptr()),
+                                 ctypes.c_void_p(mean.data_ptr()), _stream_ptr(stream)))
+    return cnt, cen, mean, ws
+
+
+def temporal_rule(mean, mean_prev, mean_iframe=None, t_p=3.0, t_i=1.0, bit_depth=8, stream=None):
+    """ivde_temporal_rule: uint8 [rows] with 0 recompute, 1 previous frame, 2 I frame."""
+    torch = _torch()
+    rows = mean.shape[0]
+    out = torch.empty(rows, dtype=torch.uint8, device=mean.device)
+    check(load().ivde_temporal_rule(rows, ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(mean_prev.data_ptr()),
+                                    ctypes.c_void_p(mean_iframe.data_ptr()) if mean_iframe is not None else None,
+                                    float(t_p), float(t_i), int(bit_depth), ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream)))
     return out

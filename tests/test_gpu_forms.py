@@ -249,11 +249,7 @@ def test_server_budget_queues_and_rejects():
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
     opt = ivde.options(ivde.BILINEAR, ivde.F32)
-    # sizes: resident = seg maps + volume, working set from the size query
-    cb, wb = ivde.sizes(dv, lr, opt)
-    resident = sum(((c.width * c.height * 4 + 255) // 256) * 256 for c in wl.cams) + ((cb + 255) // 256) * 256
-    tasks = dv.rows * 1 * 16
-    work = ((wb + 255) // 256) * 256 + 256 + tasks
+    resident, work = ivde.server_footprint(dv, lr, opt)
     # room for the resident state and exactly one working set: requests queue
     srv = ivde.Server(resident + work + 4096, max_slots=4)
     rig = _Rig(srv, wl, frames, ivde.F32)
