@@ -56,8 +56,12 @@ def sweep_evals(wl, targets=None) -> int:
 
 
 def kernel_source_hash() -> str:
-    with open(os.path.join(HERE, "paper_1909_02294_amd", "csrc", "kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sweep's sources (the kernels and their device helpers)."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device_util.h"):
+        with open(os.path.join(HERE, "paper_1909_02294_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_counters(name: str):
@@ -263,6 +267,8 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=4.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--gop", type=int, default=0, help="served: every GOP-th frame of a rig is an I frame")
+    ap.add_argument("--rule", action="store_true",
+                    help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -182,6 +182,8 @@ def bench_served(args):
         m = k % period
         return m if m < n_cycle else period - m
 
+    rule = args.rule
+
     def run(temporal: bool):
         srv = ivde.Server(arena_bytes, max_slots=args.slots)
         state = []
@@ -200,7 +202,10 @@ def bench_served(args):
         # each rig's first frame (an I frame: every row) fills its resident
         # volume before the arrival clock starts
         for st in state:
-            srv.wait(srv.submit(st["rid"], st["imgs"][0].c_images, None, None, st["labs"]))
+            if rule:
+                srv.wait(srv.submit_rule(st["rid"], st["imgs"][0].c_images, iframe=True, label_out=st["labs"]))
+            else:
+                srv.wait(srv.submit(st["rid"], st["imgs"][0].c_images, None, None, st["labs"]))
         tickets = []
         t_start = time.perf_counter()
         for k in range(n_req):
@@ -213,11 +218,14 @@ def bench_served(args):
             st = state[which[k]]
             fi = frame_index(st["count"])
             iframe = not temporal or (args.gop > 0 and st["count"] % args.gop == 0)
-            mask = None if iframe else st["masks"][max(fi, st["last"])]
             st["count"] += 1
+            if rule:
+                t = srv.submit_rule(st["rid"], st["imgs"][fi].c_images, iframe=iframe, label_out=st["labs"])
+            else:
+                mask = None if iframe else st["masks"][max(fi, st["last"])]
+                t = srv.submit(st["rid"], st["imgs"][fi].c_images, mask, None, st["labs"])
             st["last"] = fi
-            tickets.append((which[k], iframe,
-                            srv.submit(st["rid"], st["imgs"][fi].c_images, mask, None, st["labs"])))
+            tickets.append((which[k], iframe, t))
         stats = [(r, i, srv.wait(t)) for r, i, t in tickets]
         wall = time.perf_counter() - t_start
         srv.close()
@@ -227,7 +235,9 @@ def bench_served(args):
         for ri, (spec, wl, frames) in enumerate(rigs):
             l = [s["latency_ms"] for r, _, s in stats if r == ri]
             per_rig[spec["name"]] = {"frames": len(l), "p50_ms": _pct(l, 50), "p99_ms": _pct(l, 99)}
+        from_i = float(np.mean([s["rows_from_iframe"] / max(s["rows_total"], 1) for _, _, s in stats]))
         out = {"frames": len(stats), "wall_s": wall, "frames_per_s": len(stats) / wall,
+               "from_iframe_fraction": from_i,
                "swept_evals_per_s": swept / wall,
                "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99), "max": max(lat)},
                "recomputed_fraction": float(np.mean([s["rows_recomputed"] / max(s["rows_total"], 1)
@@ -252,6 +262,7 @@ def bench_served(args):
         "config": {"workload": "Poisson 60 frames/s from rigs A (4x1280x720, 64 labels), B (8x1920x1080, 256), "
                                "C (10x2048x1088, 256); YUV420 10-bit, bilinear, FP16 costs, 80 GB arena",
                    "seconds": duration, "slots": args.slots, "gop": args.gop,
+                   "mask": "temporal rule on the GPU (T_P = 3, T_I = 1)" if rule else "changed-segment mask input",
                    "protocol": "each rig's first (I) frame is computed before the arrival clock; "
                                "images resident on the device; latency = submit to completion",
                    "change_rates": {s["name"]: [round(f["rate"], 3) for f in fr[1:]] for s, _, fr in rigs}},
