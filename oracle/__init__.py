@@ -341,3 +341,77 @@ def all_segment_stats(pb: Problem):
     parts = [segment_stats(pb, v) for v in range(pb.n_views)]
     return (np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
             np.concatenate([p[2] for p in parts]))
+
+
+# ---------------------------------------------------------------- intra-view term (Sec. III-D)
+
+def adjacency(pb: Problem):
+    """T(s) of Eq. (1) and Sec. III-D: the segments of the same view adjacent
+    to s.  Two segments are adjacent when a pixel of one is a 4-neighbour
+    (left, right, above, below) of a pixel of the other.  Returned as CSR over
+    volume rows: offsets [rows + 1] and index [edges] (volume rows), each
+    list increasing; every adjacent pair appears in both lists."""
+    off = pb.row_offsets()
+    total = int(off[-1])
+    src, dst = [np.zeros(0, np.int64)], [np.zeros(0, np.int64)]
+    for v in range(pb.n_views):
+        seg = pb.seg[v].astype(np.int64)
+        if seg.size and (seg.min() < 0 or seg.max() >= pb.S[v]):
+            raise ValueError(f"view {v}: segment id out of range")
+        for a, b in ((seg[:, :-1], seg[:, 1:]), (seg[:-1, :], seg[1:, :])):
+            a, b = a.ravel(), b.ravel()
+            k = a != b
+            src += [a[k] + off[v], b[k] + off[v]]
+            dst += [b[k] + off[v], a[k] + off[v]]
+    key = np.unique(np.concatenate(src) * max(total, 1) + np.concatenate(dst))
+    s, t = key // max(total, 1), key % max(total, 1)
+    offsets = np.zeros(total + 1, np.int64)
+    offsets[1:] = np.cumsum(np.bincount(s, minlength=total))
+    return offsets, t.astype(np.int64)
+
+
+def edge_rows(offsets):
+    """The segment (volume row) owning each CSR entry."""
+    offsets = np.asarray(offsets, np.int64)
+    return np.repeat(np.arange(len(offsets) - 1, dtype=np.int64), np.diff(offsets))
+
+
+def smoothing_beta(mean, offsets, index, beta0, bit_depth, eps=1.0):
+    """Eq. (3) per CSR entry (s, t): beta0 / (||mean_s - mean_t||_1 + eps),
+    the L1 distance of the segments' mean Y, Cb, Cr in 8-bit code values
+    (differences divided by 2^(b - 8)).  eps = 1 code value keeps segments of
+    identical colour finite, where Eq. (3) itself would divide by zero."""
+    mean = np.asarray(mean, np.float64)[:, :3]
+    s = edge_rows(offsets)
+    t = np.asarray(index, np.int64)
+    d = np.abs(mean[s] - mean[t]).sum(axis=1) / float(1 << (bit_depth - 8))
+    return float(beta0) / (d + float(eps))
+
+
+def intra_cost(offsets, index, beta, labelling, num_labels, fixed=None):
+    """Eq. (2) seen from segment s at label l with its neighbours' labels
+    held: U[s, l] = sum over t in T(s) of beta_st * |l - d_t|, depths in
+    label units.  With a mask `fixed`, only neighbours t with fixed[t] count
+    (segments left out of the optimisation still enter the costs of their
+    neighbours, Sec. III-E)."""
+    s = edge_rows(offsets)
+    t = np.asarray(index, np.int64)
+    w = np.asarray(beta, np.float64)
+    if fixed is not None:
+        keep = np.asarray(fixed, bool)[t]
+        s, t, w = s[keep], t[keep], w[keep]
+    d_t = np.asarray(labelling, np.int64)[t]
+    L = int(num_labels)
+    U = np.zeros((len(offsets) - 1, L))
+    np.add.at(U, s, w[:, None] * np.abs(np.arange(L)[None, :] - d_t[:, None]))
+    return U
+
+
+def intra_energy(offsets, index, beta, labelling):
+    """The intra-view part of Eq. (1) for a labelling: the sum over s and
+    t in T(s) of beta_st |d_s - d_t| (each adjacent pair counted from both
+    sides, as the double sum is written)."""
+    d = np.asarray(labelling, np.int64)
+    s = edge_rows(offsets)
+    t = np.asarray(index, np.int64)
+    return float(np.sum(np.asarray(beta, np.float64) * np.abs(d[s] - d[t])))

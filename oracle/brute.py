@@ -219,3 +219,44 @@ def window_cost(cams, Y, U, V, seg, S, bit_depth, chroma_shift, z_near, z_far, L
             ms.append(mrow)
             hits.append(hrow)
     return ms, hits
+
+
+def adjacency_sets(seg_maps, S):
+    """T(s) as Python sets of (view, segment): 4-neighbour pixel contact."""
+    adj = {}
+    for v, seg in enumerate(seg_maps):
+        h, w = len(seg), len(seg[0])
+        for s in range(S[v]):
+            adj[(v, s)] = set()
+        for y in range(h):
+            for x in range(w):
+                a = int(seg[y][x])
+                for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                    xx, yy = x + dx, y + dy
+                    if 0 <= xx < w and 0 <= yy < h and int(seg[yy][xx]) != a:
+                        adj[(v, a)].add((v, int(seg[yy][xx])))
+    return adj
+
+
+def intra_terms(seg_maps, S, means, beta0, bit_depth, labelling, num_labels, eps=1.0):
+    """Eq. (3) weights and Eq. (2) costs by loops: returns
+    (beta {(row_s, row_t): value}, U [rows][L] list, energy)."""
+    off = [0]
+    for s in S:
+        off.append(off[-1] + s)
+    adj = adjacency_sets(seg_maps, S)
+    scale = float(2 ** (bit_depth - 8))
+    beta = {}
+    for (v, s), nb in adj.items():
+        for (_, t) in nb:
+            rs, rt = off[v] + s, off[v] + t
+            d = sum(abs(means[rs][k] - means[rt][k]) for k in range(3)) / scale
+            beta[(rs, rt)] = beta0 / (d + eps)
+    rows = off[-1]
+    U = [[0.0] * num_labels for _ in range(rows)]
+    energy = 0.0
+    for (rs, rt), b in beta.items():
+        for l in range(num_labels):
+            U[rs][l] += b * abs(l - labelling[rt])
+        energy += b * abs(labelling[rs] - labelling[rt])
+    return beta, U, energy
