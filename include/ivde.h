@@ -351,6 +351,43 @@ ivde_status ivde_temporal_rule(int64_t rows, const float *mean, const float *mea
                                const float *mean_iframe, float t_p, float t_i, int32_t bit_depth,
                                uint8_t *source_out, ivde_stream stream);
 
+/* ---------------------------------------------------------------- intra-view term */
+
+/* Workspace bytes for ivde_adjacency (segment index and statistics). */
+ivde_status ivde_adjacency_size(int32_t n_views, const ivde_camera *cams,
+                                const ivde_segmentation *segs, int32_t bit_depth,
+                                size_t *workspace_bytes);
+/* T(s) of Sec. III-D with the weights of Eq. (3).  Two segments of one view
+ * are adjacent when a pixel of one is a 4-neighbour (left, right, above,
+ * below) of a pixel of the other.  Outputs, device memory, rows ordered as in
+ * ivde_cost_volume:
+ *   offsets  int64 [rows + 1]: CSR offsets; offsets[rows] is the total number
+ *            of entries (every adjacent pair appears once in each list)
+ *   index    int32 [capacity]: neighbour rows, increasing within each row
+ *   beta     float [capacity]: beta0 / (||mean_s - mean_t||_1 + eps), mean
+ *            Y, Cb, Cr differences in 8-bit code values (divided by
+ *            2^(bit_depth - 8)); eps > 0 keeps equal colours finite (Eq. (3)
+ *            alone divides by zero there; 1 is the customary choice)
+ * Entries at or beyond `capacity` are not written: call with capacity 0
+ * (index and beta may then be NULL) to learn offsets[rows], or pass a bound.
+ * Segment ids outside [0, num_segments) are ignored and reported by
+ * ivde_workspace_status. */
+ivde_status ivde_adjacency(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                           const ivde_segmentation *segs, float beta0, float eps, void *workspace,
+                           size_t workspace_bytes, int64_t *offsets, int32_t *index, float *beta,
+                           int64_t capacity, ivde_stream stream);
+/* Eq. (2) seen from each segment with its neighbours' depths held:
+ *   out[r][l] = sum over CSR entries (r, t) of beta * |l - labelling[t]|
+ * depths in label units; with a mask (device uint8 [rows], NULL = all),
+ * only neighbours t with fixed[t] != 0 count -- segments kept out of the
+ * optimisation enter their neighbours' costs this way (Sec. III-E).
+ * offsets, index, beta as written by ivde_adjacency; labelling int32 [rows];
+ * out float [rows][num_labels].  Entries whose row is outside [0, rows) are
+ * skipped. */
+ivde_status ivde_intra_cost(int64_t rows, int32_t num_labels, const int64_t *offsets,
+                            const int32_t *index, const float *beta, const int32_t *labelling,
+                            const uint8_t *fixed, float *out, ivde_stream stream);
+
 /* ---------------------------------------------------------------- tuning */
 
 /* Times every (labels_per_lane, waves_per_group) launch shape on the given

@@ -107,6 +107,11 @@ hipError_t launch_temporal_rule(int64_t rows, const float *mean, const float *pr
 hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *source, int which, const void *from,
                                   void *to, hipStream_t s);
 // Window matching core towards views c - 1 and c + 1 for every task.
+hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write, int64_t *offsets, int32_t *index,
+                            float *beta, int64_t capacity, float beta0, float eps, float inv_scale, hipStream_t s);
+hipError_t launch_scan_rows(int64_t *a, int64_t n, hipStream_t s);
+hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const int32_t *index, const float *beta,
+                             const int32_t *labelling, const uint8_t *fixed, float *out, hipStream_t s);
 hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
                          float *m_out, int32_t *hit_out, hipStream_t s);
 hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32_t *hit, const int32_t *labelling,

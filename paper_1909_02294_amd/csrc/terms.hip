@@ -1,6 +1,7 @@
 // gfx950 kernels of the energy terms around the matching cost: segment
 // statistics (centre and mean colour), the window matching core of
-// Sec. III-C (Eqs. (4), (5)) and the temporal rule of Sec. III-E.
+// Sec. III-C (Eqs. (4), (5)), the temporal rule of Sec. III-E and the
+// intra-view term of Sec. III-D (Eqs. (2), (3)).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -211,6 +212,152 @@ __global__ void k_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *__
     reinterpret_cast<uint32_t *>(to)[i] = reinterpret_cast<const uint32_t *>(from)[i];
 }
 
+
+// ------------------------------------------------------------------ intra-view term
+// Sec. III-D: segments of one view are adjacent when a pixel of one is a
+// 4-neighbour of a pixel of the other.  One wave per segment reads, for each
+// of its pixels, the segment ids left, right, above and below, and extracts
+// the distinct ids in increasing order by repeated wave minima; the lists
+// are therefore sorted and independent of any scheduling.
+constexpr int kAdjCache = 4;            // pixel batches whose neighbour ids stay in registers
+constexpr int kNoSeg = 0x7fffffff;
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+    return uniform(v);
+}
+
+// Segment ids around pixel record i; kNoSeg outside the image, for the
+// segment itself and for ids out of range (reported by the index kernels).
+__device__ __forceinline__ void neighbours4(const ViewDesc &v, const float *rec, int i, int s, int (&c)[4])
+{
+    const float2 xy = *reinterpret_cast<const float2 *>(rec + 8 * (int64_t)i);
+    const int x = (int)xy.x, y = (int)xy.y;
+    const int32_t *row = v.seg + (int64_t)y * v.seg_pitch;
+    const int t0 = x > 0 ? row[x - 1] : kNoSeg;
+    const int t1 = x + 1 < v.W ? row[x + 1] : kNoSeg;
+    const int t2 = y > 0 ? row[x - v.seg_pitch] : kNoSeg;
+    const int t3 = y + 1 < v.H ? row[x + v.seg_pitch] : kNoSeg;
+    c[0] = (t0 != s && t0 >= 0 && t0 < v.S) ? t0 : kNoSeg;
+    c[1] = (t1 != s && t1 >= 0 && t1 < v.S) ? t1 : kNoSeg;
+    c[2] = (t2 != s && t2 >= 0 && t2 < v.S) ? t2 : kNoSeg;
+    c[3] = (t3 != s && t3 >= 0 && t3 < v.S) ? t3 : kNoSeg;
+}
+
+__device__ __forceinline__ int min_above(const int (&c)[4], int last, int m)
+{
+    for (int d = 0; d < 4; ++d)
+        if (c[d] > last) m = min(m, c[d]);
+    return m;
+}
+
+// WRITE = false: offsets[row + 1] = number of neighbours.  WRITE = true (after
+// the scan): the neighbour rows and their Eq. (3) weights from offsets[row],
+// entries at or beyond `capacity` skipped.
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P, int64_t *__restrict__ offsets,
+                                                   int32_t *__restrict__ index, float *__restrict__ beta,
+                                                   int64_t capacity, float beta0, float eps, float inv_scale)
+{
+    const ViewDesc &v = P->views[blockIdx.y];
+    const int lane = lane_id();
+    const int s = uniform(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    if (s >= v.S) return;
+    const int p0 = v.offsets[s], p1 = v.offsets[s + 1];
+    const int64_t row = v.row0 + s;
+    const float *rec = v.pixrec;
+    const bool cached = p1 - p0 <= kAdjCache * kWave;
+    int c[kAdjCache][4];
+#pragma unroll
+    for (int b = 0; b < kAdjCache; ++b) {
+        const int i = p0 + b * kWave + lane;
+        if (cached && i < p1)
+            neighbours4(v, rec, i, s, c[b]);
+        else
+            c[b][0] = c[b][1] = c[b][2] = c[b][3] = kNoSeg;
+    }
+    const int64_t out = WRITE ? offsets[row] : 0;
+    float4 ms = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (WRITE) ms = reinterpret_cast<const float4 *>(v.mean)[s];
+    int last = -1, k = 0;
+    for (;;) {
+        int m = kNoSeg;
+        if (cached) {
+#pragma unroll
+            for (int b = 0; b < kAdjCache; ++b) m = min_above(c[b], last, m);
+        } else {
+            for (int i0 = p0; i0 < p1; i0 += kWave) {
+                int cc[4] = {kNoSeg, kNoSeg, kNoSeg, kNoSeg};
+                if (i0 + lane < p1) neighbours4(v, rec, i0 + lane, s, cc);
+                m = min_above(cc, last, m);
+            }
+        }
+        m = wave_min(m);
+        if (m == kNoSeg) break;
+        if (WRITE && lane == 0 && out + k < capacity) {
+            index[out + k] = (int32_t)(v.row0 + m);
+            const float4 mt = reinterpret_cast<const float4 *>(v.mean)[m];
+            const float d = (fabsf(ms.x - mt.x) + fabsf(ms.y - mt.y) + fabsf(ms.z - mt.z)) * inv_scale;
+            beta[out + k] = beta0 / (d + eps);
+        }
+        ++k;
+        last = m;
+    }
+    if (!WRITE && lane == 0) offsets[row + 1] = k;
+}
+
+// In-place inclusive scan of a[1..n] with a[0] = 0 (one workgroup: each
+// thread owns a contiguous chunk).
+__global__ __launch_bounds__(1024) void k_scan_rows(int64_t *__restrict__ a, int64_t n)
+{
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t b = 1 + tid * chunk, e = min(n + 1, b + chunk);
+    int64_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += a[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t base = part[tid] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        base += a[i];
+        a[i] = base;
+    }
+    if (tid == 0) a[0] = 0;
+}
+
+// Eq. (2) with the neighbours' labels held: out[r][l] = sum over entries
+// (r, t) of beta * |l - d_t|, only over t with fixed[t] != 0 when a mask is
+// given.  One wave per (row, 64-label block); lanes are labels.
+__global__ __launch_bounds__(256) void k_intra_cost(int64_t rows, int L, int n_lblocks,
+                                                    const int64_t *__restrict__ offsets,
+                                                    const int32_t *__restrict__ index, const float *__restrict__ beta,
+                                                    const int32_t *__restrict__ labelling,
+                                                    const uint8_t *__restrict__ fixed, float *__restrict__ out)
+{
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + uniform(threadIdx.x / kWave);
+    if (w >= rows * n_lblocks) return;
+    const int64_t r = w / n_lblocks;
+    const int l = (int)(w - r * n_lblocks) * kWave + lane;
+    const int64_t e0 = ldu(offsets + r), e1 = ldu(offsets + r + 1);
+    float acc = 0.f;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int t = ldu(index + e);
+        if (t < 0 || t >= rows) continue;
+        if (fixed && !fixed[t]) continue;
+        acc = fmaf(ldu(beta + e), fabsf((float)(l - ldu(labelling + t))), acc);
+    }
+    if (l < L) out[r * L + l] = acc;
+}
+
 }  // namespace
 
 hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, int32_t *count_flat, hipStream_t s)
@@ -267,6 +414,37 @@ hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_window_energy, dim3((unsigned)blocks), dim3(256), 0, s, rows, L, m, hit, labelling, K, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write, int64_t *offsets, int32_t *index,
+                            float *beta, int64_t capacity, float beta0, float eps, float inv_scale, hipStream_t s)
+{
+    const dim3 grid((unsigned)((ext.max_s + 3) / 4), (unsigned)ext.n_views);
+    if (write)
+        hipLaunchKernelGGL(k_adjacency<true>, grid, dim3(256), 0, s, dprob, offsets, index, beta, capacity, beta0, eps,
+                           inv_scale);
+    else
+        hipLaunchKernelGGL(k_adjacency<false>, grid, dim3(256), 0, s, dprob, offsets, index, beta, capacity, beta0,
+                           eps, inv_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_rows(int64_t *a, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const int32_t *index, const float *beta,
+                             const int32_t *labelling, const uint8_t *fixed, float *out, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    const int nb = (L + 63) / 64;
+    const int64_t blocks = (rows * nb + 3) / 4;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_intra_cost, dim3((unsigned)blocks), dim3(256), 0, s, rows, L, nb, offsets, index, beta,
+                       labelling, fixed, out);
     return hipGetLastError();
 }
 

@@ -95,6 +95,9 @@ SIGNATURES = {
     "ivde_rig_set_temporal": (_I32, [_P, _I32, ctypes.c_float, ctypes.c_float]),
     "ivde_segment_stats_size": (_I32, [_I32, _P, _P, _I32, _P]),
     "ivde_segment_stats": (_I32, [_I32, _P, _P, _P, _P, _SZ, _P, _P, _P, _P]),
+    "ivde_adjacency_size": (_I32, [_I32, _P, _P, _I32, _P]),
+    "ivde_adjacency": (_I32, [_I32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
+    "ivde_intra_cost": (_I32, [_I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "ivde_temporal_rule": (_I32, [_I64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _I32, _P, _P]),
     "ivde_window_cost_size": (_I32, [_I32, _P, _P, _P, _I32, _P, _P]),
     "ivde_window_cost": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
@@ -517,4 +520,45 @@ def temporal_rule(mean, mean_prev, mean_iframe=None, t_p=3.0, t_i=1.0, bit_depth
                                     ctypes.c_void_p(mean_iframe.data_ptr()) if mean_iframe is not None else None,
                                     float(t_p), float(t_i), int(bit_depth), ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream)))
+    return out
+
+
+def adjacency(dv: DeviceViews, beta0: float, eps: float = 1.0, capacity=None, stream=None):
+    """ivde_adjacency: (offsets [rows + 1] int64, index [edges] int32,
+    beta [edges] float32).  With capacity None the entry count is learned
+    first (a call with capacity 0), then the lists are filled."""
+    torch = _torch()
+    lib = load()
+    wb = ctypes.c_size_t()
+    check(lib.ivde_adjacency_size(dv.n, dv.c_cams, dv.c_segs, dv.bit_depth, ctypes.byref(wb)))
+    ws = alloc_bytes(wb.value)
+    offsets = torch.empty(dv.rows + 1, dtype=torch.int64, device="cuda")
+
+    def run(cap, index, beta):
+        check(lib.ivde_adjacency(dv.n, dv.c_cams, dv.c_images, dv.c_segs, float(beta0), float(eps),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(offsets.data_ptr()),
+                                 ctypes.c_void_p(index.data_ptr()) if index is not None else None,
+                                 ctypes.c_void_p(beta.data_ptr()) if beta is not None else None, int(cap),
+                                 _stream_ptr(stream)))
+
+    if capacity is None:
+        run(0, None, None)
+        (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+        capacity = int(offsets[-1].item())
+    index = torch.empty(max(int(capacity), 1), dtype=torch.int32, device="cuda")
+    beta = torch.empty(max(int(capacity), 1), dtype=torch.float32, device="cuda")
+    run(capacity, index, beta)
+    return offsets, index[:capacity], beta[:capacity], ws
+
+
+def intra_cost(offsets, index, beta, labelling, num_labels: int, fixed=None, stream=None):
+    """ivde_intra_cost: float32 [rows, num_labels]."""
+    torch = _torch()
+    rows = offsets.shape[0] - 1
+    out = torch.empty((rows, int(num_labels)), dtype=torch.float32, device=offsets.device)
+    check(load().ivde_intra_cost(rows, int(num_labels), ctypes.c_void_p(offsets.data_ptr()),
+                                 ctypes.c_void_p(index.data_ptr()), ctypes.c_void_p(beta.data_ptr()),
+                                 ctypes.c_void_p(labelling.data_ptr()),
+                                 ctypes.c_void_p(fixed.data_ptr()) if fixed is not None else None,
+                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out

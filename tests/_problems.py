@@ -110,3 +110,48 @@ def fronto_plane_views(rng, cams, f, baseline_x, shifts, bit_depth=8, width=None
         sl = tex[:, :, pad + s: pad + s + w]
         Y.append(sl[0].astype(dt)); U.append(sl[1].astype(dt)); V.append(sl[2].astype(dt))
     return Y, U, V
+
+
+def blocky_problem(seed, sizes, n_ids, bit_depth=10, chroma_shift=1):
+    """Views whose label maps are random small rectangles with ids drawn
+    from n_ids (some ids never drawn, so some segments are empty) plus a few
+    single pixels, over random images."""
+    rng = np.random.default_rng(seed)
+    cams, seg, S = [], [], []
+    for (w, h), n in zip(sizes, n_ids):
+        K = [[6.0, 0, (w - 1) / 2], [0, 6.0, (h - 1) / 2], [0, 0, 1]]
+        cams.append(cam(K, np.eye(3), [-0.05 * len(cams), 0, 0], w, h))
+        bw, bh = rng.integers(1, 4), rng.integers(1, 4)
+        blocks = rng.integers(0, n, ((h + bh - 1) // bh, (w + bw - 1) // bw))
+        m = np.kron(blocks, np.ones((bh, bw), np.int64))[:h, :w]
+        for _ in range(3):
+            m[rng.integers(0, h), rng.integers(0, w)] = rng.integers(0, n)
+        seg.append(m.astype(np.int32))
+        S.append(int(n))
+    Y, U, V = random_images(rng, cams, bit_depth, chroma_shift)
+    return SimpleNamespace(cams=cams, Y=Y, U=U, V=V, seg=seg, S=S, bit_depth=bit_depth, chroma_shift=chroma_shift,
+                           z_near=1.0, z_far=3.0, num_labels=6)
+
+
+def islands_problem(seed, width=160, height=96, n_islands=300):
+    """One background segment holding many small islands (single pixels and
+    2 x 2 blocks), in two views: a segment with hundreds of pixels and
+    hundreds of neighbours."""
+    rng = np.random.default_rng(seed)
+    cams, seg, S = [], [], []
+    for v in range(2):
+        K = [[80.0, 0, (width - 1) / 2], [0, 80.0, (height - 1) / 2], [0, 0, 1]]
+        cams.append(cam(K, np.eye(3), [-0.05 * v, 0, 0], width, height))
+        m = np.zeros((height, width), np.int32)
+        ys = rng.choice(np.arange(1, height - 2, 3), n_islands)
+        xs = rng.choice(np.arange(1, width - 2, 3), n_islands)
+        for i, (y, x) in enumerate(zip(ys, xs)):
+            if i % 2:
+                m[y:y + 2, x:x + 2] = i + 1
+            else:
+                m[y, x] = i + 1
+        seg.append(m)
+        S.append(n_islands + 3)                 # two ids never used
+    Y, U, V = random_images(rng, cams, 8, 0)
+    return SimpleNamespace(cams=cams, Y=Y, U=U, V=V, seg=seg, S=S, bit_depth=8, chroma_shift=0,
+                           z_near=1.0, z_far=3.0, num_labels=6)

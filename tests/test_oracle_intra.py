@@ -58,23 +58,9 @@ def test_hand_derived_intra_term():
 
 
 def _blocky_problem(seed, sizes, n_ids):
-    """Random label maps of small rectangles with ids drawn from n_ids (some
-    ids never drawn, so some segments are empty), random 8-bit images."""
-    rng = np.random.default_rng(seed)
-    cams, seg, S = [], [], []
-    for (w, h), n in zip(sizes, n_ids):
-        K = [[6.0, 0, (w - 1) / 2], [0, 6.0, (h - 1) / 2], [0, 0, 1]]
-        cams.append(P.cam(K, np.eye(3), [-0.05 * len(cams), 0, 0], w, h))
-        bw, bh = rng.integers(1, 4), rng.integers(1, 4)
-        blocks = rng.integers(0, n, ((h + bh - 1) // bh, (w + bw - 1) // bw))
-        m = np.kron(blocks, np.ones((bh, bw), np.int64))[:h, :w]
-        # a few single pixels of other ids
-        for _ in range(3):
-            m[rng.integers(0, h), rng.integers(0, w)] = rng.integers(0, n)
-        seg.append(m.astype(np.int32))
-        S.append(int(n))
-    Y, U, V = P.random_images(rng, cams, 10, 1)
-    return oracle.Problem(cams, Y, U, V, seg, S, 10, 1, 1.0, 3.0, 6, False)
+    ns = P.blocky_problem(seed, sizes, n_ids)
+    return oracle.Problem(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift, 1.0, 3.0, 6,
+                          False)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
@@ -180,6 +166,20 @@ def test_identities_between_costs_and_energy():
                                oracle.intra_cost(off, idx, beta, lab, 9, fixed=~m), U, rtol=1e-12, atol=1e-12)
     # each U row is convex in the label (a sum of weighted absolute values)
     assert np.all(np.diff(U, 2, axis=1) >= -1e-9)
+
+
+def test_islands_match_brute_force():
+    """A segment with hundreds of pixels and hundreds of neighbours."""
+    ns = P.islands_problem(3, width=40, height=30, n_islands=60)
+    pb = oracle.Problem(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, 8, 0, 1.0, 3.0, 6, False)
+    off, idx = oracle.adjacency(pb)
+    sets = brute.adjacency_sets(pb.seg, pb.S)
+    row0 = pb.row_offsets()
+    for v in range(2):
+        for s in range(pb.S[v]):
+            r = row0[v] + s
+            assert list(idx[off[r]:off[r + 1]]) == sorted(row0[v] + t for (_, t) in sets[(v, s)])
+    assert off[1] - off[0] > 40
 
 
 def test_beta_units_and_eps():
