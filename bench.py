@@ -15,6 +15,7 @@ Inputs are resident in HBM before the timed region.  Prints one JSON line.
   --mode served   the serving loop on a Poisson stream from three rigs
   --mode copycal  a device copy of known size (calibrates HBM counters)
   --mode window   the paper's own 3x3 centre-window term
+  --mode intra    the intra-view term: adjacency, weights, per-label costs
 """
 from __future__ import annotations
 
@@ -236,6 +237,48 @@ def bench_window(args):
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}}
 
 
+def bench_intra(args):
+    """The intra-view term (Sec. III-D) on the 8-view 1080p workload: one
+    step is the segment index, statistics, adjacency with Eq. (3) weights,
+    and the Eq. (2) costs of every segment at 256 labels for a labelling."""
+    import torch
+    from paper_1909_02294_amd import ivde, synth
+
+    wl = synth.make_cfg1()
+    dv = ivde.DeviceViews.from_workload(wl)
+    off, idx, beta, ws = ivde.adjacency(dv, 30.0, 1.0)
+    torch.cuda.synchronize()
+    edges = int(off[-1].item())
+    lab = torch.from_numpy(np.random.default_rng(3).integers(0, wl.num_labels, dv.rows).astype(np.int32)).cuda()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        o, i, b, _ = ivde.adjacency(dv, 30.0, 1.0, capacity=edges)
+        return ivde.intra_cost(o, i, b, lab, wl.num_labels)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    lat = [a.elapsed_time(b) for a, b in ev]
+    terms = edges * wl.num_labels
+    return {"metric": "intra-view cost terms/s (adjacency entry x label)", "value": terms / elapsed,
+            "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": elapsed * 1e3, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "8-view 1920x1080 YUV420 10-bit arc rig, 20000 segments per view, 256 labels",
+                       "adjacency_entries": edges, "rows": dv.rows,
+                       "step": "segment index + statistics + adjacency (count, scan, fill with weights) + "
+                               "Eq. (2) costs for a labelling"},
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}}
+
+
 def copy_calibration(args):
     """A plain device copy of known size (read n bytes, write n bytes per
     dispatch): what the HBM counters read for it scales the sweep's counts."""
@@ -258,7 +301,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window", "intra"], default="plain")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--labels-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
@@ -285,6 +328,8 @@ def main():
         out = copy_calibration(args)
     elif args.mode == "window":
         out = bench_window(args)
+    elif args.mode == "intra":
+        out = bench_intra(args)
     elif args.mode == "batched":
         from paper_1909_02294_amd import benchforms
         out = benchforms.bench_batched(args)

@@ -42,8 +42,6 @@ struct ivde_batch {
 
 namespace {
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
 ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_options *opt, ivde_batch &b)
 {
     if (n_frames < 1 || !frames || !opt) {

@@ -191,7 +191,6 @@ int default_labels_per_lane(int L)
 }
 
 // ---------------------------------------------------------------- layout
-static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *segs, const ivde_label_range *labels,
                    const ivde_options *opt, int bit_depth)

@@ -11,6 +11,8 @@
 
 namespace ivde {
 
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
 struct ViewLayout {
     int64_t row0;
     int32_t n_bands;

@@ -28,6 +28,12 @@ ivde_options index_options()
 
 const ivde_label_range kIndexLabels{1.0, 2.0, 1, IVDE_REF_RIG_CENTER};
 
+// The index workspace, then the block sums of the offsets scan.
+size_t adjacency_workspace(const Layout &ly)
+{
+    return align_up(ly.workspace_bytes, 256) + align_up(sizeof(int64_t) * (size_t)((ly.total_rows + 255) / 256 + 1), 256);
+}
+
 }  // namespace
 
 extern "C" {
@@ -43,7 +49,7 @@ ivde_status ivde_adjacency_size(int32_t n_views, const ivde_camera *cams, const 
         return IVDE_EINVAL;
     }
     const Layout ly = plan_layout(n_views, cams, segs, &kIndexLabels, &o, bit_depth);
-    if (workspace_bytes) *workspace_bytes = ly.workspace_bytes;
+    if (workspace_bytes) *workspace_bytes = adjacency_workspace(ly);
     return IVDE_OK;
 }
 
@@ -68,10 +74,11 @@ ivde_status ivde_adjacency(int32_t n_views, const ivde_camera *cams, const ivde_
         set_error("adjacency: too many segments");
         return IVDE_EINVAL;
     }
-    if ((st = check_workspace(workspace, workspace_bytes, ly.workspace_bytes)) != IVDE_OK) return st;
+    if ((st = check_workspace(workspace, workspace_bytes, adjacency_workspace(ly))) != IVDE_OK) return st;
     if ((st = check_tex_limits(ly)) != IVDE_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
+    int64_t *block_sums = reinterpret_cast<int64_t *>(ws + align_up(ly.workspace_bytes, 256));
     Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
     st = enqueue_front(n_views, cams, views, segs, &kIndexLabels, &o, ly, ws, nullptr, 0, tasks, s);
     if (st != IVDE_OK) return st;
@@ -80,7 +87,7 @@ ivde_status ivde_adjacency(int32_t n_views, const ivde_camera *cams, const ivde_
     const float inv_scale = 1.0f / (float)(1 << (views[0].bit_depth - 8));
     hipError_t e = launch_segment_stats(dp, ext, nullptr, s);
     if (e == hipSuccess) e = launch_adjacency(dp, ext, 0, offsets, nullptr, nullptr, 0, beta0, eps, inv_scale, s);
-    if (e == hipSuccess) e = launch_scan_rows(offsets, ly.total_rows, s);
+    if (e == hipSuccess) e = launch_scan_rows(offsets, ly.total_rows, block_sums, s);
     if (e == hipSuccess && capacity > 0)
         e = launch_adjacency(dp, ext, 1, offsets, index, beta, capacity, beta0, eps, inv_scale, s);
     if (e != hipSuccess) return hip_fail(e, "adjacency");

@@ -109,7 +109,9 @@ hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *so
 // Window matching core towards views c - 1 and c + 1 for every task.
 hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write, int64_t *offsets, int32_t *index,
                             float *beta, int64_t capacity, float beta0, float eps, float inv_scale, hipStream_t s);
-hipError_t launch_scan_rows(int64_t *a, int64_t n, hipStream_t s);
+// In-place inclusive scan of a[1..n] with a[0] = 0; block_sums holds
+// ceil(n / 256) (at least 1) int64 of scratch.
+hipError_t launch_scan_rows(int64_t *a, int64_t n, int64_t *block_sums, hipStream_t s);
 hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const int32_t *index, const float *beta,
                              const int32_t *labelling, const uint8_t *fixed, float *out, hipStream_t s);
 hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,

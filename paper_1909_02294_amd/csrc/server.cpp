@@ -44,8 +44,6 @@ double now_us()
     return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
 }
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
 // First-fit allocator over the arena, 256-byte granules.
 class Arena {
   public:

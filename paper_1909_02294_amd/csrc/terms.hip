@@ -307,30 +307,64 @@ __global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P
     if (!WRITE && lane == 0) offsets[row + 1] = k;
 }
 
-// In-place inclusive scan of a[1..n] with a[0] = 0 (one workgroup: each
-// thread owns a contiguous chunk).
-__global__ __launch_bounds__(1024) void k_scan_rows(int64_t *__restrict__ a, int64_t n)
+// In-place inclusive scan of a[1..n], a[0] = 0, in three phases: sums of
+// 256-element blocks, a scan of those sums, then each block's own scan.
+__device__ __forceinline__ int64_t wave_inclusive_scan(int64_t v)
 {
-    __shared__ int64_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t chunk = (n + 1023) / 1024;
-    const int64_t b = 1 + tid * chunk, e = min(n + 1, b + chunk);
-    int64_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += a[i];
-    part[tid] = sum;
+    const int lane = lane_id();
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Inclusive scan over a 256-thread block; `total` receives the block sum.
+__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t &total)
+{
+    __shared__ int64_t wsum[4];
+    const int w = threadIdx.x / kWave;
+    v = wave_inclusive_scan(v);
+    if (lane_id() == kWave - 1) wsum[w] = v;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int64_t v = tid >= d ? part[tid - d] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    int64_t before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return v + before;
+}
+
+__global__ __launch_bounds__(256) void k_scan_block_sums(const int64_t *__restrict__ a, int64_t n,
+                                                         int64_t *__restrict__ sums)
+{
+    const int64_t i = 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t total;
+    block_inclusive_scan(i <= n ? a[i] : 0, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block sums in place (one workgroup, 256 at a time).
+__global__ __launch_bounds__(256) void k_scan_sums(int64_t *__restrict__ sums, int64_t nb)
+{
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t v = i < nb ? sums[i] : 0;
+        int64_t total;
+        const int64_t inc = block_inclusive_scan(v, total);
+        if (i < nb) sums[i] = carry + inc - v;
+        carry += total;
     }
-    int64_t base = part[tid] - sum;
-    for (int64_t i = b; i < e; ++i) {
-        base += a[i];
-        a[i] = base;
-    }
-    if (tid == 0) a[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(int64_t *__restrict__ a, int64_t n,
+                                                    const int64_t *__restrict__ sums)
+{
+    const int64_t i = 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t total;
+    const int64_t inc = block_inclusive_scan(i <= n ? a[i] : 0, total);
+    if (i <= n) a[i] = sums[blockIdx.x] + inc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a[0] = 0;
 }
 
 // Eq. (2) with the neighbours' labels held: out[r][l] = sum over entries
@@ -430,9 +464,17 @@ hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write,
     return hipGetLastError();
 }
 
-hipError_t launch_scan_rows(int64_t *a, int64_t n, hipStream_t s)
+hipError_t launch_scan_rows(int64_t *a, int64_t n, int64_t *block_sums, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, a, n);
+    const int64_t nb = (n + 255) / 256;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(256), 0, s, a, n, block_sums);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(256), 0, s, a, n, block_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, block_sums, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, a, n, block_sums);
     return hipGetLastError();
 }
 
