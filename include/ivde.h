@@ -388,6 +388,60 @@ ivde_status ivde_intra_cost(int64_t rows, int32_t num_labels, const int64_t *off
                             const int32_t *index, const float *beta, const int32_t *labelling,
                             const uint8_t *fixed, float *out, ivde_stream stream);
 
+/* ---------------------------------------------------------------- depth optimisation (host) */
+
+/* Eq. (1) over segment nodes, in host memory.  With d the label of every
+ * row and q(x) = x * quantum rounded half away from zero:
+ *   E(d) = sum_r q(unary[r][d_r])
+ *        + sum_r sum_slot [h >= 0 and d_h = d_r] q(min(0, m - K)),
+ *              m = window_m[r][slot][d_r], h = window_hit[r][slot][d_r]  (Eq. (5))
+ *        + sum over adjacency entries (r, t) of q(beta) |d_r - d_t|       (Eq. (2))
+ * Integer terms make every maximum flow exact.  Any term group may be
+ * absent (NULL).  window_m / window_hit are ivde_window_cost's outputs,
+ * adj_* ivde_adjacency's (both copied to the host).  fixed_labels, if
+ * given, holds for each row -1 (a free segment) or the label of a segment
+ * that is not a node (Sec. III-E: it keeps that label and enters the
+ * costs of the others).  The pointers are read during the call only. */
+typedef struct ivde_energy {
+    int64_t rows;
+    int32_t num_labels;
+    const float *unary;            /* [rows][num_labels] or NULL */
+    const float *window_m;         /* [rows][2][num_labels] or NULL */
+    const int32_t *window_hit;     /* [rows][2][num_labels], -1 = no match; with window_m */
+    float K;                       /* Eq. (5) truncation; the paper uses 30 */
+    const int64_t *adj_offsets;    /* [rows + 1] or NULL */
+    const int32_t *adj_index;      /* [adj_offsets[rows]] rows */
+    const float *adj_beta;         /* [adj_offsets[rows]], >= 0 */
+    const int32_t *fixed_labels;   /* [rows] or NULL */
+    double quantum;                /* > 0 */
+} ivde_energy;
+
+#define IVDE_PARTITION_BLOCKS 0        /* thread k takes levels [k L / n, (k + 1) L / n) */
+#define IVDE_PARTITION_INTERLEAVED 1   /* thread k takes levels l with l mod n = k */
+
+/* E(labels) as defined above. */
+ivde_status ivde_energy_value(const ivde_energy *energy, const int32_t *labels, int64_t *energy_out);
+
+/* Alpha-expansion from `labels` (updated in place) over the listed levels,
+ * in increasing order, in cycles until one changes nothing or max_cycles
+ * have run (graph cuts, Sec. III-B).  Each move takes the minimum cut
+ * whose source side (segments keeping their label) is smallest, i.e. the
+ * nodes reachable from the source in the residual graph; a move is kept
+ * when it lowers E.  Fixed rows must carry their fixed label. */
+ivde_status ivde_expansion(const ivde_energy *energy, int32_t *labels, const int32_t *label_list,
+                           int32_t n_list, int32_t max_cycles, int64_t *energy_out,
+                           int32_t *cycles_out);
+
+/* The label-partitioned estimation of Sec. IV-A: n_threads host threads
+ * each run ivde_expansion over their subset of the levels (IVDE_PARTITION_*),
+ * starting from each row's lowest-unary level of the subset; then results
+ * merge pairwise (k with k + 2^c in cycle c, ceil(log2 n) cycles), each merge
+ * an expansion over both subsets in which a row may only take one of its
+ * two candidate labels, starting from the lower-energy input.  The result
+ * does not depend on thread timing.  labels_out: host int32 [rows]. */
+ivde_status ivde_optimize(const ivde_energy *energy, int32_t n_threads, int32_t partition,
+                          int32_t max_cycles, int32_t *labels_out, int64_t *energy_out);
+
 /* ---------------------------------------------------------------- tuning */
 
 /* Times every (labels_per_lane, waves_per_group) launch shape on the given

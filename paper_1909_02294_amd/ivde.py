@@ -69,6 +69,16 @@ class FrameStats(ctypes.Structure):
                 ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double), ("done_us", ctypes.c_double)]
 
 
+class EnergyDesc(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("num_labels", ctypes.c_int32), ("unary", ctypes.c_void_p),
+                ("window_m", ctypes.c_void_p), ("window_hit", ctypes.c_void_p), ("K", ctypes.c_float),
+                ("adj_offsets", ctypes.c_void_p), ("adj_index", ctypes.c_void_p), ("adj_beta", ctypes.c_void_p),
+                ("fixed_labels", ctypes.c_void_p), ("quantum", ctypes.c_double)]
+
+
+PARTITION_BLOCKS, PARTITION_INTERLEAVED = 0, 1
+
+
 # every symbol include/ivde.h declares, with its ctypes signature
 _P = ctypes.c_void_p
 _I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -98,6 +108,9 @@ SIGNATURES = {
     "ivde_adjacency_size": (_I32, [_I32, _P, _P, _I32, _P]),
     "ivde_adjacency": (_I32, [_I32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
     "ivde_intra_cost": (_I32, [_I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "ivde_energy_value": (_I32, [_P, _P, _P]),
+    "ivde_expansion": (_I32, [_P, _P, _P, _I32, _I32, _P, _P]),
+    "ivde_optimize": (_I32, [_P, _I32, _I32, _I32, _P, _P]),
     "ivde_temporal_rule": (_I32, [_I64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _I32, _P, _P]),
     "ivde_window_cost_size": (_I32, [_I32, _P, _P, _P, _I32, _P, _P]),
     "ivde_window_cost": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
@@ -562,3 +575,48 @@ def intra_cost(offsets, index, beta, labelling, num_labels: int, fixed=None, str
                                  ctypes.c_void_p(fixed.data_ptr()) if fixed is not None else None,
                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+class Energy:
+    """Host-side Eq. (1) (ivde_energy): numpy arrays or CPU tensors, kept
+    alive by this object while the library reads them."""
+
+    def __init__(self, rows, num_labels, unary=None, m=None, hit=None, K=30.0, offsets=None, index=None,
+                 beta=None, fixed=None, quantum=1024.0):
+        def host(a, dt):
+            if a is None:
+                return None
+            if hasattr(a, "detach"):
+                a = a.detach().cpu().numpy()
+            return np.ascontiguousarray(a, dt)
+
+        self._keep = [host(unary, np.float32), host(m, np.float32), host(hit, np.int32), host(offsets, np.int64),
+                      host(index, np.int32), host(beta, np.float32), host(fixed, np.int32)]
+        u, mm, h, o, i, b, f = self._keep
+        ptr = lambda a: a.ctypes.data if a is not None else None  # noqa: E731
+        self.desc = EnergyDesc(int(rows), int(num_labels), ptr(u), ptr(mm), ptr(h), float(K), ptr(o), ptr(i),
+                               ptr(b), ptr(f), float(quantum))
+        self.rows, self.num_labels = int(rows), int(num_labels)
+
+    def value(self, labels) -> int:
+        d = np.ascontiguousarray(labels, np.int32)
+        e = ctypes.c_int64()
+        check(load().ivde_energy_value(ctypes.byref(self.desc), d.ctypes.data, ctypes.byref(e)))
+        return e.value
+
+    def expansion(self, labels, label_list, max_cycles=8):
+        """(labels, energy, cycles) after alpha-expansion from `labels`."""
+        d = np.array(labels, np.int32)
+        ls = np.ascontiguousarray(label_list, np.int32)
+        e, c = ctypes.c_int64(), ctypes.c_int32()
+        check(load().ivde_expansion(ctypes.byref(self.desc), d.ctypes.data, ls.ctypes.data, len(ls), int(max_cycles),
+                                    ctypes.byref(e), ctypes.byref(c)))
+        return d, e.value, c.value
+
+    def optimize(self, n_threads=1, partition=PARTITION_BLOCKS, max_cycles=8):
+        """(labels, energy) of the label-partitioned estimation."""
+        d = np.empty(self.rows, np.int32)
+        e = ctypes.c_int64()
+        check(load().ivde_optimize(ctypes.byref(self.desc), int(n_threads), int(partition), int(max_cycles),
+                                   d.ctypes.data, ctypes.byref(e)))
+        return d, e.value

@@ -155,3 +155,38 @@ def islands_problem(seed, width=160, height=96, n_islands=300):
     Y, U, V = random_images(rng, cams, 8, 0)
     return SimpleNamespace(cams=cams, Y=Y, U=U, V=V, seg=seg, S=S, bit_depth=8, chroma_shift=0,
                            z_near=1.0, z_far=3.0, num_labels=6)
+
+
+def random_energy_terms(seed, rows=9, L=4, p_hit=0.6, adj=True, unary=True, fixed=None, quantum=64.0,
+                        m_high=60.0):
+    """Terms of a random Eq. (1) instance: two views of rows/2 segments,
+    window hits into the other view, random adjacency inside each view,
+    weights and values exact in FP32."""
+    rng = np.random.default_rng(seed)
+    half = rows // 2
+    view = np.array([0] * half + [1] * (rows - half))
+    hit = np.full((rows, 2, L), -1, np.int32)
+    m = rng.uniform(0, m_high, (rows, 2, L)).astype(np.float32)
+    for r in range(rows):
+        others = np.nonzero(view != view[r])[0]
+        slot = 1 if view[r] == 0 else 0
+        take = rng.random(L) < p_hit
+        hit[r, slot, take] = rng.choice(others, int(take.sum()))
+    U = rng.uniform(0, 20, (rows, L)).astype(np.float32) if unary else None
+    off = idx = beta = None
+    if adj:
+        lists = [[] for _ in range(rows)]
+        w = {}
+        for v in (0, 1):
+            ids = np.nonzero(view == v)[0]
+            for a in ids:
+                for b in ids:
+                    if a < b and rng.random() < min(1.0, 4.0 / max(1, len(ids))):
+                        lists[a].append(b)
+                        lists[b].append(a)
+                        w[(a, b)] = w[(b, a)] = np.float32(rng.uniform(0.5, 8))
+        off = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int64)
+        idx = np.array([t for r in range(rows) for t in sorted(lists[r])], np.int32)
+        beta = np.array([w[(r, t)] for r in range(rows) for t in sorted(lists[r])], np.float32)
+    return dict(rows=rows, num_labels=L, unary=U, m=m, hit=hit, K=30.0, offsets=off, index=idx, beta=beta,
+                fixed=fixed, quantum=quantum)

@@ -52,6 +52,7 @@ int main(void) {
          sizeof(ivde_server_config), sizeof(ivde_frame_stats));
   printf("%zu %zu %zu %zu\\n", offsetof(ivde_options, target_mask), offsetof(ivde_options, sweep_events),
          offsetof(ivde_frame, labels), offsetof(ivde_frame_stats, submit_us));
+  printf("%zu %zu %zu\\n", sizeof(ivde_energy), offsetof(ivde_energy, K), offsetof(ivde_energy, quantum));
   return 0;
 }
 """)
@@ -62,6 +63,7 @@ int main(void) {
                                        ivde.Options, ivde.Frame, ivde.ServerConfig, ivde.FrameStats)]
     want += [ivde.Options.target_mask.offset, ivde.Options.sweep_events.offset, ivde.Frame.labels.offset,
              ivde.FrameStats.submit_us.offset]
+    want += [ctypes.sizeof(ivde.EnergyDesc), ivde.EnergyDesc.K.offset, ivde.EnergyDesc.quantum.offset]
     assert [int(x) for x in got] == want
 
 

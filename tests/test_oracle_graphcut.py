@@ -33,39 +33,9 @@ def test_quantize_rounds_half_away_from_zero():
 
 
 def random_energy(seed, rows=9, L=4, p_hit=0.6, adj=True, unary=True, fixed=None):
-    """A random instance: two 'views' of rows/2 segments, hits into the
-    other view, random adjacency inside each view."""
-    rng = np.random.default_rng(seed)
-    half = rows // 2
-    view = np.array([0] * half + [1] * (rows - half))
-    hit = np.full((rows, 2, L), -1, np.int64)
-    m = rng.uniform(0, 60, (rows, 2, L)).astype(np.float32)
-    for r in range(rows):
-        others = np.nonzero(view != view[r])[0]
-        slot = 1 if view[r] == 0 else 0
-        for l in range(L):
-            if rng.random() < p_hit:
-                hit[r, slot, l] = rng.choice(others)
-    U = rng.uniform(0, 20, (rows, L)).astype(np.float32) if unary else None
-    off = idx = beta = None
-    if adj:
-        pairs = set()
-        for v in (0, 1):
-            ids = np.nonzero(view == v)[0]
-            for a, b in itertools.combinations(ids, 2):
-                if rng.random() < 0.5:
-                    pairs.add((a, b))
-        lists = [[] for _ in range(rows)]
-        w = {}
-        for a, b in pairs:
-            lists[a].append(b)
-            lists[b].append(a)
-            w[(a, b)] = w[(b, a)] = float(np.float32(rng.uniform(0.5, 8)))
-        off = np.concatenate([[0], np.cumsum([len(x) for x in lists])])
-        idx = np.array([t for r in range(rows) for t in sorted(lists[r])], np.int64)
-        beta = np.array([w[(r, t)] for r in range(rows) for t in sorted(lists[r])], np.float32)
-    return G.Energy(rows, L, unary=U, m=m, hit=hit, K=30.0, offsets=off, index=idx, beta=beta, quantum=64.0,
-                    fixed=fixed)
+    t = P.random_energy_terms(seed, rows, L, p_hit, adj, unary, fixed)
+    return G.Energy(t["rows"], t["num_labels"], unary=t["unary"], m=t["m"], hit=t["hit"], K=t["K"],
+                    offsets=t["offsets"], index=t["index"], beta=t["beta"], quantum=t["quantum"], fixed=t["fixed"])
 
 
 @pytest.mark.parametrize("seed", range(6))
