@@ -388,11 +388,24 @@ ivde_status ivde_intra_cost(int64_t rows, int32_t num_labels, const int64_t *off
                             const int32_t *index, const float *beta, const int32_t *labelling,
                             const uint8_t *fixed, float *out, ivde_stream stream);
 
+/* ---------------------------------------------------------------- depth maps */
+
+/* Per-pixel depth maps from segment levels (Sec. III-B: a segment's depth
+ * is painted onto its pixels).  label_of_row: device int32 [rows] (rows
+ * ordered as in ivde_cost_volume); depth_out: device float, the views one
+ * after another, each W x H in rows of W.  A pixel gets the depth of its
+ * segment's level, 1 / (1/z_far + l/(L-1) (1/z_near - 1/z_far)) in FP64
+ * stored as FP32, or NaN for a segment id or level out of range.  Only
+ * sizes are read from cams. */
+ivde_status ivde_depth_map(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
+                           const ivde_label_range *labels, const int32_t *label_of_row,
+                           float *depth_out, ivde_stream stream);
+
 /* ---------------------------------------------------------------- depth optimisation (host) */
 
 /* Eq. (1) over segment nodes, in host memory.  With d the label of every
  * row and q(x) = x * quantum rounded half away from zero:
- *   E(d) = sum_r q(unary[r][d_r])
+ *   E(d) = sum_r q(unary_weight * unary[r][d_r])
  *        + sum_r sum_slot [h >= 0 and d_h = d_r] q(min(0, m - K)),
  *              m = window_m[r][slot][d_r], h = window_hit[r][slot][d_r]  (Eq. (5))
  *        + sum over adjacency entries (r, t) of q(beta) |d_r - d_t|       (Eq. (2))
@@ -406,6 +419,7 @@ typedef struct ivde_energy {
     int64_t rows;
     int32_t num_labels;
     const float *unary;            /* [rows][num_labels] or NULL */
+    double unary_weight;           /* multiplies unary before rounding */
     const float *window_m;         /* [rows][2][num_labels] or NULL */
     const int32_t *window_hit;     /* [rows][2][num_labels], -1 = no match; with window_m */
     float K;                       /* Eq. (5) truncation; the paper uses 30 */

@@ -415,3 +415,26 @@ def intra_energy(offsets, index, beta, labelling):
     s = edge_rows(offsets)
     t = np.asarray(index, np.int64)
     return float(np.sum(np.asarray(beta, np.float64) * np.abs(d[s] - d[t])))
+
+
+# ---------------------------------------------------------------- depth maps
+
+def level_depths(z_near, z_far, num_labels):
+    """The depth of each level: uniform in inverse depth, level 0 at z_far
+    and level L - 1 at z_near (a single level sits at z_far)."""
+    L = int(num_labels)
+    out = np.empty(L)
+    for l in range(L):
+        frac = l / (L - 1) if L > 1 else 0.0
+        out[l] = 1.0 / (1.0 / z_far + frac * (1.0 / z_near - 1.0 / z_far))
+    return out
+
+
+def depth_map(pb: Problem, labels):
+    """Per-pixel depth maps of all views (Sec. III-B: segment depths are
+    painted onto their pixels): view v's pixel (x, y) gets the depth of the
+    level of its segment's row; concatenated view after view, rows of W."""
+    z = level_depths(pb.z_near, pb.z_far, pb.num_labels)
+    off = pb.row_offsets()
+    lab = np.asarray(labels, np.int64)
+    return np.concatenate([z[lab[off[v] + pb.seg[v].astype(np.int64)]].ravel() for v in range(pb.n_views)])

@@ -7,7 +7,7 @@ written for checking by eye.
 
 Energy of a labelling d (one label per segment row), in integer units:
 
-    E(d) = sum_r q(U[r, d_r])                                   optional unary
+    E(d) = sum_r q(w U[r, d_r])                                 optional unary, weight w
          + sum_r sum_slot [h >= 0 and d_h = d_r] q(min(0, m - K))   Eqs. (4), (5)
                with m = m[r, slot, d_r], h = hit[r, slot, d_r]
          + sum over adjacency entries (r, t) of q(beta_rt) |d_r - d_t|   Eqs. (2), (3)
@@ -52,9 +52,12 @@ class Energy:
     """
 
     def __init__(self, rows, num_labels, unary=None, m=None, hit=None, K=30.0, offsets=None, index=None,
-                 beta=None, quantum=1024.0, fixed=None):
+                 beta=None, quantum=1024.0, fixed=None, unary_weight=1.0):
         self.rows, self.L = int(rows), int(num_labels)
-        self.U = quantize(unary, quantum) if unary is not None else np.zeros((self.rows, self.L), np.int64)
+        if unary is not None:
+            self.U = quantize(float(unary_weight) * np.asarray(unary, np.float32).astype(np.float64), quantum)
+        else:
+            self.U = np.zeros((self.rows, self.L), np.int64)
         if m is not None:
             m64 = np.asarray(m, np.float32).astype(np.float64)
             self.hit = np.asarray(hit, np.int64)

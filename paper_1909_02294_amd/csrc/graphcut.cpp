@@ -576,14 +576,18 @@ ivde_status build_model(const ivde_energy *E, Model &M)
     M.rows = rows;
     M.L = L;
     if (E->unary) {
+        if (!std::isfinite(E->unary_weight)) {
+            set_error("energy: unary_weight must be finite");
+            return IVDE_EINVAL;
+        }
         M.U.resize((size_t)rows * L);
         for (size_t i = 0; i < M.U.size(); ++i) {
-            const double v = (double)E->unary[i] * q;
-            if (!(std::fabs(v) < limit)) {
-                set_error("energy: unary value %g too large for quantum %g", (double)E->unary[i], q);
+            const double u = E->unary_weight * (double)E->unary[i];
+            if (!(std::fabs(u * q) < limit)) {
+                set_error("energy: unary value %g too large for quantum %g", u, q);
                 return IVDE_EINVAL;
             }
-            M.U[i] = quantize(E->unary[i], q);
+            M.U[i] = quantize(u, q);
         }
     }
     if (E->window_m) {

@@ -114,6 +114,16 @@ hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write,
 hipError_t launch_scan_rows(int64_t *a, int64_t n, int64_t *block_sums, hipStream_t s);
 hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const int32_t *index, const float *beta,
                              const int32_t *labelling, const uint8_t *fixed, float *out, hipStream_t s);
+// Views of a depth painting: caller's segment maps and output offsets.
+struct PaintViews {
+    const int32_t *seg[kMaxViews];
+    int64_t pitch[kMaxViews];
+    int64_t row0[kMaxViews];
+    int64_t out0[kMaxViews];
+    int32_t W[kMaxViews], H[kMaxViews], S[kMaxViews];
+};
+hipError_t launch_paint_depth(const PaintViews &pv, int n_views, int max_pixels, const int32_t *labels, int L,
+                              double z_near, double z_far, float *out, hipStream_t s);
 hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
                          float *m_out, int32_t *hit_out, hipStream_t s);
 hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32_t *hit, const int32_t *labelling,

@@ -2,6 +2,8 @@
 // statistics (centre and mean colour), the window matching core of
 // Sec. III-C (Eqs. (4), (5)), the temporal rule of Sec. III-E and the
 // intra-view term of Sec. III-D (Eqs. (2), (3)).
+#include <algorithm>
+
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -392,6 +394,35 @@ __global__ __launch_bounds__(256) void k_intra_cost(int64_t rows, int L, int n_l
     if (l < L) out[r * L + l] = acc;
 }
 
+
+// ------------------------------------------------------------------ depth maps
+// Sec. III-B: each pixel takes the depth of its segment's level.  The level
+// depth 1 / (1 / z_far + l / (L - 1) (1 / z_near - 1 / z_far)) is formed in
+// FP64 with one rounding per operation (no contraction) and stored as FP32;
+// NaN marks an out-of-range segment id or level.
+__global__ __launch_bounds__(256) void k_paint_depth(PaintViews pv, const int32_t *__restrict__ labels, int L,
+                                                     double z_near, double z_far, float *__restrict__ out)
+{
+    const int v = blockIdx.y;
+    const int W = pv.W[v], H = pv.H[v], S = pv.S[v];
+    const int64_t n = (int64_t)W * H;
+    const double inv_far = __ddiv_rn(1.0, z_far);
+    const double span = __dsub_rn(__ddiv_rn(1.0, z_near), inv_far);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / W, x = i - y * W;
+        const int s = pv.seg[v][y * pv.pitch[v] + x];
+        float z = __builtin_nanf("");
+        if (s >= 0 && s < S) {
+            const int l = labels[pv.row0[v] + s];
+            if (l >= 0 && l < L) {
+                const double frac = L > 1 ? __ddiv_rn((double)l, (double)(L - 1)) : 0.0;
+                z = (float)__ddiv_rn(1.0, __dadd_rn(inv_far, __dmul_rn(frac, span)));
+            }
+        }
+        out[pv.out0[v] + i] = z;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, int32_t *count_flat, hipStream_t s)
@@ -487,6 +518,15 @@ hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const 
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_intra_cost, dim3((unsigned)blocks), dim3(256), 0, s, rows, L, nb, offsets, index, beta,
                        labelling, fixed, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_paint_depth(const PaintViews &pv, int n_views, int max_pixels, const int32_t *labels, int L,
+                              double z_near, double z_far, float *out, hipStream_t s)
+{
+    if (n_views <= 0 || max_pixels <= 0) return hipSuccess;
+    const unsigned bx = (unsigned)std::min<int64_t>(((int64_t)max_pixels + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_paint_depth, dim3(bx, (unsigned)n_views), dim3(256), 0, s, pv, labels, L, z_near, z_far, out);
     return hipGetLastError();
 }
 

@@ -71,7 +71,7 @@ class FrameStats(ctypes.Structure):
 
 class EnergyDesc(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int64), ("num_labels", ctypes.c_int32), ("unary", ctypes.c_void_p),
-                ("window_m", ctypes.c_void_p), ("window_hit", ctypes.c_void_p), ("K", ctypes.c_float),
+                ("unary_weight", ctypes.c_double), ("window_m", ctypes.c_void_p), ("window_hit", ctypes.c_void_p), ("K", ctypes.c_float),
                 ("adj_offsets", ctypes.c_void_p), ("adj_index", ctypes.c_void_p), ("adj_beta", ctypes.c_void_p),
                 ("fixed_labels", ctypes.c_void_p), ("quantum", ctypes.c_double)]
 
@@ -108,6 +108,7 @@ SIGNATURES = {
     "ivde_adjacency_size": (_I32, [_I32, _P, _P, _I32, _P]),
     "ivde_adjacency": (_I32, [_I32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
     "ivde_intra_cost": (_I32, [_I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "ivde_depth_map": (_I32, [_I32, _P, _P, _P, _P, _P, _P]),
     "ivde_energy_value": (_I32, [_P, _P, _P]),
     "ivde_expansion": (_I32, [_P, _P, _P, _I32, _I32, _P, _P]),
     "ivde_optimize": (_I32, [_P, _I32, _I32, _I32, _P, _P]),
@@ -582,7 +583,7 @@ class Energy:
     alive by this object while the library reads them."""
 
     def __init__(self, rows, num_labels, unary=None, m=None, hit=None, K=30.0, offsets=None, index=None,
-                 beta=None, fixed=None, quantum=1024.0):
+                 beta=None, fixed=None, quantum=1024.0, unary_weight=1.0):
         def host(a, dt):
             if a is None:
                 return None
@@ -594,8 +595,8 @@ class Energy:
                       host(index, np.int32), host(beta, np.float32), host(fixed, np.int32)]
         u, mm, h, o, i, b, f = self._keep
         ptr = lambda a: a.ctypes.data if a is not None else None  # noqa: E731
-        self.desc = EnergyDesc(int(rows), int(num_labels), ptr(u), ptr(mm), ptr(h), float(K), ptr(o), ptr(i),
-                               ptr(b), ptr(f), float(quantum))
+        self.desc = EnergyDesc(int(rows), int(num_labels), ptr(u), float(unary_weight), ptr(mm), ptr(h), float(K),
+                               ptr(o), ptr(i), ptr(b), ptr(f), float(quantum))
         self.rows, self.num_labels = int(rows), int(num_labels)
 
     def value(self, labels) -> int:
@@ -620,3 +621,14 @@ class Energy:
         check(load().ivde_optimize(ctypes.byref(self.desc), int(n_threads), int(partition), int(max_cycles),
                                    d.ctypes.data, ctypes.byref(e)))
         return d, e.value
+
+
+def depth_map(dv: DeviceViews, lr: LabelRange, labels, stream=None):
+    """ivde_depth_map: float32 [sum of W * H] depth maps, view after view."""
+    torch = _torch()
+    n_px = sum(int(c.width) * int(c.height) for c in dv.c_cams)
+    out = torch.empty(n_px, dtype=torch.float32, device="cuda")
+    lab = labels if hasattr(labels, "data_ptr") else torch.from_numpy(np.ascontiguousarray(labels, np.int32)).cuda()
+    check(load().ivde_depth_map(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.c_void_p(lab.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out

@@ -462,6 +462,48 @@ def make_cfg2_frames(n_frames=16, seed=None, width=1920, height=1080, n_views=8,
     return out
 
 
+def true_depth(wl: Workload, view: int):
+    """Ground-truth depth of every pixel of a rendered view, measured from
+    the rig's reference plane (mean centre, mean axis) like the depth
+    levels; NaN where no plane is visible."""
+    cam = wl.cams[view]
+    pid = wl.plane_ids[view]
+    planes = wl.info["planes"]
+    Cr, nr = rig_reference(wl.cams)
+    d = _pixel_rays(cam, 0, cam.width, 0, cam.height)
+    C = cam.center
+    out = np.full(pid.shape, np.nan)
+    for k, pl in enumerate(planes):
+        m = pid == k
+        if not m.any():
+            continue
+        dk = d[m]
+        tt = float((pl.origin - C) @ pl.normal) / (dk @ pl.normal)
+        out[m] = (C[None, :] + tt[:, None] * dk - Cr[None, :]) @ nr
+    return out
+
+
+def truth_labels(wl: Workload):
+    """Reference levels of a rendered workload: each segment's median
+    ground-truth depth mapped to the nearest level in inverse depth (levels
+    uniform in 1/z, level 0 at z_far), clipped to the range."""
+    L = wl.num_labels
+    inv_far, inv_near = 1.0 / wl.z_far, 1.0 / wl.z_near
+    out = []
+    for v in range(wl.n_views):
+        z = true_depth(wl, v).ravel()
+        seg = wl.seg[v].ravel()
+        order = np.argsort(seg, kind="stable")
+        bounds = np.searchsorted(seg[order], np.arange(wl.S[v] + 1))
+        med = np.full(wl.S[v], np.nan)
+        for s in range(wl.S[v]):
+            if bounds[s + 1] > bounds[s]:
+                med[s] = np.nanmedian(z[order[bounds[s]:bounds[s + 1]]])
+        lab = np.rint((1.0 / med - inv_far) / (inv_near - inv_far) * (L - 1))
+        out.append(np.clip(np.nan_to_num(lab, nan=0.0), 0, L - 1).astype(np.int32))
+    return np.concatenate(out)
+
+
 # --------------------------------------------------------------------------
 # sequences with temporal change (serving)
 # --------------------------------------------------------------------------

@@ -15,10 +15,13 @@ from tests import _problems as P
 
 
 def _both(t):
+    w = t.get("unary_weight", 1.0)
     o = G.Energy(t["rows"], t["num_labels"], unary=t["unary"], m=t["m"], hit=t["hit"], K=t["K"],
-                 offsets=t["offsets"], index=t["index"], beta=t["beta"], quantum=t["quantum"], fixed=t["fixed"])
+                 offsets=t["offsets"], index=t["index"], beta=t["beta"], quantum=t["quantum"], fixed=t["fixed"],
+                 unary_weight=w)
     h = ivde.Energy(t["rows"], t["num_labels"], unary=t["unary"], m=t["m"], hit=t["hit"], K=t["K"],
-                    offsets=t["offsets"], index=t["index"], beta=t["beta"], fixed=t["fixed"], quantum=t["quantum"])
+                    offsets=t["offsets"], index=t["index"], beta=t["beta"], fixed=t["fixed"], quantum=t["quantum"],
+                    unary_weight=w)
     return o, h
 
 
@@ -80,6 +83,18 @@ def test_optimize_identical(n, partition):
     d_h, e_h = h.optimize(n, partition)
     np.testing.assert_array_equal(d_h, d_o)
     assert e_h == e_o == h.value(d_h)
+
+
+def test_unary_weight():
+    t = P.random_energy_terms(61, rows=30, L=6)
+    t["unary_weight"] = 2.75
+    o, h = _both(t)
+    d_o, e_o = o.optimize(2, ivde.PARTITION_INTERLEAVED)
+    d_h, e_h = h.optimize(2, ivde.PARTITION_INTERLEAVED)
+    np.testing.assert_array_equal(d_h, d_o)
+    assert e_h == e_o
+    t1 = dict(t, unary_weight=1.0)
+    assert h.value(d_h) != _both(t1)[1].value(d_h)
 
 
 def test_optimize_larger_instance():
