@@ -16,6 +16,7 @@ Inputs are resident in HBM before the timed region.  Prints one JSON line.
   --mode copycal  a device copy of known size (calibrates HBM counters)
   --mode window   the paper's own 3x3 centre-window term
   --mode intra    the intra-view term: adjacency, weights, per-label costs
+  --mode depth    depth maps end to end (GPU terms, host graph cut, painting)
 """
 from __future__ import annotations
 
@@ -279,6 +280,52 @@ def bench_intra(args):
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}}
 
 
+def bench_depth(args):
+    """Depth maps end to end (Sec. III): the energy terms on the GPU, Eq. (1)
+    minimised on the host by label-partitioned alpha-expansion (Sec. IV-A),
+    segment depths painted on the GPU.  --depth-config paper is the paper's
+    HD setting (5 views 1920x1080, 100000 segments per view, 250 levels, the
+    window and intra-view terms only); cfg1 is the 8-view 1080p workload with
+    the whole-segment cost as an extra unary term."""
+    import torch
+    from paper_1909_02294_amd import ivde, pipeline, synth
+
+    if args.depth_config == "paper":
+        wl = synth.make_arc_workload("paper-hd-5x1920x1080", synth.config_seed(5), n_views=5,
+                                     arc_deg=30.0 * 4 / 7, n_segments=100000, num_labels=250)
+        kw = dict(unary_weight=0.0)
+    else:
+        wl = synth.make_cfg1()
+        kw = {}
+    threads = args.threads or min(16, os.cpu_count() or 1)
+    dv = ivde.DeviceViews.from_workload(wl)
+    lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
+    print(f"[bench] depth: {wl.name}, {dv.rows} segments, {wl.num_labels} levels, {threads} host threads",
+          file=sys.stderr, flush=True)
+    runs = []
+    for k in range(max(1, args.steps)):
+        res = pipeline.estimate_depth(dv, lr, n_threads=threads, **kw)
+        runs.append(res)
+        print(f"[bench] run {k}: {res['times']}", file=sys.stderr, flush=True)
+    truth = synth.truth_labels(wl)
+    best = min(runs, key=lambda r: r["times"]["total"])
+    quality = {"cut_within_2_levels": float(np.mean(np.abs(best["labels"] - truth) <= 2))}
+    if best["cost"] is not None:
+        wta = ivde.argmin(best["cost"]).cpu().numpy()
+        quality["winner_take_all_within_2_levels"] = float(np.mean(np.abs(wta - truth) <= 2))
+    tot = best["times"]["total"]
+    return {"metric": "depth estimation time per frame (all views)", "value": tot, "unit": "s",
+            "n_gpus": 1, "steps": len(runs), "warmup": 0, "ms_per_step": tot * 1e3, "higher_is_better": False,
+            "dtype": "f32 terms, int64 energies", "data": "synthetic",
+            "config": {"workload": f"{wl.name}: {wl.n_views} views {wl.cams[0].width}x{wl.cams[0].height}, "
+                                   f"{wl.S[0]} segments per view, {wl.num_labels} levels",
+                       "energy": "window (Eq. 4, 5) + intra-view (Eq. 2, 3)" +
+                                 (" + whole-segment cost as unary" if kw.get("unary_weight", 1) else ""),
+                       "host_threads": threads, "partition": "interleaved"},
+            "per_view_s": tot / wl.n_views, "stage_s": best["times"], "energy": best["energy"],
+            "quality": quality}
+
+
 def copy_calibration(args):
     """A plain device copy of known size (read n bytes, write n bytes per
     dispatch): what the HBM counters read for it scales the sweep's counts."""
@@ -301,7 +348,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window", "intra"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window", "intra", "depth"], default="plain")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--labels-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
@@ -310,6 +357,8 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=4.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--gop", type=int, default=0, help="served: every GOP-th frame of a rig is an I frame")
+    ap.add_argument("--depth-config", choices=["cfg1", "paper"], default="cfg1")
+    ap.add_argument("--threads", type=int, default=0, help="depth: host threads (default min(16, cores))")
     ap.add_argument("--rule", action="store_true",
                     help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")
     args = ap.parse_args()
@@ -330,6 +379,8 @@ def main():
         out = bench_window(args)
     elif args.mode == "intra":
         out = bench_intra(args)
+    elif args.mode == "depth":
+        out = bench_depth(args)
     elif args.mode == "batched":
         from paper_1909_02294_amd import benchforms
         out = benchforms.bench_batched(args)

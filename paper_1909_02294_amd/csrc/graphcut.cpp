@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <thread>
 #include <vector>
 
@@ -33,11 +34,8 @@ public:
     void reset(int n)
     {
         n_ = n;
-        first_.assign(n, -1);
         tr_.assign(n, 0);
-        head_.clear();
-        next_.clear();
-        rcap_.clear();
+        edges_.clear();
         flow_ = 0;
     }
     // cap_source: cost of putting i on the sink side; cap_sink: on the source side
@@ -48,25 +46,18 @@ public:
         tr_[i] += (cap_source - d) - (cap_sink - d);
     }
     // arc i->j of capacity c (cut when i is on the source side, j on the sink side)
-    void add_edge(int i, int j, int64_t c)
-    {
-        const int a = (int)head_.size();
-        head_.push_back(j);
-        next_.push_back(first_[i]);
-        rcap_.push_back(c);
-        first_[i] = a;
-        head_.push_back(i);
-        next_.push_back(first_[j]);
-        rcap_.push_back(0);
-        first_[j] = a + 1;
-    }
+    void add_edge(int i, int j, int64_t c) { edges_.push_back({i, j, c}); }
     int64_t solve();
     // nodes reachable from the source in the residual graph
     void source_side(std::vector<uint8_t> &out) const;
 
 private:
+    struct Edge {
+        int i, j;
+        int64_t c;
+    };
     static constexpr int kTerminal = -2, kOrphan = -3, kNone = -1;
-    static int sister(int a) { return a ^ 1; }
+    void build_arcs();
     void set_active(int i)
     {
         if (!queued_[i]) {
@@ -78,19 +69,47 @@ private:
     void adopt();
 
     int n_ = 0;
-    std::vector<int> first_, head_, next_;
+    std::vector<Edge> edges_;
+    // arcs in CSR order: node i owns [first_[i], first_[i + 1])
+    std::vector<int> first_, head_, sister_;
     std::vector<int64_t> rcap_, tr_;
     int64_t flow_ = 0;
     // search state
     std::vector<int> parent_, ts_, dist_;
     std::vector<uint8_t> sink_, queued_;
-    std::vector<int> queue_, orphans_;
+    std::vector<int> queue_;
+    std::deque<int> orphans_;   // taken from the front; freed nodes' children join at the back
     size_t qhead_ = 0;
     int time_ = 0;
 };
 
+void MaxFlow::build_arcs()
+{
+    first_.assign(n_ + 1, 0);
+    for (const Edge &e : edges_) {
+        ++first_[e.i + 1];
+        ++first_[e.j + 1];
+    }
+    for (int i = 0; i < n_; ++i) first_[i + 1] += first_[i];
+    const size_t na = 2 * edges_.size();
+    head_.resize(na);
+    sister_.resize(na);
+    rcap_.resize(na);
+    std::vector<int> pos(first_.begin(), first_.end() - 1);
+    for (const Edge &e : edges_) {
+        const int a = pos[e.i]++, b = pos[e.j]++;
+        head_[a] = e.j;
+        rcap_[a] = e.c;
+        sister_[a] = b;
+        head_[b] = e.i;
+        rcap_[b] = 0;
+        sister_[b] = a;
+    }
+}
+
 int64_t MaxFlow::solve()
 {
+    build_arcs();
     parent_.assign(n_, kNone);
     ts_.assign(n_, 0);
     dist_.assign(n_, 0);
@@ -101,14 +120,9 @@ int64_t MaxFlow::solve()
     orphans_.clear();
     time_ = 0;
     for (int i = 0; i < n_; ++i) {
-        if (tr_[i] > 0) {
+        if (tr_[i] != 0) {
             parent_[i] = kTerminal;
-            sink_[i] = 0;
-            dist_[i] = 1;
-            set_active(i);
-        } else if (tr_[i] < 0) {
-            parent_[i] = kTerminal;
-            sink_[i] = 1;
+            sink_[i] = tr_[i] < 0;
             dist_[i] = 1;
             set_active(i);
         }
@@ -135,13 +149,14 @@ int64_t MaxFlow::solve()
         }
         // growth
         int mid = -1;
+        const int a0 = first_[i], a1 = first_[i + 1];
         if (!sink_[i]) {
-            for (int a = first_[i]; a >= 0; a = next_[a]) {
+            for (int a = a0; a < a1; ++a) {
                 if (rcap_[a] <= 0) continue;
                 const int j = head_[a];
                 if (parent_[j] == kNone) {
                     sink_[j] = 0;
-                    parent_[j] = sister(a);
+                    parent_[j] = sister_[a];
                     ts_[j] = ts_[i];
                     dist_[j] = dist_[i] + 1;
                     set_active(j);
@@ -149,26 +164,26 @@ int64_t MaxFlow::solve()
                     mid = a;
                     break;
                 } else if (ts_[j] <= ts_[i] && dist_[j] > dist_[i]) {
-                    parent_[j] = sister(a);
+                    parent_[j] = sister_[a];
                     ts_[j] = ts_[i];
                     dist_[j] = dist_[i] + 1;
                 }
             }
         } else {
-            for (int a = first_[i]; a >= 0; a = next_[a]) {
-                if (rcap_[sister(a)] <= 0) continue;
+            for (int a = a0; a < a1; ++a) {
+                if (rcap_[sister_[a]] <= 0) continue;
                 const int j = head_[a];
                 if (parent_[j] == kNone) {
                     sink_[j] = 1;
-                    parent_[j] = sister(a);
+                    parent_[j] = sister_[a];
                     ts_[j] = ts_[i];
                     dist_[j] = dist_[i] + 1;
                     set_active(j);
                 } else if (!sink_[j]) {
-                    mid = sister(a);
+                    mid = sister_[a];
                     break;
                 } else if (ts_[j] <= ts_[i] && dist_[j] > dist_[i]) {
-                    parent_[j] = sister(a);
+                    parent_[j] = sister_[a];
                     ts_[j] = ts_[i];
                     dist_[j] = dist_[i] + 1;
                 }
@@ -185,14 +200,15 @@ int64_t MaxFlow::solve()
 }
 
 // Push the bottleneck along source -> ... -> tail(mid) -> head(mid) -> ... -> sink.
+// A node's parent arc leads from the node towards its tree's root.
 void MaxFlow::augment(int mid)
 {
     int64_t b = rcap_[mid];
     int i;
-    for (i = head_[sister(mid)];; i = head_[parent_[i]]) {
+    for (i = head_[sister_[mid]];; i = head_[parent_[i]]) {
         const int a = parent_[i];
         if (a == kTerminal) break;
-        b = std::min(b, rcap_[sister(a)]);
+        b = std::min(b, rcap_[sister_[a]]);
     }
     b = std::min(b, tr_[i]);
     for (i = head_[mid];; i = head_[parent_[i]]) {
@@ -202,24 +218,24 @@ void MaxFlow::augment(int mid)
     }
     b = std::min(b, -tr_[i]);
 
-    rcap_[sister(mid)] += b;
+    rcap_[sister_[mid]] += b;
     rcap_[mid] -= b;
-    for (i = head_[sister(mid)];;) {
+    for (i = head_[sister_[mid]];;) {
         const int a = parent_[i];
         if (a == kTerminal) {
             tr_[i] -= b;
             if (tr_[i] == 0) {
                 parent_[i] = kOrphan;
-                orphans_.push_back(i);
+                orphans_.push_front(i);
             }
             break;
         }
         rcap_[a] += b;
-        rcap_[sister(a)] -= b;
+        rcap_[sister_[a]] -= b;
         const int up = head_[a];
-        if (rcap_[sister(a)] == 0) {
+        if (rcap_[sister_[a]] == 0) {
             parent_[i] = kOrphan;
-            orphans_.push_back(i);
+            orphans_.push_front(i);
         }
         i = up;
     }
@@ -229,16 +245,16 @@ void MaxFlow::augment(int mid)
             tr_[i] += b;
             if (tr_[i] == 0) {
                 parent_[i] = kOrphan;
-                orphans_.push_back(i);
+                orphans_.push_front(i);
             }
             break;
         }
-        rcap_[sister(a)] += b;
+        rcap_[sister_[a]] += b;
         rcap_[a] -= b;
         const int down = head_[a];
         if (rcap_[a] == 0) {
             parent_[i] = kOrphan;
-            orphans_.push_back(i);
+            orphans_.push_front(i);
         }
         i = down;
     }
@@ -250,15 +266,16 @@ void MaxFlow::augment(int mid)
 void MaxFlow::adopt()
 {
     while (!orphans_.empty()) {
-        const int i = orphans_.back();
-        orphans_.pop_back();
+        const int i = orphans_.front();
+        orphans_.pop_front();
         const bool sink = sink_[i];
         int best = -1;
         int dmin = INT_MAX;
-        for (int a0 = first_[i]; a0 >= 0; a0 = next_[a0]) {
+        const int a0 = first_[i], a1 = first_[i + 1];
+        for (int a = a0; a < a1; ++a) {
             // residual towards i (source tree) or away from i (sink tree)
-            if ((sink ? rcap_[a0] : rcap_[sister(a0)]) <= 0) continue;
-            const int j = head_[a0];
+            if ((sink ? rcap_[a] : rcap_[sister_[a]]) <= 0) continue;
+            const int j = head_[a];
             if (sink_[j] != sink || parent_[j] == kNone) continue;
             // does j's path reach the terminal?
             int d = 0;
@@ -268,22 +285,22 @@ void MaxFlow::adopt()
                     d += dist_[k];
                     break;
                 }
-                const int a = parent_[k];
+                const int pa = parent_[k];
                 ++d;
-                if (a == kTerminal) {
+                if (pa == kTerminal) {
                     ts_[k] = time_;
                     dist_[k] = 1;
                     break;
                 }
-                if (a == kOrphan) {
+                if (pa == kOrphan) {
                     d = INT_MAX;
                     break;
                 }
-                k = head_[a];
+                k = head_[pa];
             }
             if (d == INT_MAX) continue;
             if (d < dmin) {
-                best = a0;
+                best = a;
                 dmin = d;
             }
             for (k = j; ts_[k] != time_; k = head_[parent_[k]]) {
@@ -298,14 +315,14 @@ void MaxFlow::adopt()
             continue;
         }
         // free i
-        for (int a0 = first_[i]; a0 >= 0; a0 = next_[a0]) {
-            const int j = head_[a0];
+        for (int a = a0; a < a1; ++a) {
+            const int j = head_[a];
             if (sink_[j] != sink || parent_[j] == kNone) continue;
-            if ((sink ? rcap_[a0] : rcap_[sister(a0)]) > 0) set_active(j);
-            const int a = parent_[j];
-            if (a != kTerminal && a != kOrphan && head_[a] == i) {
+            if ((sink ? rcap_[a] : rcap_[sister_[a]]) > 0) set_active(j);
+            const int pa = parent_[j];
+            if (pa != kTerminal && pa != kOrphan && head_[pa] == i) {
                 parent_[j] = kOrphan;
-                orphans_.insert(orphans_.begin(), j);
+                orphans_.push_back(j);
             }
         }
         parent_[i] = kNone;
@@ -324,7 +341,7 @@ void MaxFlow::source_side(std::vector<uint8_t> &out) const
     while (!st.empty()) {
         const int i = st.back();
         st.pop_back();
-        for (int a = first_[i]; a >= 0; a = next_[a]) {
+        for (int a = first_[i]; a < first_[i + 1]; ++a) {
             const int j = head_[a];
             if (!out[j] && rcap_[a] > 0) {
                 out[j] = 1;
@@ -337,20 +354,25 @@ void MaxFlow::source_side(std::vector<uint8_t> &out) const
 // ------------------------------------------------------------------ energy
 int64_t quantize(double x, double q) { return (int64_t)std::llround(x * q); }
 
+// The term tables are stored level-major ([L][rows] and [L][rows][2]), so
+// that a move towards one level reads them in row order.
 struct Model {
     int64_t rows = 0;
     int L = 0;
-    std::vector<int64_t> U;          // [rows][L] or empty
-    std::vector<int64_t> R;          // [rows][2][L] rewards, 0 without a hit, or empty
-    const int32_t *hit = nullptr;    // [rows][2][L]
-    const int64_t *off = nullptr;
-    const int32_t *idx = nullptr;
-    std::vector<int64_t> W;          // per adjacency entry
+    std::vector<int64_t> UT;         // [L][rows] quantised unary, or empty
+    std::vector<int32_t> HT;         // [L][rows][2] window hits (-1: none), or empty
+    std::vector<int64_t> RT;         // [L][rows][2] quantised rewards (0 without a hit), or empty
+    // adjacency as unordered pairs, listed from both ends: row r's pairs are
+    // [poff[r], poff[r + 1]), weight = the sum of both ordered entries' weights
+    std::vector<int64_t> poff;
+    std::vector<int32_t> ptgt;
+    std::vector<int64_t> pw;
     std::vector<int32_t> fixed;      // label or -1
 
-    int64_t unary(int64_t r, int l) const { return U.empty() ? 0 : U[r * L + l]; }
-    int32_t hit_at(int64_t r, int s, int l) const { return hit ? hit[(r * 2 + s) * L + l] : -1; }
-    int64_t reward(int64_t r, int s, int l) const { return R.empty() ? 0 : R[(r * 2 + s) * L + l]; }
+    int64_t unary(int64_t r, int l) const { return UT.empty() ? 0 : UT[(size_t)l * rows + r]; }
+    int32_t hit_at(int64_t r, int s, int l) const { return HT.empty() ? -1 : HT[((size_t)l * rows + r) * 2 + s]; }
+    int64_t reward(int64_t r, int s, int l) const { return RT.empty() ? 0 : RT[((size_t)l * rows + r) * 2 + s]; }
+    bool is_free(int64_t r) const { return fixed.empty() || fixed[r] < 0; }
 
     int64_t energy(const std::vector<int32_t> &d) const
     {
@@ -362,90 +384,123 @@ struct Model {
                 const int32_t h = hit_at(r, s, l);
                 if (h >= 0 && d[h] == l) e += reward(r, s, l);
             }
-            if (off)
-                for (int64_t k = off[r]; k < off[r + 1]; ++k) e += W[k] * std::abs(l - d[idx[k]]);
+            for (int64_t k = poff.empty() ? 0 : poff[r]; k < (poff.empty() ? 0 : poff[r + 1]); ++k)
+                if (ptgt[k] > r) e += pw[k] * std::abs(l - d[ptgt[k]]);
         }
         return e;
     }
 };
 
-// One alpha-expansion move over the segments allowed to switch.
+// Rows that may take level l in a merge: those whose candidate labels
+// include l, bucketed by level.
+struct Buckets {
+    std::vector<int64_t> off;
+    std::vector<int32_t> row;
+};
+
+// Alpha-expansion moves over one labelling.  Keeps an index from each row
+// to the (row, slot) window terms whose current hit lands on it, so a move
+// visits only the segments that may switch and the terms touching them.
 class Mover {
 public:
-    explicit Mover(const Model &m) : M(m), node_(m.rows, -1) {}
+    explicit Mover(const Model &m) : M(m), node_(m.rows, -1), rev_(m.rows) {}
+
+    void begin(const std::vector<int32_t> &d)
+    {
+        cu_.resize(M.rows);
+        ch_.resize(2 * M.rows);
+        cr_.resize(2 * M.rows);
+        for (int64_t q = 0; q < M.rows; ++q) set_current(q, d[q]);
+        for (auto &v : rev_) v.clear();
+        for (int64_t q = 0; q < M.rows; ++q)
+            for (int s = 0; s < 2; ++s) rev_add(q, s);
+    }
 
     // Returns true (and updates d, e) when the canonical optimal move lowers the energy.
     bool move(std::vector<int32_t> &d, int64_t &e, int alpha, const std::vector<int32_t> *cand_a,
-              const std::vector<int32_t> *cand_b)
+              const std::vector<int32_t> *cand_b, const Buckets *bk)
     {
-        // switchable segments: free, not at alpha, and (in a merge) alpha among their candidates
         nodes_.clear();
-        for (int64_t r = 0; r < M.rows; ++r) {
-            bool sw = M.fixed.empty() || M.fixed[r] < 0;
-            sw = sw && d[r] != alpha;
-            if (sw && cand_a) sw = (*cand_a)[r] == alpha || (*cand_b)[r] == alpha;
-            node_[r] = sw ? (int)nodes_.size() : -1;
-            if (sw) nodes_.push_back(r);
+        auto consider = [&](int64_t r) {
+            if (!M.is_free(r) || d[r] == alpha || node_[r] >= 0) return;
+            if (cand_a && (*cand_a)[r] != alpha && (*cand_b)[r] != alpha) return;
+            node_[r] = (int)nodes_.size();
+            nodes_.push_back(r);
+        };
+        if (bk) {
+            for (int64_t k = bk->off[alpha]; k < bk->off[alpha + 1]; ++k) consider(bk->row[k]);
+        } else {
+            for (int64_t r = 0; r < M.rows; ++r) consider(r);
         }
         if (nodes_.empty()) return false;
         const int n = (int)nodes_.size();
         g_.reset(n);
         net_.assign(n, 0);
+        pairs_.clear();
         auto lab = [&](int64_t r, int x) { return (x && node_[r] >= 0) ? alpha : d[r]; };
         auto unary1 = [&](int i, int64_t c0, int64_t c1) { net_[i] += c1 - c0; };
+        bool nonsub = false;
         auto pair = [&](int i, int j, int64_t A, int64_t B, int64_t C, int64_t D) {
             // A + (C - A) x_i + (D - C) x_j + (B + C - A - D)(1 - x_i) x_j
             net_[i] += C - A;
             net_[j] += D - C;
             const int64_t w = B + C - A - D;
-            if (w > 0) g_.add_edge(i, j, w);
-            if (w < 0) nonsub_ = true;
+            if (w > 0) {
+                g_.add_edge(i, j, w);
+                pairs_.push_back({i, j, w});
+            }
+            if (w < 0) nonsub = true;
         };
-        nonsub_ = false;
-        for (int64_t r = 0; r < M.rows; ++r) {
-            const int ir = node_[r];
-            if (ir >= 0) unary1(ir, M.unary(r, d[r]), M.unary(r, alpha));
+        for (int ir = 0; ir < n; ++ir) {
+            const int64_t r = nodes_[ir];
+            const int dr = d[r];
+            unary1(ir, cu_[r], M.unary(r, alpha));
+            // r's own window terms: Rv [label_r = c][label_h = c] for its two candidates c
             for (int s = 0; s < 2; ++s) {
-                for (int xr = 0; xr < (ir >= 0 ? 2 : 1); ++xr) {
-                    const int c = lab(r, xr);
-                    const int32_t h = M.hit_at(r, s, c);
+                for (int xr = 0; xr < 2; ++xr) {
+                    const int c = xr ? alpha : dr;
+                    const int32_t h = xr ? M.hit_at(r, s, alpha) : ch_[2 * r + s];
                     if (h < 0) continue;
-                    const int64_t Rv = M.reward(r, s, c);
+                    const int64_t Rv = xr ? M.reward(r, s, alpha) : cr_[2 * r + s];
                     if (Rv == 0) continue;
                     const int ih = node_[h];
-                    // Rv [label_r = c][label_h = c]
                     if (h == r) {
-                        if (ir >= 0) unary1(ir, xr == 0 ? Rv : 0, xr == 1 ? Rv : 0);
-                    } else if (ir >= 0 && ih >= 0) {
+                        unary1(ir, xr == 0 ? Rv : 0, xr == 1 ? Rv : 0);
+                    } else if (ih >= 0) {
                         int64_t t[2][2];
                         for (int a = 0; a < 2; ++a)
                             for (int b = 0; b < 2; ++b) t[a][b] = (a == xr && lab(h, b) == c) ? Rv : 0;
                         pair(ir, ih, t[0][0], t[0][1], t[1][0], t[1][1]);
-                    } else if (ir >= 0) {
+                    } else {
                         const int64_t v = d[h] == c ? Rv : 0;
                         unary1(ir, xr == 0 ? v : 0, xr == 1 ? v : 0);
-                    } else if (ih >= 0) {
-                        unary1(ih, lab(h, 0) == c ? Rv : 0, lab(h, 1) == c ? Rv : 0);
                     }
                 }
             }
-            if (M.off) {
-                for (int64_t k = M.off[r]; k < M.off[r + 1]; ++k) {
-                    const int64_t t = M.idx[k];
-                    const int it = node_[t];
-                    const int64_t w = M.W[k];
-                    if (w == 0 || (ir < 0 && it < 0)) continue;
-                    if (ir >= 0 && it >= 0) {
-                        pair(ir, it, w * std::abs(d[r] - d[t]), w * std::abs(d[r] - alpha),
-                             w * std::abs(alpha - d[t]), 0);
-                    } else if (ir >= 0) {
-                        unary1(ir, w * std::abs(d[r] - d[t]), w * std::abs(alpha - d[t]));
-                    } else {
-                        unary1(it, w * std::abs(d[r] - d[t]), w * std::abs(d[r] - alpha));
-                    }
+            // window terms of segments that keep their label and hit r
+            for (uint64_t code : rev_[r]) {
+                const int64_t q = (int64_t)(code >> 1);
+                if (node_[q] >= 0) continue;   // a switchable q's terms are its own
+                const int s = (int)(code & 1);
+                const int c = d[q];
+                const int64_t Rq = cr_[2 * q + s];
+                unary1(ir, dr == c ? Rq : 0, alpha == c ? Rq : 0);
+            }
+            // intra-view pairs
+            for (int64_t k = M.poff.empty() ? 0 : M.poff[r]; k < (M.poff.empty() ? 0 : M.poff[r + 1]); ++k) {
+                const int64_t t = M.ptgt[k];
+                const int64_t w = M.pw[k];
+                const int it = node_[t];
+                const int dt = d[t];
+                if (it >= 0) {
+                    if (t < r) continue;   // handled from t
+                    pair(ir, it, w * std::abs(dr - dt), w * std::abs(dr - alpha), w * std::abs(alpha - dt), 0);
+                } else {
+                    unary1(ir, w * std::abs(dr - dt), w * std::abs(alpha - dt));
                 }
             }
         }
+        nonsub_ |= nonsub;
         for (int i = 0; i < n; ++i) {
             if (net_[i] > 0)
                 g_.add_tweights(i, net_[i], 0);
@@ -454,30 +509,78 @@ public:
         }
         g_.solve();
         g_.source_side(side_);
-        cand_ = d;
+        // energy change of the move, from its binary form
+        int64_t delta = 0;
         bool any = false;
         for (int i = 0; i < n; ++i)
             if (!side_[i]) {
-                cand_[nodes_[i]] = alpha;
+                delta += net_[i];
                 any = true;
             }
-        if (!any) return false;
-        const int64_t e2 = M.energy(cand_);
-        if (e2 >= e) return false;
-        d.swap(cand_);
-        e = e2;
-        return true;
+        for (const PairEdge &pe : pairs_)
+            if (side_[pe.i] && !side_[pe.j]) delta += pe.w;
+        bool taken = false;
+        if (any && delta < 0) {
+            for (int i = 0; i < n; ++i)
+                if (!side_[i]) {
+                    const int64_t q = nodes_[i];
+                    for (int s = 0; s < 2; ++s) rev_remove(q, s);
+                    d[q] = alpha;
+                    set_current(q, alpha);
+                    for (int s = 0; s < 2; ++s) rev_add(q, s);
+                }
+            e += delta;
+            taken = true;
+        }
+        for (int64_t r : nodes_) node_[r] = -1;
+        return taken;
     }
 
     bool nonsubmodular() const { return nonsub_; }
 
 private:
+    struct PairEdge {
+        int i, j;
+        int64_t w;
+    };
+    // terms of row q at its current level
+    void set_current(int64_t q, int l)
+    {
+        cu_[q] = M.unary(q, l);
+        for (int s = 0; s < 2; ++s) {
+            ch_[2 * q + s] = M.hit_at(q, s, l);
+            cr_[2 * q + s] = M.reward(q, s, l);
+        }
+    }
+    void rev_add(int64_t q, int s)
+    {
+        const int32_t h = ch_[2 * q + s];
+        if (h >= 0 && cr_[2 * q + s] != 0) rev_[h].push_back(((uint64_t)q << 1) | (uint64_t)s);
+    }
+    void rev_remove(int64_t q, int s)
+    {
+        const int32_t h = ch_[2 * q + s];
+        if (h < 0 || cr_[2 * q + s] == 0) return;
+        auto &v = rev_[h];
+        const uint64_t code = ((uint64_t)q << 1) | (uint64_t)s;
+        for (size_t k = 0; k < v.size(); ++k)
+            if (v[k] == code) {
+                v[k] = v.back();
+                v.pop_back();
+                return;
+            }
+    }
+
     const Model &M;
     std::vector<int> node_;
+    std::vector<int64_t> cu_;        // unary at the current level
+    std::vector<int32_t> ch_;        // [rows][2] hits at the current level
+    std::vector<int64_t> cr_;        // [rows][2] rewards at the current level
+    std::vector<std::vector<uint64_t>> rev_;
     std::vector<int64_t> nodes_;
     std::vector<int64_t> net_;
+    std::vector<PairEdge> pairs_;
     std::vector<uint8_t> side_;
-    std::vector<int32_t> cand_;
     MaxFlow g_;
     bool nonsub_ = false;
 };
@@ -494,15 +597,31 @@ void expansion(const Model &M, Result &res, const std::vector<int> &labels, int 
                const std::vector<int32_t> *cand_a, const std::vector<int32_t> *cand_b, bool &nonsub)
 {
     Mover mv(M);
+    mv.begin(res.d);
     res.e = M.energy(res.d);
     res.cycles = 0;
+    Buckets bk;
+    if (cand_a) {
+        bk.off.assign(M.L + 1, 0);
+        for (int64_t r = 0; r < M.rows; ++r) {
+            ++bk.off[(*cand_a)[r] + 1];
+            if ((*cand_b)[r] != (*cand_a)[r]) ++bk.off[(*cand_b)[r] + 1];
+        }
+        for (int l = 0; l < M.L; ++l) bk.off[l + 1] += bk.off[l];
+        bk.row.resize(bk.off[M.L]);
+        std::vector<int64_t> pos(bk.off.begin(), bk.off.end() - 1);
+        for (int64_t r = 0; r < M.rows; ++r) {
+            bk.row[pos[(*cand_a)[r]]++] = (int32_t)r;
+            if ((*cand_b)[r] != (*cand_a)[r]) bk.row[pos[(*cand_b)[r]]++] = (int32_t)r;
+        }
+    }
     for (int c = 0; c < max_cycles; ++c) {
         ++res.cycles;
         bool changed = false;
-        for (int alpha : labels) changed |= mv.move(res.d, res.e, alpha, cand_a, cand_b);
-        nonsub |= mv.nonsubmodular();
+        for (int alpha : labels) changed |= mv.move(res.d, res.e, alpha, cand_a, cand_b, cand_a ? &bk : nullptr);
         if (!changed) break;
     }
+    nonsub |= mv.nonsubmodular();
 }
 
 std::vector<std::vector<int>> partition_labels(int L, int n, int partition)
@@ -526,20 +645,20 @@ std::vector<std::vector<int>> partition_labels(int L, int n, int partition)
 void initial(const Model &M, const std::vector<int> &labels, std::vector<int32_t> &d)
 {
     d.assign(M.rows, labels[0]);
-    for (int64_t r = 0; r < M.rows; ++r) {
-        if (!M.fixed.empty() && M.fixed[r] >= 0) {
-            d[r] = M.fixed[r];
-            continue;
-        }
-        int best = labels[0];
-        int64_t bv = M.unary(r, best);
+    if (!M.UT.empty()) {
+        std::vector<int64_t> best(M.rows);
+        for (int64_t r = 0; r < M.rows; ++r) best[r] = M.unary(r, labels[0]);
         for (int l : labels)
-            if (M.unary(r, l) < bv) {
-                bv = M.unary(r, l);
-                best = l;
+            for (int64_t r = 0; r < M.rows; ++r) {
+                const int64_t u = M.unary(r, l);
+                if (u < best[r]) {
+                    best[r] = u;
+                    d[r] = l;
+                }
             }
-        d[r] = best;
     }
+    for (int64_t r = 0; r < M.rows; ++r)
+        if (!M.is_free(r)) d[r] = M.fixed[r];
 }
 
 Result merge(const Model &M, const Result &A, const Result &B, int max_cycles, bool &nonsub)
@@ -553,6 +672,8 @@ Result merge(const Model &M, const Result &A, const Result &B, int max_cycles, b
     expansion(M, out, out.labels, max_cycles, &A.d, &B.d, nonsub);
     return out;
 }
+
+int build_threads() { return (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
 
 ivde_status build_model(const ivde_energy *E, Model &M)
 {
@@ -575,67 +696,148 @@ ivde_status build_model(const ivde_energy *E, Model &M)
     const double limit = std::ldexp(1.0, 40);
     M.rows = rows;
     M.L = L;
+    // level-major transposition in blocks of rows, spread over host threads
+    constexpr int64_t kBlock = 64;
+    const int64_t n_blocks = (rows + kBlock - 1) / kBlock;
+    const int workers = (int)std::max<int64_t>(1, std::min<int64_t>(n_blocks, build_threads()));
+    struct Bad {
+        int kind = 0;   // 1 unary, 2 hit, 3 window value
+        size_t at = 0;
+        double value = 0;
+    };
+    std::vector<Bad> bad(workers);
+    auto run = [&](auto &&body) {
+        std::vector<std::thread> pool;
+        for (int w = 0; w < workers; ++w)
+            pool.emplace_back([&, w] {
+                for (int64_t b = w; b < n_blocks; b += workers) {
+                    const int64_t r0 = b * kBlock, r1 = std::min(rows, r0 + kBlock);
+                    if (!body(r0, r1, bad[w])) return;
+                }
+            });
+        for (auto &t : pool) t.join();
+        for (const Bad &x : bad)
+            if (x.kind) return x;
+        return Bad{};
+    };
     if (E->unary) {
         if (!std::isfinite(E->unary_weight)) {
             set_error("energy: unary_weight must be finite");
             return IVDE_EINVAL;
         }
-        M.U.resize((size_t)rows * L);
-        for (size_t i = 0; i < M.U.size(); ++i) {
-            const double u = E->unary_weight * (double)E->unary[i];
-            if (!(std::fabs(u * q) < limit)) {
-                set_error("energy: unary value %g too large for quantum %g", u, q);
-                return IVDE_EINVAL;
-            }
-            M.U[i] = quantize(u, q);
+        M.UT.resize((size_t)rows * L);
+        const Bad x = run([&](int64_t r0, int64_t r1, Bad &bd) {
+            for (int l = 0; l < L; ++l)
+                for (int64_t r = r0; r < r1; ++r) {
+                    const double u = E->unary_weight * (double)E->unary[(size_t)r * L + l];
+                    if (!(std::fabs(u * q) < limit)) {
+                        bd = {1, (size_t)r * L + l, u};
+                        return false;
+                    }
+                    M.UT[(size_t)l * rows + r] = quantize(u, q);
+                }
+            return true;
+        });
+        if (x.kind) {
+            set_error("energy: unary value %g too large for quantum %g", x.value, q);
+            return IVDE_EINVAL;
         }
     }
     if (E->window_m) {
-        M.hit = E->window_hit;
-        M.R.resize((size_t)rows * 2 * L);
-        for (size_t i = 0; i < M.R.size(); ++i) {
-            const int32_t h = E->window_hit[i];
-            if (h < -1 || h >= rows) {
-                set_error("energy: window_hit entry %zu (%d) outside [-1, rows)", i, h);
-                return IVDE_EINVAL;
-            }
-            if (h < 0) {
-                M.R[i] = 0;
-                continue;
-            }
-            const double v = std::min(0.0, (double)E->window_m[i] - (double)E->K);
-            if (!(std::fabs(v * q) < limit)) {
-                set_error("energy: window value %g too large for quantum %g", (double)E->window_m[i], q);
-                return IVDE_EINVAL;
-            }
-            M.R[i] = quantize(v, q);
+        M.HT.resize((size_t)rows * 2 * L);
+        M.RT.resize((size_t)rows * 2 * L);
+        const Bad x = run([&](int64_t r0, int64_t r1, Bad &bd) {
+            for (int l = 0; l < L; ++l)
+                for (int64_t r = r0; r < r1; ++r)
+                    for (int sl = 0; sl < 2; ++sl) {
+                        const size_t src = ((size_t)r * 2 + sl) * L + l;
+                        const size_t dst = ((size_t)l * rows + r) * 2 + sl;
+                        const int32_t h = E->window_hit[src];
+                        if (h < -1 || h >= rows) {
+                            bd = {2, src, (double)h};
+                            return false;
+                        }
+                        M.HT[dst] = h;
+                        if (h < 0) {
+                            M.RT[dst] = 0;
+                            continue;
+                        }
+                        const double v = std::min(0.0, (double)E->window_m[src] - (double)E->K);
+                        if (!(std::fabs(v * q) < limit)) {
+                            bd = {3, src, (double)E->window_m[src]};
+                            return false;
+                        }
+                        M.RT[dst] = quantize(v, q);
+                    }
+            return true;
+        });
+        if (x.kind == 2) {
+            set_error("energy: window_hit entry %zu (%d) outside [-1, rows)", x.at, (int)x.value);
+            return IVDE_EINVAL;
+        }
+        if (x.kind == 3) {
+            set_error("energy: window value %g too large for quantum %g", x.value, q);
+            return IVDE_EINVAL;
         }
     }
     if (E->adj_offsets) {
-        M.off = E->adj_offsets;
-        M.idx = E->adj_index;
-        if (M.off[0] != 0) {
+        const int64_t *off = E->adj_offsets;
+        if (off[0] != 0) {
             set_error("energy: adjacency offsets must start at 0");
             return IVDE_EINVAL;
         }
         for (int64_t r = 0; r < rows; ++r)
-            if (M.off[r + 1] < M.off[r]) {
+            if (off[r + 1] < off[r]) {
                 set_error("energy: adjacency offsets decrease at row %lld", (long long)r);
                 return IVDE_EINVAL;
             }
-        const int64_t n = M.off[rows];
-        M.W.resize((size_t)n);
-        for (int64_t k = 0; k < n; ++k) {
-            if (M.idx[k] < 0 || M.idx[k] >= rows) {
-                set_error("energy: adjacency entry %lld names row %d", (long long)k, M.idx[k]);
-                return IVDE_EINVAL;
+        // unordered pairs with the summed weight of both ordered entries
+        struct P3 {
+            int32_t a, b;
+            int64_t w;
+        };
+        std::vector<P3> prs;
+        prs.reserve((size_t)off[rows]);
+        for (int64_t r = 0; r < rows; ++r)
+            for (int64_t k = off[r]; k < off[r + 1]; ++k) {
+                const int32_t t = E->adj_index[k];
+                if (t < 0 || t >= rows) {
+                    set_error("energy: adjacency entry %lld names row %d", (long long)k, t);
+                    return IVDE_EINVAL;
+                }
+                const double v = (double)E->adj_beta[k] * q;
+                if (!(E->adj_beta[k] >= 0.f) || !(v < limit / L)) {
+                    set_error("energy: beta %g must be >= 0 and small enough for quantum %g",
+                              (double)E->adj_beta[k], q);
+                    return IVDE_EINVAL;
+                }
+                const int64_t w = quantize(E->adj_beta[k], q);
+                if (t == r || w == 0) continue;
+                prs.push_back({(int32_t)std::min<int64_t>(r, t), (int32_t)std::max<int64_t>(r, t), w});
             }
-            const double v = (double)E->adj_beta[k] * q;
-            if (!(E->adj_beta[k] >= 0.f) || !(v < limit / L)) {
-                set_error("energy: beta %g must be >= 0 and small enough for quantum %g", (double)E->adj_beta[k], q);
-                return IVDE_EINVAL;
-            }
-            M.W[k] = quantize(E->adj_beta[k], q);
+        std::sort(prs.begin(), prs.end(), [](const P3 &x, const P3 &y) { return x.a != y.a ? x.a < y.a : x.b < y.b; });
+        size_t u = 0;
+        for (size_t k = 0; k < prs.size(); ++k) {
+            if (u > 0 && prs[u - 1].a == prs[k].a && prs[u - 1].b == prs[k].b)
+                prs[u - 1].w += prs[k].w;
+            else
+                prs[u++] = prs[k];
+        }
+        prs.resize(u);
+        M.poff.assign(rows + 1, 0);
+        for (const P3 &p : prs) {
+            ++M.poff[p.a + 1];
+            ++M.poff[p.b + 1];
+        }
+        for (int64_t r = 0; r < rows; ++r) M.poff[r + 1] += M.poff[r];
+        M.ptgt.resize(M.poff[rows]);
+        M.pw.resize(M.poff[rows]);
+        std::vector<int64_t> pos(M.poff.begin(), M.poff.end() - 1);
+        for (const P3 &p : prs) {
+            M.ptgt[pos[p.a]] = p.b;
+            M.pw[pos[p.a]++] = p.w;
+            M.ptgt[pos[p.b]] = p.a;
+            M.pw[pos[p.b]++] = p.w;
         }
     }
     if (E->fixed_labels) {
@@ -703,6 +905,10 @@ ivde_status ivde_expansion(const ivde_energy *energy, int32_t *labels, const int
         set_error("expansion: a move was not submodular (negative adjacency weight or positive reward)");
         return IVDE_EINVAL;
     }
+    if (M.energy(res.d) != res.e) {
+        set_error("expansion: tracked energy disagrees with the recomputed energy");
+        return IVDE_EINVAL;
+    }
     std::copy(res.d.begin(), res.d.end(), labels);
     if (energy_out) *energy_out = res.e;
     if (cycles_out) *cycles_out = res.cycles;
@@ -750,6 +956,10 @@ ivde_status ivde_optimize(const ivde_energy *energy, int32_t n_threads, int32_t 
             set_error("optimize: a move was not submodular (negative adjacency weight or positive reward)");
             return IVDE_EINVAL;
         }
+    if (M.energy(res[0].d) != res[0].e) {
+        set_error("optimize: tracked energy disagrees with the recomputed energy");
+        return IVDE_EINVAL;
+    }
     std::copy(res[0].d.begin(), res[0].d.end(), labels_out);
     if (energy_out) *energy_out = res[0].e;
     return IVDE_OK;
