@@ -172,8 +172,29 @@ __global__ __launch_bounds__(1024) void k_scan(const Problem *__restrict__ P)
     if (threadIdx.x == 0) v.offsets[v.S] = carry;
 }
 
-// Pixel records in raster order inside each segment: one wave scans its
-// segment's box row by row and compacts the member pixels with a ballot.
+// One pixel record: position, g . p~ and the pixel's Y, Cb, Cr.
+__device__ __forceinline__ void write_record(const ViewDesc &v, int k, int b, float g0, float g1, float g2, int x,
+                                             int y, int64_t pos)
+{
+    const float fx = (float)x, fy = (float)y;
+    float4 r0, r1;
+    r0.x = fx;
+    r0.y = fy;
+    r0.z = fmaf(g0, fx, fmaf(g1, fy, g2));
+    r0.w = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
+    r1.x = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
+    r1.y = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+    r1.z = 0.f;
+    r1.w = 0.f;
+    float4 *dst = reinterpret_cast<float4 *>(v.pixrec) + 2 * pos;
+    dst[0] = r0;
+    dst[1] = r1;
+}
+
+// One wave per segment scans its box in raster order and writes the pixel
+// records in that order.  A box at most half a wave wide is covered several
+// rows per step (lane order is still raster order); wider boxes row by row
+// in 64-pixel chunks.
 __global__ void k_seg_fill(const Problem *__restrict__ P)
 {
     const ViewDesc &v = P->views[blockIdx.y];
@@ -187,28 +208,28 @@ __global__ void k_seg_fill(const Problem *__restrict__ P)
     const int base = v.offsets[s];
     const int cap = v.offsets[s + 1];
     const float g0 = v.g[0], g1 = v.g[1], g2 = v.g[2];
+    const int bw = x1 - x0 + 1;
     int run = 0;
+    if (bw <= kWave / 2) {
+        const int rows = kWave / bw;                   // rows per step
+        const int lr = lane / bw, lc = lane - lr * bw;
+        for (int yb = y0; yb <= y1; yb += rows) {
+            const int y = yb + lr, x = x0 + lc;
+            const bool m = lr < rows && y <= y1 && v.seg[(int64_t)y * v.seg_pitch + x] == s;
+            const uint64_t bal = __ballot(m);
+            const int pos = base + run + __builtin_popcountll(bal & ((1ull << lane) - 1));
+            if (m && pos < cap) write_record(v, k, b, g0, g1, g2, x, y, pos);
+            run += __builtin_popcountll(bal);
+        }
+        return;
+    }
     for (int y = y0; y <= y1; ++y) {
         for (int xb = x0; xb <= x1; xb += kWave) {
             const int x = xb + lane;
             const bool m = x <= x1 && v.seg[(int64_t)y * v.seg_pitch + x] == s;
             const uint64_t bal = __ballot(m);
             const int pos = base + run + __builtin_popcountll(bal & ((1ull << lane) - 1));
-            if (m && pos < cap) {
-                const float fx = (float)x, fy = (float)y;
-                float4 r0, r1;
-                r0.x = fx;
-                r0.y = fy;
-                r0.z = fmaf(g0, fx, fmaf(g1, fy, g2));
-                r0.w = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
-                r1.x = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
-                r1.y = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
-                r1.z = 0.f;
-                r1.w = 0.f;
-                float4 *dst = reinterpret_cast<float4 *>(v.pixrec) + 2 * (int64_t)pos;
-                dst[0] = r0;
-                dst[1] = r1;
-            }
+            if (m && pos < cap) write_record(v, k, b, g0, g1, g2, x, y, pos);
             run += __builtin_popcountll(bal);
         }
     }
