@@ -246,9 +246,11 @@ typedef struct {
  * streams; frames of one rig run in submission order. */
 ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out);
 
-/* Arena bytes a rig holds while registered (resident) and one of its
- * frames holds while admitted (per_request), for images of bit_depth bits:
- * an arena of resident + k per_request bytes runs k of its frames at once. */
+/* Arena bytes a rig holds while registered (resident: segment maps, the
+ * rig's workspace sized for 16-bit images, two cost volumes, two mean-colour
+ * tables) and one of its frames holds while admitted (per_request, for
+ * images of bit_depth bits): an arena of resident + k per_request bytes runs
+ * k of its frames at once. */
 ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams,
                                   const ivde_segmentation *segs, const ivde_label_range *labels,
                                   const ivde_options *opt, int32_t bit_depth, size_t *resident,

@@ -437,16 +437,22 @@ Extents extents_of(const Layout &ly)
 ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
                           const Layout &ly, char *ws, void *cost_out, int problem_index, Task *tasks,
-                          hipStream_t s)
+                          hipStream_t s, bool index_ready)
 {
     HostConstants hc;
     ivde_status st = compose(n, cams, views, segs, labels, opt, ly, ws, cost_out, hc);
     if (st != IVDE_OK) return st;
     hipError_t e = upload_constants(hc, ly, ws, s);
     if (e != hipSuccess) return hip_fail(e, "constant upload");
+    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    if (index_ready) {
+        // the segment-id flag of the index build stays as it was
+        e = launch_refresh(dp, extents_of(ly), ly.tex_f32, s);
+        if (e != hipSuccess) return hip_fail(e, "frame refresh");
+        return IVDE_OK;
+    }
     e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s);
     if (e != hipSuccess) return hip_fail(e, "segment index");
     e = launch_worklist(dp, extents_of(ly), problem_index, tasks, s);

@@ -53,10 +53,13 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
                     void *cost_out, HostConstants &hc);
 hipError_t upload_constants(const HostConstants &hc, const Layout &ly, char *ws_base, hipStream_t s);
 Extents extents_of(const Layout &ly);
+// index_ready: the workspace already holds the segment index and work list
+// of this segmentation and layout; only the frame's images are taken in
 ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
                           const Layout &ly, char *ws, void *cost_out, int problem_index, Task *tasks,
-                          hipStream_t s);
+                          hipStream_t s,
+                          bool index_ready = false);
 ivde_status check_workspace(const void *workspace, size_t have, size_t need);
 ivde_status check_tex_limits(const Layout &ly);
 

@@ -84,6 +84,9 @@ struct Extents {
     int max_w, max_h, max_s, max_bands;
 };
 hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
+// a new frame over an index already built for the same segmentation:
+// repack the texels and refresh the records' colours
+hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
 hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem_index, Task *tasks,
                            hipStream_t s);
 hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J,

@@ -14,6 +14,8 @@
 // target and go through buffer loads (out-of-range reads return zero, never
 // fault).  Per-row results are produced entirely inside one wave in a fixed
 // order, so plain, batched and served launches give bitwise equal costs.
+#include <algorithm>
+
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -232,6 +234,28 @@ __global__ void k_seg_fill(const Problem *__restrict__ P)
             if (m && pos < cap) write_record(v, k, b, g0, g1, g2, x, y, pos);
             run += __builtin_popcountll(bal);
         }
+    }
+}
+
+// A new frame of the same segmentation: record positions and g . p~ stay,
+// the colours are read again (the same samples a full fill would write).
+__global__ void k_seg_colour(const Problem *__restrict__ P)
+{
+    const ViewDesc &v = P->views[blockIdx.y];
+    const int64_t n = v.offsets[v.S];
+    const int k = P->chroma_shift, b = P->bit_depth;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float4 *rec = reinterpret_cast<float4 *>(v.pixrec) + 2 * i;
+        float4 r0 = rec[0];
+        const int x = (int)r0.x, y = (int)r0.y;
+        r0.w = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
+        float4 r1;
+        r1.x = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
+        r1.y = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+        r1.z = 0.f;
+        r1.w = 0.f;
+        rec[0] = r0;
+        rec[1] = r1;
     }
 }
 
@@ -732,6 +756,23 @@ hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32,
     }
     hipLaunchKernelGGL(k_scan, dim3(nv), dim3(1024), 0, s, dprob);
     hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((ext.max_s + 3) / 4), nv), dim3(256), 0, s, dprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
+{
+    const unsigned nv = (unsigned)ext.n_views;
+    {
+        dim3 blk(64, 4);
+        dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + 3) / 4), nv);
+        if (tex_f32)
+            hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
+        else
+            hipLaunchKernelGGL(k_pack<uint2>, grd, blk, 0, s, dprob);
+    }
+    const int64_t px = (int64_t)ext.max_w * ext.max_h;
+    const unsigned bx = (unsigned)std::min<int64_t>((px + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_seg_colour, dim3(bx, nv), dim3(256), 0, s, dprob);
     return hipGetLastError();
 }
 

@@ -98,8 +98,10 @@ struct Rig {
     std::vector<ivde_segmentation> segs;   // pointing at the arena copies
     ivde_label_range labels{};
     ivde_options opt{};
-    Layout ly{};                           // rows, tasks and cost layout (bit-depth independent)
-    size_t res_off = 0, res_bytes = 0;     // resident: seg maps, volumes, mean colours
+    Layout ly{};                           // the largest layout (16-bit images): sizes the workspace
+    size_t res_off = 0, res_bytes = 0;     // resident: seg maps, workspace, volumes, mean colours
+    char *ws = nullptr;                    // the rig's workspace: index, work list, texels, constants
+    int index_tex = -1;                    // texel format the index in ws was built for, -1: none
     char *cost = nullptr;                  // resident cost volume (the latest frame)
     char *cost_i = nullptr;                // the latest I frame's volume
     float *mean_prev = nullptr;            // [rows][4] mean colours of the latest frame
@@ -130,10 +132,10 @@ struct Request {
     bool done = false;
 };
 
-// workspace, counters, the compacted task list, and the rule's per-row
-// source and changed flags
-// A rig's resident state: its segment maps, the latest and the I-frame
-// cost volumes, and two mean-colour tables.
+// A rig's resident state: its segment maps, its workspace (frames of one
+// rig run one after another, so they share it and the segment index built
+// by the first), the latest and the I-frame cost volumes, and two
+// mean-colour tables.  ly is the largest layout (16-bit images).
 size_t resident_bytes(int n_views, const ivde_camera *cams, const Layout &ly, size_t *seg_off, size_t *seg_total)
 {
     size_t seg_bytes = 0;
@@ -142,13 +144,15 @@ size_t resident_bytes(int n_views, const ivde_camera *cams, const Layout &ly, si
         seg_bytes = align_up(seg_bytes + sizeof(int32_t) * (size_t)cams[v].width * cams[v].height, 256);
     }
     if (seg_total) *seg_total = seg_bytes;
-    return seg_bytes + 2 * align_up(ly.cost_bytes, 256) + 2 * align_up((size_t)ly.total_rows * 16, 256);
+    return seg_bytes + align_up(ly.workspace_bytes, 256) + 2 * align_up(ly.cost_bytes, 256) +
+           2 * align_up((size_t)ly.total_rows * 16, 256);
 }
 
+// One admitted frame's own memory: counters, the compacted task list, and
+// the rule's per-row source and changed flags.
 size_t working_set(const Layout &ly)
 {
-    return align_up(ly.workspace_bytes, 256) + 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256) +
-           2 * align_up((size_t)ly.total_rows, 256);
+    return 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256) + 2 * align_up((size_t)ly.total_rows, 256);
 }
 
 struct Slot {
@@ -260,15 +264,19 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
     hipStream_t s = sl.stream;
     hipError_t e;
     if (rig.last_valid && (e = hipStreamWaitEvent(s, rig.last, 0)) != hipSuccess) return hip_fail(e, "rig order");
-    char *ws = arena_base + r.work_off;
+    char *ws = rig.ws;
     const Layout &ly = r.ly;
     Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
+    // the first frame (or one with another texel format) builds the index
+    const bool index_ready = rig.index_tex == ly.tex_f32;
+    rig.index_tex = -1;
     ivde_status st = enqueue_front(rig.n, rig.cams.data(), r.views.data(), rig.segs.data(), &rig.labels, &rig.opt, ly,
-                                   ws, rig.cost, 0, tasks, s);
+                                   ws, rig.cost, 0, tasks, s, index_ready);
     if (st != IVDE_OK) return st;
+    rig.index_tex = ly.tex_f32;
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     const int bil = rig.opt.sampling == IVDE_BILINEAR;
-    char *extra = ws + align_up(ly.workspace_bytes, 256);
+    char *extra = arena_base + r.work_off;
     int32_t *counters = reinterpret_cast<int32_t *>(extra);   // [0] tasks kept, [1] cursor, [2..4] rule counts
     Task *changed = reinterpret_cast<Task *>(extra + 256);
     uint8_t *source = reinterpret_cast<uint8_t *>(extra + 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256));
@@ -438,7 +446,8 @@ ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_came
         return IVDE_EBUDGET;
     }
     char *base = srv->arena_base + rig.res_off;
-    rig.cost = base + seg_bytes;
+    rig.ws = base + seg_bytes;
+    rig.cost = rig.ws + align_up(rig.ly.workspace_bytes, 256);
     rig.cost_i = rig.cost + align_up(rig.cost_bytes, 256);
     rig.mean_prev = reinterpret_cast<float *>(rig.cost_i + align_up(rig.cost_bytes, 256));
     rig.mean_i = reinterpret_cast<float *>(reinterpret_cast<char *>(rig.mean_prev) + mean_bytes);
@@ -478,8 +487,10 @@ ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams, cons
     }
     ivde_options o = *opt;
     o.sweep_events[0] = o.sweep_events[1] = nullptr;
+    // the resident workspace is sized for 16-bit images, as at registration
+    const Layout big = plan_layout(n_views, cams, segs, labels, &o, 16);
     const Layout ly = plan_layout(n_views, cams, segs, labels, &o, bit_depth);
-    if (resident) *resident = align_up(resident_bytes(n_views, cams, ly, nullptr, nullptr), 256);
+    if (resident) *resident = align_up(resident_bytes(n_views, cams, big, nullptr, nullptr), 256);
     if (per_request) *per_request = align_up(working_set(ly), 256);
     return IVDE_OK;
 }
