@@ -110,6 +110,20 @@ void MaxFlow::build_arcs()
 int64_t MaxFlow::solve()
 {
     build_arcs();
+    // push along every path source -> i -> j -> sink before the tree search
+    for (int i = 0; i < n_; ++i) {
+        if (tr_[i] <= 0) continue;
+        for (int a = first_[i]; a < first_[i + 1] && tr_[i] > 0; ++a) {
+            const int j = head_[a];
+            if (tr_[j] >= 0 || rcap_[a] <= 0) continue;
+            const int64_t f = std::min(std::min(tr_[i], rcap_[a]), -tr_[j]);
+            tr_[i] -= f;
+            tr_[j] += f;
+            rcap_[a] -= f;
+            rcap_[sister_[a]] += f;
+            flow_ += f;
+        }
+    }
     parent_.assign(n_, kNone);
     ts_.assign(n_, 0);
     dist_.assign(n_, 0);
