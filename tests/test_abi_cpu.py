@@ -191,3 +191,71 @@ def test_status_strings(lib):
     for s in range(-6, 1):
         assert lib.ivde_status_string(s)
     assert b"gfx950" in lib.ivde_version()
+
+
+def _imgs(n, w, bits=8):
+    imgs = (ivde.Image * n)()
+    for i in range(n):
+        for p in range(3):
+            imgs[i].plane[p] = 0x2000
+            imgs[i].pitch[p] = w
+        imgs[i].bit_depth, imgs[i].chroma_shift = bits, 0
+    return imgs
+
+
+def test_term_entry_points_reject_bad_arguments(lib):
+    """Window, statistics, rule, adjacency and intra-cost calls refuse bad
+    arguments before any device work."""
+    n, w, h, S, L = 2, 16, 8, 3, 8
+    cams, segs, imgs = _cams(n, w, h), _segs(n, S, w, h), _imgs(n, w)
+    lr = ivde.label_range(1.0, 5.0, L)
+    ob, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.ivde_window_cost_size(n, cams, segs, ctypes.byref(lr), 8, ctypes.byref(ob), ctypes.byref(wb)) == 0
+    assert ob.value == n * S * 2 * L * 4
+    big = ctypes.c_void_p(0x100000)
+    # radius out of range, missing outputs
+    assert lib.ivde_window_cost(n, cams, imgs, segs, ctypes.byref(lr), 9, big, 1 << 30, big, big, None) == \
+        ivde.IVDE_EINVAL
+    assert lib.ivde_window_cost(n, cams, imgs, segs, ctypes.byref(lr), 1, big, 1 << 30, None, big, None) == \
+        ivde.IVDE_EINVAL
+    assert lib.ivde_window_energy(-1, L, None, None, None, ctypes.c_float(30.0), None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_segment_stats_size(n, cams, segs, 20, ctypes.byref(wb)) == ivde.IVDE_EINVAL
+    assert lib.ivde_temporal_rule(4, None, None, None, ctypes.c_float(3.0), ctypes.c_float(1.0), 10, None,
+                                  None) == ivde.IVDE_EINVAL
+    assert lib.ivde_temporal_rule(0, None, None, None, ctypes.c_float(3.0), ctypes.c_float(1.0), 10, None,
+                                  None) == ivde.IVDE_OK
+    # adjacency: offsets required; index/beta required with a capacity; beta0 and eps positive
+    assert lib.ivde_adjacency_size(n, cams, segs, 8, ctypes.byref(wb)) == ivde.IVDE_OK
+    f = ctypes.c_float
+    assert lib.ivde_adjacency(n, cams, imgs, segs, f(1.0), f(1.0), big, 1 << 30, None, None, None, 0, None) == \
+        ivde.IVDE_EINVAL
+    assert lib.ivde_adjacency(n, cams, imgs, segs, f(1.0), f(1.0), big, 1 << 30, big, None, None, 5, None) == \
+        ivde.IVDE_EINVAL
+    assert lib.ivde_adjacency(n, cams, imgs, segs, f(1.0), f(0.0), big, 1 << 30, big, None, None, 0, None) == \
+        ivde.IVDE_EINVAL
+    assert lib.ivde_adjacency(n, cams, imgs, segs, f(float("nan")), f(1.0), big, 1 << 30, big, None, None, 0,
+                              None) == ivde.IVDE_EINVAL
+    assert lib.ivde_adjacency(n, cams, imgs, segs, f(1.0), f(1.0), None, 0, big, None, None, 0, None) == \
+        ivde.IVDE_EINVAL
+    assert lib.ivde_intra_cost(3, 0, None, None, None, None, None, None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_intra_cost(3, 4, None, big, big, big, None, big, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_intra_cost(0, 4, None, None, None, None, None, None, None) == ivde.IVDE_OK
+
+
+def test_depth_map_and_footprint_argument_checks(lib):
+    n, w, h, S, L = 2, 16, 8, 3, 8
+    cams, segs = _cams(n, w, h), _segs(n, S, w, h)
+    big = ctypes.c_void_p(0x100000)
+    bad = ivde.label_range(2.0, 2.0, L)
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(bad), big, big, None) == ivde.IVDE_EINVAL
+    lr = ivde.label_range(1.0, 5.0, L)
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), None, big, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_depth_map(0, cams, segs, ctypes.byref(lr), big, big, None) == ivde.IVDE_EINVAL
+    r, q = ctypes.c_size_t(), ctypes.c_size_t()
+    opt = ivde.options(ivde.BILINEAR, ivde.F16)
+    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, ctypes.byref(r),
+                                     ctypes.byref(q)) == ivde.IVDE_OK
+    # resident holds two FP16 volumes, the maps and a workspace; a frame holds at least its counters
+    assert r.value > 2 * n * S * L * 2 + n * w * h * 4 and q.value >= 256
+    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 20, ctypes.byref(r),
+                                     ctypes.byref(q)) == ivde.IVDE_EINVAL
