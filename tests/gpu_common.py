@@ -55,3 +55,12 @@ def compare(G, O, f16=False, argmin_min=ARGMIN_AGREE, label=""):
     ag = (np.argmin(G, 1) == np.argmin(O, 1)).mean()
     assert ag >= argmin_min, f"{label}: argmin agreement {ag:.5f} < {argmin_min}"
     return dict(mean_err=float(err.mean()), max_err=float(err.max()), argmin_agree=float(ag))
+
+
+def tie_aware(G, O, tol=1e-5):
+    """Share of rows whose GPU argmin has an oracle cost within tol of the
+    oracle minimum (several labels are then equally correct)."""
+    G = np.asarray(G, np.float64)
+    O = np.asarray(O, np.float64)
+    ga = np.argmin(G, 1)
+    return float((O[np.arange(len(O)), ga] <= O.min(1) + tol).mean())

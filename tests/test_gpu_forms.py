@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_common import compare, run_oracle
+from tests.gpu_common import compare, run_oracle, tie_aware
 
 pytestmark = pytest.mark.gpu
 
@@ -113,10 +113,7 @@ def test_autotune():
     assert torch.equal(a, c)
 
 
-def _tie_aware(G, O, tol=1e-5):
-    """GPU argmin whose oracle cost is within tol of the oracle minimum."""
-    ga = np.argmin(G, 1)
-    return float((O[np.arange(len(O)), ga] <= O.min(1) + tol).mean())
+_tie_aware = tie_aware
 
 
 def test_precision_small_512_labels():

@@ -157,3 +157,29 @@ def test_cfg1_full_size_sampled_rows():
     O = run_oracle(wl, rows=rows)
     r = compare(G[rows], O, label="cfg1")
     assert r["max_err"] <= 1e-4, r
+
+
+@pytest.mark.parametrize("bilinear", [False, True])
+def test_thirty_two_views(bilinear):
+    """The largest rig the library takes: 32 views of a converging arc,
+    31 targets each, 4:2:0 10-bit."""
+    _print_case(f"32 views bilinear={bilinear}")
+    ns = P.tiny_problem(320 + int(bilinear), n_views=32, width=24, height=16, n_seg=6, L=9, bilinear=bilinear,
+                        rotated=True, chroma_shift=1, bit_depth=10)
+    G, _ = run_gpu(ns)
+    O = run_oracle(ns)
+    compare(G, O, label="32 views")
+
+
+def test_ten_view_2k_rig_fp16_sampled_rows():
+    """The largest serving rig: 10 views 2048x1088 YUV420 10-bit on a
+    proportionally longer arc, 21500 segments per view, 256 levels, FP16
+    costs; 150 seeded rows against the oracle."""
+    _print_case("10-view 2048x1088 FP16 sampled rows")
+    wl = synth.make_arc_workload("rig-10x2048x1088", synth.config_seed(4) + 3, n_views=10, width=2048, height=1088,
+                                 f=1400.0 * 2048 / 1920, n_segments=21500, num_labels=256, arc_deg=30.0 * 9 / 7)
+    G, _ = run_gpu(wl, cost_dtype=ivde.F16)
+    rng = np.random.default_rng(13)
+    rows = np.sort(rng.choice(G.shape[0], 150, replace=False))
+    O = run_oracle(wl, rows=rows)
+    compare(G[rows], O, f16=True, label="rig C")
