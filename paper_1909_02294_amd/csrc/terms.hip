@@ -79,14 +79,21 @@ __device__ __forceinline__ void texel_at(const void *tex, uint32_t tp, int X, in
 // rounds to the nearest pixel of the target and compares the (2r+1)^2
 // windows (taps clamped to the images).  m is in 8-bit code values; hit is
 // the volume row of the target segment under the projected centre.
-template <bool TEXF32>
+// R > 0 fixes the radius at compile time: the source window (the same for
+// every lane) is read once per wave and all target taps are issued before
+// the first is used.  R == 0 takes any radius at run time.
+template <bool TEXF32, int R>
 __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, const Task *__restrict__ tasks,
                                                 int64_t n_tasks, int radius, float *__restrict__ m_out,
                                                 int32_t *__restrict__ hit_out)
 {
+    constexpr int kTexB = TEXF32 ? 16 : 8;
+    constexpr int kSide = 2 * R + 1;
+    constexpr int kTaps = R > 0 ? kSide * kSide : 1;
     const int lane = lane_id();
     const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + uniform(threadIdx.x / kWave);
     if (t >= n_tasks) return;
+    if constexpr (R > 0) radius = R;
     const Task task = ldu_task(tasks + t);
     const int c = task.view, s = task.seg;
     const int L = ldu(&P->L), n = ldu(&P->n_views);
@@ -103,6 +110,18 @@ __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, c
     const int l = task.lblock * kWave + lane;
     const float sig = l < L ? ldu(&P->sigma)[c * L + l] : 0.f;
     const float taps = (float)((2 * radius + 1) * (2 * radius + 1));
+    float sy[kTaps], su[kTaps], sv[kTaps];
+    if constexpr (R > 0) {
+        if (cx >= 0) {
+#pragma unroll
+            for (int dy = 0; dy < kSide; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < kSide; ++dx)
+                    texel_at<TEXF32>(stex, stp, min(max(cx + dx - R, 0), Wc - 1) + 1,
+                                     min(max(cy + dy - R, 0), Hc - 1) + 1, sy[dy * kSide + dx], su[dy * kSide + dx],
+                                     sv[dy * kSide + dx]);
+        }
+    }
     for (int slot = 0; slot < 2; ++slot) {
         const int c2 = slot == 0 ? c - 1 : c + 1;
         float m = __builtin_nanf("");
@@ -128,15 +147,63 @@ __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, c
                 const void *ttex = ldu(&vt->tex);
                 const uint32_t ttp = (uint32_t)ldu(&vt->tex_pitch);
                 float sum = 0.f;
-                for (int dy = -radius; dy <= radius; ++dy)
-                    for (int dx = -radius; dx <= radius; ++dx) {
-                        float ay, au, av, by, bu, bv;
-                        texel_at<TEXF32>(stex, stp, min(max(cx + dx, 0), Wc - 1) + 1, min(max(cy + dy, 0), Hc - 1) + 1,
-                                         ay, au, av);
-                        texel_at<TEXF32>(ttex, ttp, min(max(tx + dx, 0), W2 - 1) + 1, min(max(ty + dy, 0), H2 - 1) + 1,
-                                         by, bu, bv);
-                        sum += fabsf(ay - by) + fabsf(au - bu) + fabsf(av - bv);
+                if constexpr (R > 0) {
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        const_cast<void *>(ttex), (short)0, (int)ldu(&vt->tex_bytes), (int)0x00020000);
+                    int colo[kSide], rowo[kSide];
+#pragma unroll
+                    for (int k = 0; k < kSide; ++k) {
+                        colo[k] = (min(max(tx + k - R, 0), W2 - 1) + 1) * kTexB;
+                        rowo[k] = (min(max(ty + k - R, 0), H2 - 1) + 1) * (int)ttp * kTexB;
                     }
+                    if constexpr (TEXF32) {
+                        float4 tv[kTaps];
+#pragma unroll
+                        for (int k = 0; k < kTaps; ++k)
+                            tv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                   rs, rowo[k / kSide] + colo[k % kSide], 0, 0));
+#pragma unroll
+                        for (int k = 0; k < kTaps; ++k)
+                            sum += fabsf(sy[k] - tv[k].x) + fabsf(su[k] - tv[k].y) + fabsf(sv[k] - tv[k].z);
+                    } else if constexpr (R == 1) {
+                        // the one-texel border repeats the edge pixels, so the
+                        // taps of a row are the three texels from (tx, ty + k),
+                        // and no clamp is needed: one 16-byte and one 8-byte load
+                        uint2 tv[kTaps];
+#pragma unroll
+                        for (int k = 0; k < kSide; ++k) {
+                            const int o = (ty + k) * (int)ttp * kTexB + tx * kTexB;
+                            const uint4 ab = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+                            tv[3 * k] = make_uint2(ab.x, ab.y);
+                            tv[3 * k + 1] = make_uint2(ab.z, ab.w);
+                            tv[3 * k + 2] = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, o + 16, 0, 0));
+                        }
+#pragma unroll
+                        for (int k = 0; k < kTaps; ++k)
+                            sum += fabsf(sy[k] - h_lo(tv[k].x)) + fabsf(su[k] - h_hi(tv[k].x)) +
+                                   fabsf(sv[k] - h_lo(tv[k].y));
+                    } else {
+                        uint2 tv[kTaps];
+#pragma unroll
+                        for (int k = 0; k < kTaps; ++k)
+                            tv[k] = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                                  rs, rowo[k / kSide] + colo[k % kSide], 0, 0));
+#pragma unroll
+                        for (int k = 0; k < kTaps; ++k)
+                            sum += fabsf(sy[k] - h_lo(tv[k].x)) + fabsf(su[k] - h_hi(tv[k].x)) +
+                                   fabsf(sv[k] - h_lo(tv[k].y));
+                    }
+                } else {
+                    for (int dy = -radius; dy <= radius; ++dy)
+                        for (int dx = -radius; dx <= radius; ++dx) {
+                            float ay, au, av, by, bu, bv;
+                            texel_at<TEXF32>(stex, stp, min(max(cx + dx, 0), Wc - 1) + 1,
+                                             min(max(cy + dy, 0), Hc - 1) + 1, ay, au, av);
+                            texel_at<TEXF32>(ttex, ttp, min(max(tx + dx, 0), W2 - 1) + 1,
+                                             min(max(ty + dy, 0), H2 - 1) + 1, by, bu, bv);
+                            sum += fabsf(ay - by) + fabsf(au - bu) + fabsf(av - bv);
+                        }
+                }
                 m = sum / (taps * scale);
                 const int32_t *seg2 = ldu(&vt->seg);
                 hit = (int)ldu(&vt->row0) + seg2[(int64_t)ty * ldu(&vt->seg_pitch) + tx];
@@ -462,12 +529,18 @@ hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_task
     if (n_tasks <= 0) return hipSuccess;
     const int64_t blocks = (n_tasks + 3) / 4;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (tex_f32)
-        hipLaunchKernelGGL(k_window<true>, dim3((unsigned)blocks), dim3(256), 0, s, dprob, tasks, n_tasks, radius, m_out,
-                           hit_out);
-    else
-        hipLaunchKernelGGL(k_window<false>, dim3((unsigned)blocks), dim3(256), 0, s, dprob, tasks, n_tasks, radius,
-                           m_out, hit_out);
+    const dim3 g((unsigned)blocks), b(256);
+    if (tex_f32) {
+        if (radius == 1)
+            hipLaunchKernelGGL((k_window<true, 1>), g, b, 0, s, dprob, tasks, n_tasks, radius, m_out, hit_out);
+        else
+            hipLaunchKernelGGL((k_window<true, 0>), g, b, 0, s, dprob, tasks, n_tasks, radius, m_out, hit_out);
+    } else {
+        if (radius == 1)
+            hipLaunchKernelGGL((k_window<false, 1>), g, b, 0, s, dprob, tasks, n_tasks, radius, m_out, hit_out);
+        else
+            hipLaunchKernelGGL((k_window<false, 0>), g, b, 0, s, dprob, tasks, n_tasks, radius, m_out, hit_out);
+    }
     return hipGetLastError();
 }
 
