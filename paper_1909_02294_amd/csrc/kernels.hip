@@ -108,35 +108,74 @@ __global__ void k_pack(const Problem *__restrict__ P)
     }
 }
 
-// Pixel counts and boxes.  A wave covers 64 consecutive pixels of one row;
-// runs of equal ids are merged so one lane per run issues the atomics.
-__global__ void k_seg_count(const Problem *__restrict__ P)
+// Pixel counts and boxes.  A block covers a tile of 64 x 16 pixels, a wave
+// four of its rows.  Runs of equal ids in a row are merged so one lane per
+// run records it, first in a small table in LDS (segment id -> count and
+// box, linear probing), which the block then adds to the global arrays with
+// one set of atomics per distinct segment.  Runs that find the table full
+// go to the global arrays directly.
+constexpr int kCountTileRows = 16;
+constexpr int kCountSlots = 128;
+
+__device__ __forceinline__ void count_global(const ViewDesc &v, int id, int n, int x0, int y0, int x1, int y1)
 {
+    atomicAdd(&v.counts[id], n);
+    atomicMin(&v.bbox[4 * id + 0], x0);
+    atomicMin(&v.bbox[4 * id + 1], y0);
+    atomicMax(&v.bbox[4 * id + 2], x1);
+    atomicMax(&v.bbox[4 * id + 3], y1);
+}
+
+__global__ __launch_bounds__(256) void k_seg_count(const Problem *__restrict__ P)
+{
+    __shared__ int key[kCountSlots];
+    __shared__ int cnt[kCountSlots], bx0[kCountSlots], by0[kCountSlots], bx1[kCountSlots], by1[kCountSlots];
     const ViewDesc &v = P->views[blockIdx.z];
+    const int tid = threadIdx.y * kWave + threadIdx.x;
+    if (tid < kCountSlots) {
+        key[tid] = -1;
+        cnt[tid] = 0;
+        bx0[tid] = by0[tid] = 0x7fffffff;
+        bx1[tid] = by1[tid] = -1;
+    }
+    __syncthreads();
     const int lane = threadIdx.x;
     const int x = blockIdx.x * kWave + lane;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const bool in = x < v.W && y < v.H;
-    int id = in ? v.seg[(int64_t)y * v.seg_pitch + x] : -1;
-    if (in && (id < 0 || id >= v.S)) {
-        atomicOr(P->flag, 1);
-        id = -1;
+    for (int k = 0; k < kCountTileRows / 4; ++k) {
+        const int y = blockIdx.y * kCountTileRows + 4 * k + threadIdx.y;
+        const bool in = x < v.W && y < v.H;
+        int id = in ? v.seg[(int64_t)y * v.seg_pitch + x] : -1;
+        if (in && (id < 0 || id >= v.S)) {
+            atomicOr(P->flag, 1);
+            id = -1;
+        }
+        const int prev = __shfl_up(id, 1);
+        const int next = __shfl_down(id, 1);
+        const bool head = id >= 0 && (lane == 0 || prev != id);
+        const bool tail = id >= 0 && (lane == kWave - 1 || next != id);
+        const uint64_t tails = __ballot(tail);
+        if (head) {
+            const uint64_t after = tails & (~0ull << lane);
+            const int len = __builtin_ctzll(after) - lane + 1;
+            int slot = id & (kCountSlots - 1), probe = 0;
+            for (; probe < kCountSlots; ++probe) {
+                const int k0 = atomicCAS(&key[slot], -1, id);
+                if (k0 == -1 || k0 == id) break;
+                slot = (slot + 1) & (kCountSlots - 1);
+            }
+            if (probe < kCountSlots) {
+                atomicAdd(&cnt[slot], len);
+                atomicMin(&bx0[slot], x);
+                atomicMin(&by0[slot], y);
+                atomicMax(&bx1[slot], x + len - 1);
+                atomicMax(&by1[slot], y);
+            } else {
+                count_global(v, id, len, x, y, x + len - 1, y);
+            }
+        }
     }
-    const int prev = __shfl_up(id, 1);
-    const int next = __shfl_down(id, 1);
-    const bool head = id >= 0 && (lane == 0 || prev != id);
-    const bool tail = id >= 0 && (lane == kWave - 1 || next != id);
-    const uint64_t tails = __ballot(tail);
-    if (head) {
-        const uint64_t after = tails & (~0ull << lane);
-        const int end = __builtin_ctzll(after);
-        const int len = end - lane + 1;
-        atomicAdd(&v.counts[id], len);
-        atomicMin(&v.bbox[4 * id + 0], x);
-        atomicMin(&v.bbox[4 * id + 1], y);
-        atomicMax(&v.bbox[4 * id + 2], x + len - 1);
-        atomicMax(&v.bbox[4 * id + 3], y);
-    }
+    __syncthreads();
+    if (tid < kCountSlots && key[tid] >= 0) count_global(v, key[tid], cnt[tid], bx0[tid], by0[tid], bx1[tid], by1[tid]);
 }
 
 // Exclusive scan of the counts, one 1024-thread block per view.
@@ -751,7 +790,7 @@ hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32,
     }
     {
         dim3 blk(64, 4);
-        dim3 grd((unsigned)((ext.max_w + 63) / 64), (unsigned)((ext.max_h + 3) / 4), nv);
+        dim3 grd((unsigned)((ext.max_w + 63) / 64), (unsigned)((ext.max_h + kCountTileRows - 1) / kCountTileRows), nv);
         hipLaunchKernelGGL(k_seg_count, grd, blk, 0, s, dprob);
     }
     hipLaunchKernelGGL(k_scan, dim3(nv), dim3(1024), 0, s, dprob);
