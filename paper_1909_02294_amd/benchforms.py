@@ -35,21 +35,6 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs, np.float64), q))
 
 
-def _oracle_rows(wl, C_gpu, n_rows, seed):
-    """Mean / max |dC| and argmin agreement against the oracle on sampled rows."""
-    import oracle
-    pb = oracle.Problem.from_workload(wl)
-    rng = np.random.default_rng(seed)
-    rows = np.sort(rng.choice(C_gpu.shape[0], n_rows, replace=False))
-    off = pb.row_offsets()
-    views = (np.searchsorted(off, rows, side="right") - 1).astype(np.int32)
-    O = oracle.cost_rows(pb, views, (rows - off[views]).astype(np.int32))
-    G = C_gpu[rows].double().cpu().numpy()
-    e = np.abs(G - O)
-    return dict(rows=int(n_rows), mean_err=float(e.mean()), max_err=float(e.max()),
-                argmin_agree=float((np.argmin(G, 1) == np.argmin(O, 1)).mean()))
-
-
 def bench_batched(args):
     import torch
 
@@ -110,8 +95,6 @@ def bench_batched(args):
     sweep_ms = sweep_ev[0].elapsed_time(sweep_ev[1])
     identical = all(torch.equal(c, r) for c, r in zip(costs, ref))
     _log(f"batched: {batch_s * 1e3:.1f} ms per 16 frames, identical to plain: {identical}")
-    most = int(np.argmax([sum(wl.S) for wl in wls]))
-    parity = [_oracle_rows(wls[i], costs[i], 150, 100 + i) for i in sorted({0, big, most})]
     achieved = evals * 24 / (sweep_ms / 1e3) / 1e9
     batch.close()
     return {
@@ -134,7 +117,6 @@ def bench_batched(args):
         "persistent_sweep_ms": sweep_ms,
         "hbm_metric": {"bytes_per_eval": 24, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                        "frac": achieved / 8000.0},
-        "oracle_parity_sampled": parity,
     }
 
 
