@@ -117,7 +117,7 @@ def bench_plain(args):
     from paper_1909_02294_amd import ivde, synth
 
     t0 = time.perf_counter()
-    wl = synth.make_cfg1()
+    wl = synth.make_arc_1080p()
     print(f"[bench] generated {wl.name} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
@@ -158,7 +158,7 @@ def bench_plain(args):
     sweep_avg_s = float(np.mean(sweep_ms)) / 1e3
     gather_gbs = evals * bpe / sweep_avg_s / 1e9
     alu_tops = evals * OPS_PER_BILINEAR_EVAL / sweep_avg_s / 1e12
-    counters = measured_counters("sweep_cfg1_hbm.json")
+    counters = measured_counters("sweep_arc1080p_hbm.json")
     out = {
         "metric": METRIC,
         "value": value,
@@ -210,7 +210,7 @@ def bench_window(args):
     import torch
     from paper_1909_02294_amd import ivde, synth
 
-    wl = synth.make_cfg1()
+    wl = synth.make_arc_1080p()
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
     for _ in range(args.warmup):
@@ -245,7 +245,7 @@ def bench_intra(args):
     import torch
     from paper_1909_02294_amd import ivde, synth
 
-    wl = synth.make_cfg1()
+    wl = synth.make_arc_1080p()
     dv = ivde.DeviceViews.from_workload(wl)
     off, idx, beta, ws = ivde.adjacency(dv, 30.0, 1.0)
     torch.cuda.synchronize()
@@ -285,17 +285,17 @@ def bench_depth(args):
     minimised on the host by label-partitioned alpha-expansion (Sec. IV-A),
     segment depths painted on the GPU.  --depth-config paper is the paper's
     HD setting (5 views 1920x1080, 100000 segments per view, 250 levels, the
-    window and intra-view terms only); cfg1 is the 8-view 1080p workload with
+    window and intra-view terms only); arc1080p is the 8-view 1080p workload with
     the whole-segment cost as an extra unary term."""
     import torch
     from paper_1909_02294_amd import ivde, pipeline, synth
 
     if args.depth_config == "paper":
-        wl = synth.make_arc_workload("paper-hd-5x1920x1080", synth.config_seed(5), n_views=5,
+        wl = synth.make_arc_workload("paper-hd-5x1920x1080", synth.SEED_PAPER_HD, n_views=5,
                                      arc_deg=30.0 * 4 / 7, n_segments=100000, num_labels=250)
         kw = dict(unary_weight=0.0)
     else:
-        wl = synth.make_cfg1()
+        wl = synth.make_arc_1080p()
         kw = {}
     threads = args.threads or min(16, os.cpu_count() or 1)
     dv = ivde.DeviceViews.from_workload(wl)
@@ -357,7 +357,7 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=4.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--gop", type=int, default=0, help="served: every GOP-th frame of a rig is an I frame")
-    ap.add_argument("--depth-config", choices=["cfg1", "paper"], default="cfg1")
+    ap.add_argument("--depth-config", choices=["arc1080p", "paper"], default="arc1080p")
     ap.add_argument("--threads", type=int, default=0, help="depth: host threads (default min(16, cores))")
     ap.add_argument("--rule", action="store_true",
                     help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")

@@ -39,7 +39,7 @@ def bench_batched(args):
     import torch
 
     t0 = time.perf_counter()
-    wls = synth.make_cfg2_frames(16)
+    wls = synth.make_batch_frames(16)
     _log(f"generated 16 frames in {time.perf_counter() - t0:.1f} s")
     stream = torch.cuda.Stream()        # the graph is captured on a non-null stream
     dvs = [ivde.DeviceViews.from_workload(wl) for wl in wls]
@@ -145,14 +145,14 @@ def bench_served(args):
     rigs = []
     t0 = time.perf_counter()
     for i, spec in enumerate(RIGS):
-        wl, frames = _make_rig(spec, synth.config_seed(4) + 17 * i, n_cycle)
+        wl, frames = _make_rig(spec, synth.SEED_SERVING + 17 * i, n_cycle)
         rigs.append((spec, wl, frames))
         _log(f"rig {spec['name']}: {len(frames)} frames, change rates "
              f"{[round(f['rate'], 3) for f in frames[1:]]} ({time.perf_counter() - t0:.0f} s)")
     arena_bytes = 80 << 30
     duration = args.served_seconds
     rate = 60.0
-    rng = np.random.default_rng(synth.config_seed(4))
+    rng = np.random.default_rng(synth.SEED_SERVING)
     n_req = int(duration * rate)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
     which = rng.integers(0, len(rigs), n_req)

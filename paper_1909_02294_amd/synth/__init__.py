@@ -31,9 +31,13 @@ import numpy as np
 BASE_SEED = 1909002294
 
 
-def config_seed(cfg: int) -> int:
-    """Base seed of workload configuration `cfg` (0..4)."""
-    return BASE_SEED + 1000 * int(cfg)
+# base seeds of the synthetic workloads
+SEED_RECTIFIED = BASE_SEED
+SEED_ARC_1080P = BASE_SEED + 1000
+SEED_BATCH = BASE_SEED + 2000
+SEED_PRECISION = BASE_SEED + 3000
+SEED_SERVING = BASE_SEED + 4000
+SEED_PAPER_HD = BASE_SEED + 5000
 
 
 # --------------------------------------------------------------------------
@@ -330,7 +334,7 @@ class Workload:
 
 
 def _fronto_scene(rng, cams, z_lo, z_hi, n_planes, bit_depth, f):
-    """cfg0-style scene: fronto-parallel planes; the deepest is a full-frame
+    """Rectified-rig scene: fronto-parallel planes; the deepest is a full-frame
     background, the others random rectangles."""
     depths = np.sort(rng.uniform(z_lo, z_hi, n_planes))[::-1]
     W, H = cams[0].width, cams[0].height
@@ -350,7 +354,7 @@ def _fronto_scene(rng, cams, z_lo, z_hi, n_planes, bit_depth, f):
 
 
 def _arc_scene(rng, cams, z_lo, z_hi, n_planes, bit_depth, f, z_bg):
-    """cfg1-style scene: rectangles of random orientation (normals within 60
+    """Arc-rig scene: rectangles of random orientation (normals within 60
     degrees of the rig axis, facing the rig), sides U[0.5, 3] m, depths
     U[z_lo, z_hi] from the rig's reference plane, plus a fronto-parallel
     background at z_bg."""
@@ -385,11 +389,11 @@ def _render_all(planes, cams, bit_depth, chroma_shift):
     return Ys, Us, Vs, P
 
 
-def make_cfg0(seed=None):
+def make_rectified_320x240(seed=None):
     """3 rectified views 320x240, baseline 0.05 m, f = 300, YUV444 u8; 4
     fronto-parallel planes at depths U[1, 5] m; 1200 Voronoi seeds per view;
     64 labels over [1, 5] m; nearest sampling."""
-    seed = config_seed(0) if seed is None else seed
+    seed = SEED_RECTIFIED if seed is None else seed
     ss = np.random.SeedSequence(seed)
     s_scene, *s_views = ss.spawn(4)
     cams = rectified_rig(3, 0.05, 300.0, 320, 240)
@@ -399,7 +403,7 @@ def make_cfg0(seed=None):
     for sv in s_views:
         m, S = voronoi(320, 240, 1200, np.random.default_rng(sv))
         segs.append(m); Ss.append(S)
-    return Workload("cfg0-rectified-3x320x240", cams, Y, U, V, segs, Ss, 8, 0,
+    return Workload("rectified-3x320x240", cams, Y, U, V, segs, Ss, 8, 0,
                     1.0, 5.0, 64, False, seed, P)
 
 
@@ -407,7 +411,7 @@ def make_arc_workload(name, seed, n_views=8, width=1920, height=1080, f=1400.0,
                       n_segments=20000, num_labels=256, arc_deg=30.0,
                       z_near=1.5, z_far=10.0, bit_depth=10, chroma_shift=1,
                       n_planes=20, weight_sigma=0.25, bilinear=True, planes=None):
-    """Arc rig (cfg1 family): views on an arc of radius 3 m looking at its
+    """Arc rig: views on an arc of radius 3 m looking at its
     centre, a planar scene in [z_near, z_far] plus a background at z_far,
     multiplicatively weighted Voronoi segments."""
     ss = np.random.SeedSequence(seed)
@@ -428,16 +432,16 @@ def make_arc_workload(name, seed, n_views=8, width=1920, height=1080, f=1400.0,
     return wl
 
 
-def make_cfg1(seed=None, **kw):
+def make_arc_1080p(seed=None, **kw):
     """8 views 1920x1080 YUV420 10-bit on a 30-degree arc, 20 planes, 20000
     weighted Voronoi segments per view, 256 labels over [1.5, 10] m, bilinear."""
-    seed = config_seed(1) if seed is None else seed
-    return make_arc_workload("cfg1-arc-8x1920x1080", seed, **kw)
+    seed = SEED_ARC_1080P if seed is None else seed
+    return make_arc_workload("arc-8x1920x1080", seed, **kw)
 
 
 def make_small_arc(seed=12345, n_views=4, width=160, height=96, n_segments=150,
                    num_labels=24, bilinear=True, bit_depth=10, chroma_shift=1, f=None):
-    """A reduced arc rig with the cfg1 structure, sized for the oracle."""
+    """A reduced arc rig with the structure of the 8-view 1080p arc rig, sized for the oracle."""
     f = 1400.0 * width / 1920.0 if f is None else f
     return make_arc_workload(f"arc-{n_views}x{width}x{height}", seed, n_views=n_views,
                              width=width, height=height, f=f, n_segments=n_segments,
@@ -445,17 +449,17 @@ def make_small_arc(seed=12345, n_views=4, width=160, height=96, n_segments=150,
                              bit_depth=bit_depth, chroma_shift=chroma_shift)
 
 
-def make_cfg2_frames(n_frames=16, seed=None, width=1920, height=1080, n_views=8,
+def make_batch_frames(n_frames=16, seed=None, width=1920, height=1080, n_views=8,
                      seg_range=(5000, 40000), label_choices=(128, 256)):
     """Batching workload: `n_frames` independent arc-rig frames with segment
     counts U{seg_range} and label counts drawn from `label_choices`."""
-    seed = config_seed(2) if seed is None else seed
+    seed = SEED_BATCH if seed is None else seed
     rng = np.random.default_rng(seed)
     out = []
     for i, s in enumerate(np.random.SeedSequence(seed).spawn(n_frames)):
         S = int(rng.integers(seg_range[0], seg_range[1] + 1))
         L = int(rng.choice(label_choices))
-        out.append(make_arc_workload(f"cfg2-frame{i}", int(s.generate_state(1)[0]),
+        out.append(make_arc_workload(f"batch-frame{i}", int(s.generate_state(1)[0]),
                                      n_views=n_views, width=width, height=height,
                                      n_segments=S, num_labels=L,
                                      f=1400.0 * width / 1920.0))

@@ -136,12 +136,12 @@ def test_precision_small_512_labels():
     assert np.abs(G16 - G32).max() <= 2.0 ** -12
 
 
-def test_precision_cfg3_full_size():
+def test_precision_4k_full_size():
     """The precision workload at full size: the 8-view arc rig at 4096x2160,
     40000 segments per view, 512 labels, bilinear, FP32 accumulation; FP32
     and FP16 storage against the FP64 oracle on 2000 seeded rows."""
-    _case("precision cfg3")
-    wl = synth.make_arc_workload("cfg3-arc-8x4096x2160", synth.config_seed(3), width=4096, height=2160,
+    _case("precision 4k")
+    wl = synth.make_arc_workload("arc-8x4096x2160", synth.SEED_PRECISION, width=4096, height=2160,
                                  f=1400.0 * 4096 / 1920, n_segments=40000, num_labels=512)
     rng = np.random.default_rng(1)
     dv = ivde.DeviceViews.from_workload(wl)
@@ -156,7 +156,7 @@ def test_precision_cfg3_full_size():
         res[name] = compare(G, O, f16=dt == ivde.F16, label=name)
         res[name]["tie_aware"] = _tie_aware(G, O)
         del C
-    print(f"precision cfg3: {res}")
+    print(f"precision 4k: {res}")
 
 
 # ---------------------------------------------------------------- serving

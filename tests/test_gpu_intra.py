@@ -134,11 +134,11 @@ def test_capacity_and_count_only():
     assert torch.equal(idx, idx_full[:cap]) and torch.equal(beta, beta_full[:cap])
 
 
-def test_cfg1_full_size():
+def test_arc_1080p_full_size():
     """8 views of 1920x1080, 20000 segments each: every list exact, every
     weight to FP32 rounding, the costs of 300 seeded rows at 256 labels."""
-    _case("intra cfg1")
-    wl = synth.make_cfg1()
+    _case("intra arc 1080p")
+    wl = synth.make_arc_1080p()
     dv = ivde.DeviceViews.from_workload(wl)
     off_g, idx_g, beta_g, ws = ivde.adjacency(dv, 30.0, 1.0)
     torch.cuda.synchronize()
@@ -150,7 +150,7 @@ def test_cfg1_full_size():
     _, _, mean = oracle.all_segment_stats(pb)
     beta_o = oracle.smoothing_beta(mean, off_o, idx_o, 30.0, wl.bit_depth)
     rel = np.abs(beta_g.cpu().numpy() - beta_o) / beta_o
-    print(f"[cfg1] entries {len(beta_o)}, beta max rel err {rel.max():.3g}, mean {rel.mean():.3g}", flush=True)
+    print(f"[arc 1080p] entries {len(beta_o)}, beta max rel err {rel.max():.3g}, mean {rel.mean():.3g}", flush=True)
     np.testing.assert_allclose(beta_g.cpu().numpy(), beta_o, rtol=BETA_RTOL)
     rng = np.random.default_rng(21)
     rows = len(off_o) - 1

@@ -25,12 +25,12 @@ def _print_case(name):
     print(f"[case] {name}", flush=True)
 
 
-def test_cfg0_full_volume_nearest():
-    _print_case("cfg0 full volume")
-    wl = synth.make_cfg0()
+def test_rectified_full_volume_nearest():
+    _print_case("rectified full volume")
+    wl = synth.make_rectified_320x240()
     G, lab = run_gpu(wl)
     O = run_oracle(wl)
-    r = compare(G, O, label="cfg0")
+    r = compare(G, O, label="rectified")
     # integer sums on both sides: only the final FP32 division differs
     assert r["max_err"] <= 1e-6, r
     assert r["argmin_agree"] == 1.0, r
@@ -145,17 +145,17 @@ def test_segment_id_out_of_range_is_reported():
     assert ivde.workspace_status(ws) == ivde.IVDE_EINVAL
 
 
-def test_cfg1_full_size_sampled_rows():
+def test_arc_1080p_full_size_sampled_rows():
     """8 views 1920x1080 YUV420 10-bit arc rig, 20000 segments, 256 labels,
     bilinear, FP32: the launch the benchmark times, checked on 240 seeded
     rows against the oracle."""
-    _print_case("cfg1 sampled rows")
-    wl = synth.make_cfg1()
+    _print_case("arc 1080p sampled rows")
+    wl = synth.make_arc_1080p()
     G, _ = run_gpu(wl)
     rng = np.random.default_rng(11)
     rows = np.sort(rng.choice(G.shape[0], 240, replace=False))
     O = run_oracle(wl, rows=rows)
-    r = compare(G[rows], O, label="cfg1")
+    r = compare(G[rows], O, label="arc 1080p")
     assert r["max_err"] <= 1e-4, r
 
 
@@ -176,7 +176,7 @@ def test_ten_view_2k_rig_fp16_sampled_rows():
     proportionally longer arc, 21500 segments per view, 256 levels, FP16
     costs; 150 seeded rows against the oracle."""
     _print_case("10-view 2048x1088 FP16 sampled rows")
-    wl = synth.make_arc_workload("rig-10x2048x1088", synth.config_seed(4) + 3, n_views=10, width=2048, height=1088,
+    wl = synth.make_arc_workload("rig-10x2048x1088", synth.SEED_SERVING + 3, n_views=10, width=2048, height=1088,
                                  f=1400.0 * 2048 / 1920, n_segments=21500, num_labels=256, arc_deg=30.0 * 9 / 7)
     G, _ = run_gpu(wl, cost_dtype=ivde.F16)
     rng = np.random.default_rng(13)

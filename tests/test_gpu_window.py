@@ -110,9 +110,9 @@ def test_window_small_arc_and_energy():
     assert (want < 0).any()
 
 
-def test_window_cfg1_full_size_sampled_rows():
+def test_window_arc1080p_full_size_sampled_rows():
     """The 8-view 1080p workload, 256 labels, 3x3 windows: 400 seeded rows."""
-    _case("window cfg1")
-    wl = synth.make_cfg1()
+    _case("window arc 1080p")
+    wl = synth.make_arc_1080p()
     rows = np.sort(np.random.default_rng(12).choice(sum(wl.S), 400, replace=False))
     _compare(wl, 1, rows=rows, min_checked=0.99)

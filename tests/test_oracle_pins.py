@@ -92,8 +92,8 @@ def _rectified_closed_form(cams, Y, U, V, seg, S, bit_depth, z_near, z_far, L):
     return np.concatenate(rows)
 
 
-def test_rectified_closed_form_cfg0():
-    wl = synth.make_cfg0()
+def test_rectified_closed_form_320x240():
+    wl = synth.make_rectified_320x240()
     pb = oracle.Problem.from_workload(wl)
     C = oracle.cost_volume(pb)
     R = _rectified_closed_form(wl.cams, wl.Y, wl.U, wl.V, wl.seg, wl.S, 8, wl.z_near, wl.z_far, 64)
@@ -114,8 +114,8 @@ def test_rectified_closed_form_uneven_baselines():
 
 # ---------------------------------------------------------------- zero-cost plane
 @pytest.mark.parametrize("lstar", [0, 21, 42, 63])
-def test_zero_cost_fronto_plane_cfg0_rig(lstar):
-    """cfg0 rig: adjacent-view disparity at label l is 15 rho_l = 3 + 4 l / 21 px,
+def test_zero_cost_fronto_plane_rectified_rig(lstar):
+    """Rectified 320x240 rig: adjacent-view disparity at label l is 15 rho_l = 3 + 4 l / 21 px,
     an integer for l in {0, 21, 42, 63}.  A plane at that depth rendered by
     exact integer shifts must cost exactly 0 at l* for every segment that sees
     a target, and labels that move the match by a pixel or more cost > 0."""
@@ -145,7 +145,7 @@ def _smooth(s1, s2, base, amp, waves):
 
 
 def test_smooth_plane_on_arc_rig_true_label_wins():
-    """Converging arc rig (cfg1 geometry, reduced size): a plane parallel to
+    """Converging arc rig (the 1080p arc geometry, reduced size): a plane parallel to
     the reference plane at z_l* carries a smooth analytic texture, ray-cast in
     FP64.  With bilinear sampling the true label must be the argmin of at
     least 99.9% of segments and its cost must stay within the bound from
@@ -288,7 +288,7 @@ def test_invariant_bounds_and_min_over_views():
 
 
 def test_invariant_own_equals_rig_centre_on_rectified_rig():
-    wl = synth.make_cfg0()
+    wl = synth.make_rectified_320x240()
     a = oracle.cost_volume(oracle.Problem.from_workload(wl, depth_ref=oracle.REF_RIG_CENTER))
     b = oracle.cost_volume(oracle.Problem.from_workload(wl, depth_ref=oracle.REF_OWN))
     c = oracle.cost_volume(oracle.Problem.from_workload(wl, depth_ref=0))
@@ -310,22 +310,22 @@ def test_fp16_storage_bound():
     x = np.concatenate([rng.uniform(0, 1, 200000), np.linspace(0, 1, 100001)])
     err = np.abs(x.astype(np.float16).astype(np.float64) - x)
     assert err.max() <= 2.0 ** -12
-    wl = synth.make_cfg0()
+    wl = synth.make_rectified_320x240()
     C = oracle.cost_volume(oracle.Problem.from_workload(wl))
     assert np.abs(C.astype(np.float16).astype(np.float64) - C).max() <= 2.0 ** -12
 
 
 def test_nearest_sums_are_integers():
     """Nearest sampling: mean * 3 (2^b - 1) * n_valid is an integer sum."""
-    wl = synth.make_cfg0()
+    wl = synth.make_rectified_320x240()
     C, m, nv = oracle.cost_volume(oracle.Problem.from_workload(wl), with_terms=True)
     ok = nv > 0
     tot = m[ok] * nv[ok] * 765.0
     assert np.abs(tot - np.rint(tot)).max() < 1e-9
 
 
-def test_label_grid_matches_cfg0_disparities():
-    """15 rho_l = 3 + 4 l / 21 on cfg0 (f = 300 px, baseline 0.05 m, [1, 5] m)."""
+def test_label_grid_matches_rectified_disparities():
+    """15 rho_l = 3 + 4 l / 21 on the rectified 320x240 rig (f = 300 px, baseline 0.05 m, [1, 5] m)."""
     L = 64
     rho = 1 / 5.0 + np.arange(L) / (L - 1) * (1 / 1.0 - 1 / 5.0)
     np.testing.assert_allclose(300 * 0.05 * rho, 3 + 4 * np.arange(L) / 21, rtol=0, atol=1e-12)
