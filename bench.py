@@ -363,8 +363,8 @@ def main():
                     help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sweep shards by view or label block without collectives; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the sweep would shard "
+              "by view, frame or level block, needing only the images replicated to every GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch
