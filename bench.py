@@ -66,15 +66,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_counters(name: str):
+def workload_hash(wl) -> str:
+    """Hash of a workload's images and segment maps."""
+    h = hashlib.sha256()
+    for planes in (wl.Y, wl.U, wl.V, wl.seg):
+        for a in planes:
+            h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+def measured_counters(name: str, wl_sha: str):
     """The committed rocprofv3 counter summary of the sweep, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source and the same workload; else None."""
     path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_sha") != kernel_source_hash():
+    if rec.get("kernel_sha") != kernel_source_hash() or rec.get("workload_sha") != wl_sha:
         return None
     return rec
 
@@ -158,7 +167,8 @@ def bench_plain(args):
     sweep_avg_s = float(np.mean(sweep_ms)) / 1e3
     gather_gbs = evals * bpe / sweep_avg_s / 1e9
     alu_tops = evals * OPS_PER_BILINEAR_EVAL / sweep_avg_s / 1e12
-    counters = measured_counters("sweep_arc1080p_hbm.json")
+    wl_sha = workload_hash(wl)
+    counters = measured_counters("sweep_arc1080p_hbm.json", wl_sha)
     out = {
         "metric": METRIC,
         "value": value,
@@ -173,11 +183,12 @@ def bench_plain(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "8-view 1920x1080 YUV420 10-bit arc rig, 20000 Voronoi segments per view, "
+            "workload": "8-view 1920x1080 YUV420 10-bit arc rig, 20000 weighted Voronoi segments per view (log-area sigma 0.5), "
                         "256 inverse-depth labels over [1.5, 10] m, bilinear, FP32 cost volume",
             "views": wl.n_views, "width": 1920, "height": 1080, "segments": int(sum(wl.S)),
             "labels": wl.num_labels, "targets": "all other views", "evals_per_step": evals,
-            "seed": wl.seed, "step": "pack + segment index + work list + sweep + argmin",
+            "seed": wl.seed, "workload_sha": wl_sha, "log_area_sigma": wl.info["area_sigma"],
+            "step": "pack + segment index + work list + sweep + argmin",
         },
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "sweep_ms": {"mean": float(np.mean(sweep_ms)), "min": float(np.min(sweep_ms))},

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from tests import _problems as P
-from tests.gpu_common import compare, tie_aware
+from tests.gpu_common import compare
 
 pytestmark = pytest.mark.gpu
 
@@ -101,11 +101,7 @@ def test_server_rule_frames_match_oracle(dtype):
                 assert stats[i]["rows_recomputed"] == int((src == 0).sum())
                 assert stats[i]["rows_from_iframe"] == int((src == 2).sum())
             assert (src == 0).any() and (src != 0).any()
-        # FP16 storage (2^-12 near 0.25) makes near-equal labels tie: strict
-        # agreement at 99%, tie-aware at 99.9%, as for the other FP16 cases
-        compare(outs[i][keep], want[keep], f16=f16, argmin_min=0.99 if f16 else 0.999, label=f"frame {i}")
-        if f16:
-            assert tie_aware(outs[i][keep], want[keep], 2.0 ** -11) >= 0.999
+        compare(outs[i][keep], want[keep], f16=f16, label=f"frame {i}")
         total_checked += keep.sum()
         prev, mean_prev = want, mean
     assert total_checked >= 0.99 * len(frames) * outs[0].shape[0]
