@@ -264,7 +264,9 @@ def voronoi(width, height, n_seeds, rng, weight_sigma=0.0, k_candidates=12, jitt
 
     Seeds are uniform over the image, or with `jittered` one uniform point in
     each of `n_seeds` distinct cells drawn from the smallest grid of about
-    square cells that has at least `n_seeds` of them (more regular cells).
+    square cells that has at least `n_seeds` of them (more regular cells),
+    taken in raster order of the cells, so that segment ids follow the image
+    as those of grid-seeded superpixel methods do.
     With weight_sigma > 0 the cells are multiplicatively weighted: pixel p
     joins argmin_i |p - c_i| / w_i with w_i ~ LogNormal(0, weight_sigma),
     searched among the k nearest seeds (exact ties, which need coincident
@@ -277,7 +279,7 @@ def voronoi(width, height, n_seeds, rng, weight_sigma=0.0, k_candidates=12, jitt
     if jittered:
         nx = int(np.ceil(np.sqrt(n_seeds * width / height)))
         ny = int(np.ceil(n_seeds / nx))
-        cell = rng.choice(nx * ny, n_seeds, replace=False)
+        cell = np.sort(rng.choice(nx * ny, n_seeds, replace=False))   # raster order of the grid
         seeds = np.stack([(cell % nx + rng.uniform(0, 1, n_seeds)) * (width / nx),
                           (cell // nx + rng.uniform(0, 1, n_seeds)) * (height / ny)], axis=1)
     else:

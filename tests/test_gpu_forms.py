@@ -97,6 +97,40 @@ def test_batched_mixed_label_counts_other_shapes():
         b.close()
 
 
+def test_batched_full_size_1080p_frames():
+    """The batching workload at full size: three 8-view 1920x1080 frames with
+    their own segment and label counts, one persistent launch replayed from a
+    hipGraph in the autotuned shape, as the benchmark times it.  Every frame
+    is bitwise its plain launch, and 200 seeded rows per frame are checked
+    against the oracle."""
+    _case("batched full size")
+    wls = synth.make_batch_frames(3)
+    assert {wl.num_labels for wl in wls} == {128, 256} and all(wl.seg[0].shape == (1080, 1920) for wl in wls)
+    dvs = [ivde.DeviceViews.from_workload(wl) for wl in wls]
+    lrs = [ivde.label_range(wl.z_near, wl.z_far, wl.num_labels) for wl in wls]
+    big = int(np.argmax([dv.rows * wl.num_labels for dv, wl in zip(dvs, wls)]))
+    tuned, _ = ivde.autotune(dvs[big], lrs[big], ivde.options(ivde.BILINEAR, ivde.F32), reps=1)
+    opt = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=tuned.labels_per_lane,
+                       waves_per_group=tuned.waves_per_group)
+    ref = [ivde.cost_volume(dv, lr, opt)[0] for dv, lr in zip(dvs, lrs)]
+    costs = [torch.full_like(r, -1.0) for r in ref]
+    labs = [torch.full((r.shape[0],), -1, dtype=torch.int32, device="cuda") for r in ref]
+    b = ivde.Batch([(dv, lr, c, l) for dv, lr, c, l in zip(dvs, lrs, costs, labs)], opt)
+    torch.cuda.synchronize()
+    b.run(stream=torch.cuda.Stream(), use_graph=True)
+    torch.cuda.synchronize()
+    b.close()
+    rng = np.random.default_rng(21)
+    for i, (wl, c, l, r) in enumerate(zip(wls, costs, labs, ref)):
+        assert torch.equal(c, r), f"frame {i}"
+        assert torch.equal(l, ivde.argmin(r)), f"frame {i}"
+        rows = np.sort(rng.choice(c.shape[0], 200, replace=False))
+        G = c[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+        res = compare(G, run_oracle(wl, rows=rows), label=f"frame {i}")
+        assert res["max_err"] <= 1e-4, res
+        print(f"frame {i}: segments {sum(wl.S)} labels {wl.num_labels} {res}", flush=True)
+
+
 def test_autotune():
     _case("autotune")
     wl = synth.make_small_arc(seed=5, n_views=4, width=160, height=96, n_segments=120, num_labels=96)
