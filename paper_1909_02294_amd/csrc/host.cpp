@@ -238,6 +238,7 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
     ly.off_tasks = take(sizeof(Task) * (size_t)ly.n_tasks);
     ly.off_centre = take(sizeof(int32_t) * 2 * (size_t)ly.total_rows);
     ly.off_mean = take(sizeof(float) * 4 * (size_t)ly.total_rows);
+    ly.off_sums = take(sizeof(uint64_t) * 6 * (size_t)ly.total_rows);
     ly.workspace_bytes = off;
     ly.cost_bytes = (size_t)ly.total_rows * ly.L * (ly.f16 ? 2 : 4);
     return ly;
@@ -457,6 +458,26 @@ ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *
     if (e != hipSuccess) return hip_fail(e, "segment index");
     e = launch_worklist(dp, extents_of(ly), problem_index, tasks, s);
     if (e != hipSuccess) return hip_fail(e, "work list");
+    return IVDE_OK;
+}
+
+ivde_status enqueue_stats(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                          const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
+                          const Layout &ly, char *ws, Task *tasks, int32_t *count_flat, hipStream_t s)
+{
+    HostConstants hc;
+    ivde_status st = compose(n, cams, views, segs, labels, opt, ly, ws, nullptr, hc);
+    if (st != IVDE_OK) return st;
+    hipError_t e = upload_constants(hc, ly, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "constant upload");
+    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "flag reset");
+    e = launch_pack(dp, extents_of(ly), ly.tex_f32, s);
+    if (e != hipSuccess) return hip_fail(e, "texel packing");
+    e = launch_segment_sums(dp, extents_of(ly), reinterpret_cast<unsigned long long *>(ws + ly.off_sums),
+                            ly.total_rows, count_flat, tasks, s);
+    if (e != hipSuccess) return hip_fail(e, "segment statistics");
     return IVDE_OK;
 }
 

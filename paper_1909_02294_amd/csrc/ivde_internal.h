@@ -84,6 +84,8 @@ struct Extents {
     int max_w, max_h, max_s, max_bands;
 };
 hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
+// the bordered texel image of every view
+hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
 // a new frame over an index already built for the same segmentation:
 // repack the texels and refresh the records' colours
 hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
@@ -105,6 +107,11 @@ hipError_t launch_copy_rows(const void *src, void *dst, int64_t bytes, hipStream
 // Per-segment count, centre and mean colour (needs the segment index);
 // count_flat [rows] may be null.
 hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, int32_t *count_flat, hipStream_t s);
+// segment statistics from the segment map alone (no segment index): clears
+// and fills sums [rows][6], then counts, centres and means; with tasks, also
+// the work list in row order
+hipError_t launch_segment_sums(const Problem *dprob, const Extents &ext, unsigned long long *sums, int64_t rows,
+                               int32_t *count_flat, Task *tasks, hipStream_t s);
 hipError_t launch_temporal_rule(int64_t rows, const float *mean, const float *prev, const float *iframe, float t_p,
                                 float t_i, uint8_t *source, uint8_t *changed, int32_t *counts, hipStream_t s);
 hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *source, int which, const void *from,

@@ -773,6 +773,17 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
+{
+    dim3 blk(64, 4);
+    dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + 3) / 4), (unsigned)ext.n_views);
+    if (tex_f32)
+        hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
+    else
+        hipLaunchKernelGGL(k_pack<uint2>, grd, blk, 0, s, dprob);
+    return hipGetLastError();
+}
+
 hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
 {
     const unsigned nv = (unsigned)ext.n_views;
@@ -781,12 +792,8 @@ hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32,
         hipLaunchKernelGGL(k_index_init, dim3((unsigned)((n + 255) / 256), nv), dim3(256), 0, s, dprob);
     }
     {
-        dim3 blk(64, 4);
-        dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + 3) / 4), nv);
-        if (tex_f32)
-            hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
-        else
-            hipLaunchKernelGGL(k_pack<uint2>, grd, blk, 0, s, dprob);
+        const hipError_t e = launch_pack(dprob, ext, tex_f32, s);
+        if (e != hipSuccess) return e;
     }
     {
         dim3 blk(64, 4);
@@ -802,12 +809,8 @@ hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32,
 {
     const unsigned nv = (unsigned)ext.n_views;
     {
-        dim3 blk(64, 4);
-        dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + 3) / 4), nv);
-        if (tex_f32)
-            hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
-        else
-            hipLaunchKernelGGL(k_pack<uint2>, grd, blk, 0, s, dprob);
+        const hipError_t e = launch_pack(dprob, ext, tex_f32, s);
+        if (e != hipSuccess) return e;
     }
     const int64_t px = (int64_t)ext.max_w * ext.max_h;
     const unsigned bx = (unsigned)std::min<int64_t>((px + 255) / 256, 4096);

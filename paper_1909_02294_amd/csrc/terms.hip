@@ -56,6 +56,150 @@ __global__ void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__
     }
 }
 
+// Pixel sums of every segment straight from the segment map, without the
+// segment index: count, sum x, sum y and the sums of Y, Cb, Cr (chroma at
+// (x >> k, y >> k)), in 64-bit integers at [row][6].  A 256-thread block
+// covers a 64 x kSumRows tile; each wave row is split into runs of equal id,
+// a run's colour sums are differences of wave prefix sums, and the runs of a
+// tile meet in an LDS table before one set of global atomics per distinct
+// segment.  Integer sums do not depend on the order of the additions.
+constexpr int kSumRows = 16;
+constexpr int kSumSlots = 128;
+
+__device__ __forceinline__ uint32_t plane_at(const void *p, int64_t off, int bit_depth)
+{
+    if (bit_depth <= 8) return static_cast<const uint8_t *>(p)[off];
+    return static_cast<const uint16_t *>(p)[off];
+}
+
+__device__ __forceinline__ void sums_global(unsigned long long *row, uint32_t n, uint32_t sx, uint32_t sy,
+                                            uint32_t c0, uint32_t c1, uint32_t c2)
+{
+    atomicAdd(row + 0, (unsigned long long)n);
+    atomicAdd(row + 1, (unsigned long long)sx);
+    atomicAdd(row + 2, (unsigned long long)sy);
+    atomicAdd(row + 3, (unsigned long long)c0);
+    atomicAdd(row + 4, (unsigned long long)c1);
+    atomicAdd(row + 5, (unsigned long long)c2);
+}
+
+__global__ __launch_bounds__(256) void k_seg_sums(const Problem *__restrict__ P, unsigned long long *__restrict__ sums)
+{
+    __shared__ int key[kSumSlots];
+    __shared__ uint32_t acc[6][kSumSlots];
+    const ViewDesc &v = P->views[blockIdx.z];
+    const int b = P->bit_depth, k = P->chroma_shift;
+    const int tid = threadIdx.y * kWave + threadIdx.x;
+    if (tid < kSumSlots) {
+        key[tid] = -1;
+        for (int c = 0; c < 6; ++c) acc[c][tid] = 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x;
+    const int x = blockIdx.x * kWave + lane;
+    unsigned long long *rows = sums + 6 * v.row0;
+    for (int r = 0; r < kSumRows / 4; ++r) {
+        const int y = blockIdx.y * kSumRows + 4 * r + threadIdx.y;
+        const bool in = x < v.W && y < v.H;
+        int id = in ? v.seg[(int64_t)y * v.seg_pitch + x] : -1;
+        if (in && (id < 0 || id >= v.S)) {
+            atomicOr(P->flag, 1);
+            id = -1;
+        }
+        uint32_t col[3] = {0, 0, 0};
+        if (id >= 0) {
+            col[0] = plane_at(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
+            col[1] = plane_at(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
+            col[2] = plane_at(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+        }
+        // inclusive prefix sums over the wave row (at most 64 x 65535 each)
+        uint32_t pre[3] = {col[0], col[1], col[2]};
+        for (int d = 1; d < kWave; d <<= 1)
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t t = __shfl_up(pre[c], d);
+                if (lane >= d) pre[c] += t;
+            }
+        const int prev = __shfl_up(id, 1);
+        const int next = __shfl_down(id, 1);
+        const bool head = id >= 0 && (lane == 0 || prev != id);
+        const bool tail = id >= 0 && (lane == kWave - 1 || next != id);
+        const uint64_t tails = __ballot(tail);
+        // the run of a head lane ends at the first tail at or after it
+        const int end = head ? __builtin_ctzll(tails & (~0ull << lane)) : lane;
+        uint32_t before[3], upto[3];
+        for (int c = 0; c < 3; ++c) {
+            before[c] = __shfl_up(pre[c], 1);
+            upto[c] = __shfl(pre[c], end);
+        }
+        if (head) {
+            const uint32_t len = (uint32_t)(end - lane + 1);
+            uint32_t cs[3];
+            for (int c = 0; c < 3; ++c) cs[c] = upto[c] - (lane > 0 ? before[c] : 0u);
+            const uint32_t sx = len * (uint32_t)x + len * (len - 1) / 2, sy = len * (uint32_t)y;
+            int slot = id & (kSumSlots - 1), probe = 0;
+            for (; probe < kSumSlots; ++probe) {
+                const int k0 = atomicCAS(&key[slot], -1, id);
+                if (k0 == -1 || k0 == id) break;
+                slot = (slot + 1) & (kSumSlots - 1);
+            }
+            if (probe < kSumSlots) {
+                atomicAdd(&acc[0][slot], len);
+                atomicAdd(&acc[1][slot], sx);
+                atomicAdd(&acc[2][slot], sy);
+                for (int c = 0; c < 3; ++c) atomicAdd(&acc[3 + c][slot], cs[c]);
+            } else {
+                sums_global(rows + 6 * (int64_t)id, len, sx, sy, cs[0], cs[1], cs[2]);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < kSumSlots && key[tid] >= 0)
+        sums_global(rows + 6 * (int64_t)key[tid], acc[0][tid], acc[1][tid], acc[2][tid], acc[3][tid], acc[4][tid],
+                    acc[5][tid]);
+}
+
+// Count, centre (centroid rounded half up) and mean colour from the sums,
+// one thread per segment (the same formulas as k_seg_stats).
+__global__ void k_seg_finish(const Problem *__restrict__ P, const unsigned long long *__restrict__ sums,
+                             int32_t *__restrict__ count_flat)
+{
+    const ViewDesc &v = P->views[blockIdx.y];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= v.S) return;
+    const unsigned long long *r = sums + 6 * (v.row0 + s);
+    const unsigned long long n = r[0];
+    if (count_flat) count_flat[v.row0 + s] = (int32_t)n;
+    if (n == 0) {
+        v.centre[2 * s] = v.centre[2 * s + 1] = -1;
+        for (int c = 0; c < 4; ++c) v.mean[4 * s + c] = 0.f;
+        return;
+    }
+    const double dn = (double)n;
+    v.centre[2 * s] = (int)floor((double)r[1] / dn + 0.5);
+    v.centre[2 * s + 1] = (int)floor((double)r[2] / dn + 0.5);
+    for (int c = 0; c < 3; ++c) v.mean[4 * s + c] = (float)((double)r[3 + c] / dn);
+    v.mean[4 * s + 3] = 0.f;
+}
+
+// Tasks in row order (view, segment, label block), for kernels that need no
+// spatial ordering of their work.
+__global__ void k_row_tasks(const Problem *__restrict__ P, Task *__restrict__ tasks)
+{
+    const ViewDesc &v = P->views[blockIdx.y];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= v.S) return;
+    const int nb = P->n_lblocks;
+    Task *t = tasks + (v.row0 + s) * nb;
+    for (int b = 0; b < nb; ++b) {
+        Task tk;
+        tk.problem = 0;
+        tk.view = blockIdx.y;
+        tk.seg = s;
+        tk.lblock = b;
+        t[b] = tk;
+    }
+}
+
 // ------------------------------------------------------------------ window matching core
 template <bool TEXF32>
 __device__ __forceinline__ void texel_at(const void *tex, uint32_t tp, int X, int Y, float &y, float &u, float &v)
@@ -496,6 +640,23 @@ hipError_t launch_segment_stats(const Problem *dprob, const Extents &ext, int32_
 {
     hipLaunchKernelGGL(k_seg_stats, dim3((unsigned)((ext.max_s + 3) / 4), (unsigned)ext.n_views), dim3(256), 0, s,
                        dprob, count_flat);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sums(const Problem *dprob, const Extents &ext, unsigned long long *sums, int64_t rows,
+                               int32_t *count_flat, Task *tasks, hipStream_t s)
+{
+    hipError_t e = launch_fill_i32(reinterpret_cast<int32_t *>(sums), 0, 12 * rows, s);
+    if (e != hipSuccess) return e;
+    const unsigned nv = (unsigned)ext.n_views;
+    {
+        dim3 blk(64, 4);
+        dim3 grd((unsigned)((ext.max_w + 63) / 64), (unsigned)((ext.max_h + kSumRows - 1) / kSumRows), nv);
+        hipLaunchKernelGGL(k_seg_sums, grd, blk, 0, s, dprob, sums);
+    }
+    const unsigned gs = (unsigned)((ext.max_s + 255) / 256);
+    hipLaunchKernelGGL(k_seg_finish, dim3(gs, nv), dim3(256), 0, s, dprob, sums, count_flat);
+    if (tasks) hipLaunchKernelGGL(k_row_tasks, dim3(gs, nv), dim3(256), 0, s, dprob, tasks);
     return hipGetLastError();
 }
 

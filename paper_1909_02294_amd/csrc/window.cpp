@@ -65,12 +65,10 @@ ivde_status ivde_window_cost(int32_t n_views, const ivde_camera *cams, const ivd
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
-    st = enqueue_front(n_views, cams, views, segs, labels, &o, ly, ws, nullptr, 0, tasks, s);
+    st = enqueue_stats(n_views, cams, views, segs, labels, &o, ly, ws, tasks, nullptr, s);
     if (st != IVDE_OK) return st;
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
-    hipError_t e = launch_segment_stats(dp, extents_of(ly), nullptr, s);
-    if (e != hipSuccess) return hip_fail(e, "segment statistics");
-    e = launch_window(dp, tasks, ly.n_tasks, radius, ly.tex_f32, m_out, hit_out, s);
+    hipError_t e = launch_window(dp, tasks, ly.n_tasks, radius, ly.tex_f32, m_out, hit_out, s);
     if (e != hipSuccess) return hip_fail(e, "window matching");
     return IVDE_OK;
 }
@@ -121,12 +119,9 @@ ivde_status ivde_segment_stats(int32_t n_views, const ivde_camera *cams, const i
     if ((st = check_tex_limits(ly)) != IVDE_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
-    st = enqueue_front(n_views, cams, views, segs, &lr, &o, ly, ws, nullptr, 0, tasks, s);
+    st = enqueue_stats(n_views, cams, views, segs, &lr, &o, ly, ws, nullptr, count_out, s);
     if (st != IVDE_OK) return st;
-    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
-    hipError_t e = launch_segment_stats(dp, extents_of(ly), count_out, s);
-    if (e != hipSuccess) return hip_fail(e, "segment statistics");
+    hipError_t e;
     if (centre_out &&
         (e = launch_copy_rows(ws + ly.off_centre, centre_out, (int64_t)ly.total_rows * 8, s)) != hipSuccess)
         return hip_fail(e, "centre copy");
