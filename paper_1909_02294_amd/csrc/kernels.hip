@@ -307,12 +307,34 @@ __device__ __forceinline__ int segment_band(const ViewDesc &v, int s)
     return b < v.n_bands ? b : v.n_bands - 1;
 }
 
+// counter[key] += 1 for every active lane, one atomic per distinct key in
+// the wave (neighbouring segments mostly share a band, and one atomic per
+// lane on one address serialises); returns the counter's old value plus the
+// lane's rank among the active lanes with its key.
+__device__ __forceinline__ int wave_increment(int *counter, int key)
+{
+    const int lane = lane_id();
+    uint64_t pending = __ballot(1);
+    int out = 0;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int k = __shfl(key, leader);
+        const uint64_t group = __ballot(key == k) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counter[k], (int)__popcll(group));
+        base = __shfl(base, leader);
+        if ((group >> lane) & 1) out = base + (int)__popcll(group & ((1ull << lane) - 1));
+        pending &= ~group;
+    }
+    return out;
+}
+
 __global__ void k_band_count(const Problem *__restrict__ P)
 {
     const ViewDesc &v = P->views[blockIdx.y];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= v.S) return;
-    atomicAdd(&v.band_count[segment_band(v, s)], 1);
+    wave_increment(v.band_count, segment_band(v, s));
 }
 
 // Band cursors: exclusive scan of the band counts (one thread per view; a
@@ -331,7 +353,8 @@ __global__ void k_band_scan(const Problem *__restrict__ P)
 
 // Tasks of one problem: view-major, spatial bands inside a view (segments
 // near each other run near each other in time), label blocks innermost.
-// The order inside a band depends on atomics; no result depends on it.
+// The order of waves inside a band depends on atomics (inside a wave it is
+// segment order); no result depends on it.
 __global__ void k_task_fill(const Problem *__restrict__ P, int problem_index, Task *__restrict__ tasks)
 {
     const int vi = blockIdx.y;
@@ -339,7 +362,7 @@ __global__ void k_task_fill(const Problem *__restrict__ P, int problem_index, Ta
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= v.S) return;
     const int nb = P->n_lblocks;
-    const int pos = atomicAdd(&v.band_count[v.n_bands + segment_band(v, s)], 1);
+    const int pos = wave_increment(v.band_count + v.n_bands, segment_band(v, s));
     Task *t = tasks + (v.row0 + pos) * nb;
     for (int b = 0; b < nb; ++b) {
         Task tk;
