@@ -20,7 +20,7 @@ def _case(name):
     print(f"[case] {name}", flush=True)
 
 
-@pytest.mark.parametrize("chroma,bits", [(0, 8), (1, 10), (1, 12)])
+@pytest.mark.parametrize("chroma,bits", [(0, 8), (1, 10), (1, 12), (0, 16)])
 def test_segment_stats(chroma, bits):
     _case(f"stats {chroma} {bits}")
     ns = P.tiny_problem(50 + bits, n_views=3, width=57, height=31, n_seg=25, L=2, chroma_shift=chroma, bit_depth=bits)
@@ -35,6 +35,38 @@ def test_segment_stats(chroma, bits):
     g = mean.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(g[:, :3], omean, rtol=1e-6, atol=1e-6)
     assert np.all(g[:, 3] == 0)
+
+
+def test_segment_stats_one_pixel_segments_and_several_tiles():
+    """Every pixel its own segment on a 150 x 40 image (1024 distinct ids per
+    64 x 16 tile, more than the per-tile table holds, so most sums take the
+    direct global path), in a shuffled order, beside a view of large random
+    segments: counts, centres and means exact against the oracle."""
+    _case("stats one-pixel segments")
+    ns = P.tiny_problem(77, n_views=2, width=150, height=40, n_seg=30, L=2, chroma_shift=1, bit_depth=10)
+    rng = np.random.default_rng(3)
+    ns.seg[0] = rng.permutation(150 * 40).reshape(40, 150).astype(np.int32)
+    ns.S[0] = 150 * 40
+    dv = ivde.DeviceViews(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift)
+    cnt, cen, mean, ws = ivde.segment_stats(dv)
+    torch.cuda.synchronize()
+    assert ivde.workspace_status(ws) == ivde.IVDE_OK
+    pb = oracle.Problem(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, 10, 1, 1.0, 2.0, 1, False)
+    oc, ocen, omean = oracle.all_segment_stats(pb)
+    np.testing.assert_array_equal(cnt.cpu().numpy(), oc)
+    np.testing.assert_array_equal(cen.cpu().numpy(), ocen)
+    np.testing.assert_allclose(mean.cpu().numpy()[:, :3].astype(np.float64), omean, rtol=1e-6, atol=1e-6)
+
+
+def test_segment_stats_reports_out_of_range_ids():
+    _case("stats bad id")
+    ns = P.tiny_problem(78, n_views=2, width=40, height=20, n_seg=8, L=2)
+    ns.seg[1] = ns.seg[1].copy()
+    ns.seg[1][5, 7] = ns.S[1] + 3
+    dv = ivde.DeviceViews(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift)
+    *_, ws = ivde.segment_stats(dv)
+    torch.cuda.synchronize()
+    assert ivde.workspace_status(ws) == ivde.IVDE_EINVAL
 
 
 def test_temporal_rule_kernel():
