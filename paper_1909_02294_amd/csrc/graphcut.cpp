@@ -48,7 +48,7 @@ public:
     // arc i->j of capacity c (cut when i is on the source side, j on the sink side)
     void add_edge(int i, int j, int64_t c) { edges_.push_back({i, j, c}); }
     int64_t solve();
-    // nodes reachable from the source in the residual graph
+    // nodes reachable from the source in the residual graph (after solve)
     void source_side(std::vector<uint8_t> &out) const;
 
 private:
@@ -343,26 +343,14 @@ void MaxFlow::adopt()
     }
 }
 
+// When the search stops, no source-tree node has a residual arc to a node
+// outside the tree (that node would still be active) and every tree node
+// reaches the source along its parent arcs, so the source tree is exactly
+// the set of nodes reachable from the source in the residual graph.
 void MaxFlow::source_side(std::vector<uint8_t> &out) const
 {
-    out.assign(n_, 0);
-    std::vector<int> st;
-    for (int i = 0; i < n_; ++i)
-        if (tr_[i] > 0) {
-            out[i] = 1;
-            st.push_back(i);
-        }
-    while (!st.empty()) {
-        const int i = st.back();
-        st.pop_back();
-        for (int a = first_[i]; a < first_[i + 1]; ++a) {
-            const int j = head_[a];
-            if (!out[j] && rcap_[a] > 0) {
-                out[j] = 1;
-                st.push_back(j);
-            }
-        }
-    }
+    out.resize(n_);
+    for (int i = 0; i < n_; ++i) out[i] = parent_[i] != kNone && !sink_[i];
 }
 
 // ------------------------------------------------------------------ energy
