@@ -252,6 +252,43 @@ def test_served_frames_match_oracle_and_carry_rows():
     srv.close()
 
 
+def test_served_full_size_1080p_rig_sampled_rows():
+    """The serving workload's 8-view 1080p rig at full size (20000 segments
+    per view, 256 levels, FP16 storage) through the server: an I frame, then
+    a P frame whose changed mask marks the segments that see moved planes.
+    1000 seeded rows of the I frame and up to 1000 changed rows of the P frame
+    against the oracle at the FP16 bars; every unchanged row of the P frame is
+    bitwise the I frame's."""
+    from types import SimpleNamespace
+
+    _case("served full size")
+    seed = synth.SEED_SERVING + 17
+    wl = synth.make_arc_workload("rigB", seed, n_views=8, width=1920, height=1080, f=1400.0, n_segments=20000,
+                                 num_labels=256, arc_deg=30.0)
+    frames = synth.make_sequence(wl, 2, seed + 7, tries=3)
+    mask = np.concatenate(frames[1]["mask"])
+    assert 0 < mask.sum() < len(mask)
+    srv = ivde.Server(8 << 30, max_slots=2)
+    rig = _Rig(srv, wl, frames, ivde.F16)
+    stats = [srv.wait(rig.submit(srv, i)) for i in range(2)]
+    assert stats[0]["rows_recomputed"] == stats[0]["rows_total"] == len(mask)
+    assert stats[1]["rows_recomputed"] == int(mask.sum())
+    keep = torch.from_numpy(~mask).cuda()
+    assert torch.equal(rig.out[1][keep], rig.out[0][keep])
+    rng = np.random.default_rng(31)
+    for i, pool in ((0, np.arange(len(mask))), (1, np.flatnonzero(mask))):
+        rows = np.sort(rng.choice(pool, min(1000, len(pool)), replace=False))
+        fr = frames[i]
+        ns = SimpleNamespace(cams=wl.cams, Y=fr["Y"], U=fr["U"], V=fr["V"], seg=wl.seg, S=wl.S,
+                             bit_depth=wl.bit_depth, chroma_shift=wl.chroma_shift, z_near=wl.z_near,
+                             z_far=wl.z_far, num_labels=wl.num_labels, bilinear=True)
+        G = rig.out[i][torch.from_numpy(rows).cuda()].double().cpu().numpy()
+        res = compare(G, run_oracle(ns, rows=rows), f16=True, label=f"frame {i}")
+        assert torch.equal(rig.lab[i], ivde.argmin(rig.out[i]))
+        print(f"frame {i}: changed {int(mask.sum()) if i else len(mask)} rows, {res}", flush=True)
+    srv.close()
+
+
 def test_served_same_alone_and_in_the_mix():
     _case("alone vs mix")
     seqs = [_rig_sequence(50, 3, 120, 72, 90, 64, 5), _rig_sequence(60, 4, 160, 96, 150, 96, 5),
