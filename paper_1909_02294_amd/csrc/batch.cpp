@@ -118,7 +118,7 @@ ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_op
     b.off_tasks = off;
     off = align_up(off + sizeof(Task) * (size_t)b.n_tasks, 256);
     b.off_counters = off;
-    off = align_up(off + 2 * sizeof(int32_t), 256);
+    off = align_up(off + (kXcds + 1) * sizeof(int32_t), 256);   // cursors, then the task count
     // keep host copies of the frame descriptions: the plan outlives the caller's arrays
     b.cams.resize(n_frames);
     b.views.resize(n_frames);
@@ -163,8 +163,9 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
     if ((e = launch_upload(b.ws + b.off_probs, probs.data(), sizeof(Problem) * probs.size(), s)) != hipSuccess)
         return hip_fail(e, "batch problem table");
     int32_t *counters = reinterpret_cast<int32_t *>(b.ws + b.off_counters);
-    if ((e = launch_fill_i32(counters, 0, 1, s)) != hipSuccess) return hip_fail(e, "batch cursor");
-    if ((e = launch_fill_i32(counters + 1, (int32_t)b.n_tasks, 1, s)) != hipSuccess) return hip_fail(e, "batch count");
+    if ((e = launch_fill_i32(counters, 0, kXcds, s)) != hipSuccess) return hip_fail(e, "batch cursors");
+    if ((e = launch_fill_i32(counters + kXcds, (int32_t)b.n_tasks, 1, s)) != hipSuccess)
+        return hip_fail(e, "batch count");
     // timing events only in eager runs: a captured graph replays without them
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "capture status");
@@ -172,7 +173,7 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
     if (timed && (e = hipEventRecord(static_cast<hipEvent_t>(b.opt.sweep_events[0]), s)) != hipSuccess)
         return hip_fail(e, "event record");
     e = launch_sweep_persistent(reinterpret_cast<const Problem *>(b.ws + b.off_probs),
-                                reinterpret_cast<const Task *>(b.ws + b.off_tasks), counters + 1, counters,
+                                reinterpret_cast<const Task *>(b.ws + b.off_tasks), counters + kXcds, counters,
                                 b.n_tasks, b.J, b.bilinear, b.tex_f32, b.f16, b.wpg, b.n_groups, s);
     if (e != hipSuccess) return hip_fail(e, "batch sweep");
     if (timed && (e = hipEventRecord(static_cast<hipEvent_t>(b.opt.sweep_events[1]), s)) != hipSuccess)

@@ -8,6 +8,7 @@ namespace ivde {
 
 constexpr int kMaxViews = 32;          // views per problem (pair table is n x n)
 constexpr int kBand = 32;              // rows per spatial band of the work list
+constexpr int kXcds = 8;               // XCDs of the MI355X; consecutive blocks go to consecutive XCDs
 constexpr float kEdge = 1.0f / 64.0f;  // bilinear margin outside the outer pixel centres
 
 // Per-view device descriptor.  Everything a kernel needs about one view:
@@ -93,8 +94,9 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
                            hipStream_t s);
 hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J,
                         int bilinear, int tex_f32, int f16out, int waves_per_group, hipStream_t s);
+// cursors: kXcds zeroed counters, one per contiguous range of the task list
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
-                                   int32_t *cursor, int64_t max_tasks, int J, int bilinear, int tex_f32,
+                                   int32_t *cursors, int64_t max_tasks, int J, int bilinear, int tex_f32,
                                    int f16out, int waves_per_group, int n_groups, hipStream_t s);
 // Resident groups per CU of the persistent sweep for this launch shape.
 hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16out, int waves_per_group,

@@ -692,17 +692,27 @@ template <int J, bool BIL, bool TEXF32, bool F16OUT>
 __global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restrict__ probs,
                                                           const Task *__restrict__ tasks,
                                                           const int32_t *__restrict__ n_tasks,
-                                                          int32_t *__restrict__ cursor, int64_t max_tasks)
+                                                          int32_t *__restrict__ cursors, int64_t max_tasks)
 {
     const int lane = lane_id();
     const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(cursor, 1);
-        t = uniform(__shfl(t, 0));
-        if (t >= limit) break;
-        const Task task = ldu_task(tasks + t);
-        sweep_task<J, BIL, TEXF32, F16OUT>(probs + task.problem, task);
+    // The task list is cut into kXcds contiguous ranges with a cursor each.
+    // Block b runs on XCD b mod kXcds: its waves drain their own XCD's range
+    // first (so that XCD's L2 holds the image bands those tasks gather
+    // from), then help with the other ranges in turn.  Every wave tries
+    // every range until it is empty, so all waves end.
+    const int home = (int)(blockIdx.x % kXcds);
+    for (int k = 0; k < kXcds; ++k) {
+        const int x = (home + k) % kXcds;
+        const int64_t lo = limit * x / kXcds, n = limit * (x + 1) / kXcds - lo;
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(&cursors[x], 1);
+            t = uniform(__shfl(t, 0));
+            if (t >= n) break;
+            const Task task = ldu_task(tasks + lo + t);
+            sweep_task<J, BIL, TEXF32, F16OUT>(probs + task.problem, task);
+        }
     }
 }
 
@@ -869,11 +879,11 @@ static hipError_t sweep_plain(const Problem *dprobs, const Task *tasks, int64_t 
 }
 
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
-static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursor,
+static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursors,
                              int64_t max_tasks, int wpg, int n_groups, hipStream_t s)
 {
     hipLaunchKernelGGL((k_sweep_persistent<J, BIL, TEXF32, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
-                       dprobs, tasks, n_tasks, cursor, max_tasks);
+                       dprobs, tasks, n_tasks, cursors, max_tasks);
     return hipGetLastError();
 }
 
@@ -934,14 +944,14 @@ hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16o
 }
 
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
-                                   int32_t *cursor, int64_t max_tasks, int J, int bilinear, int tex_f32,
+                                   int32_t *cursors, int64_t max_tasks, int J, int bilinear, int tex_f32,
                                    int f16out, int wpg, int n_groups, hipStream_t s)
 {
     switch (J) {
-    case 1: IVDE_DISPATCH_FLAGS(sweep_pers, 1, dprobs, tasks, n_tasks_dev, cursor, max_tasks, wpg, n_groups, s);
-    case 2: IVDE_DISPATCH_FLAGS(sweep_pers, 2, dprobs, tasks, n_tasks_dev, cursor, max_tasks, wpg, n_groups, s);
-    case 4: IVDE_DISPATCH_FLAGS(sweep_pers, 4, dprobs, tasks, n_tasks_dev, cursor, max_tasks, wpg, n_groups, s);
-    case 8: IVDE_DISPATCH_FLAGS(sweep_pers, 8, dprobs, tasks, n_tasks_dev, cursor, max_tasks, wpg, n_groups, s);
+    case 1: IVDE_DISPATCH_FLAGS(sweep_pers, 1, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
+    case 2: IVDE_DISPATCH_FLAGS(sweep_pers, 2, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
+    case 4: IVDE_DISPATCH_FLAGS(sweep_pers, 4, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
+    case 8: IVDE_DISPATCH_FLAGS(sweep_pers, 8, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
     default: return hipErrorInvalidValue;
     }
 }

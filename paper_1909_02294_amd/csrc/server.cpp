@@ -277,7 +277,8 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     const int bil = rig.opt.sampling == IVDE_BILINEAR;
     char *extra = arena_base + r.work_off;
-    int32_t *counters = reinterpret_cast<int32_t *>(extra);   // [0] tasks kept, [1] cursor, [2..4] rule counts
+    // [0] tasks kept, [2..4] rule counts, [8, 8 + kXcds) sweep cursors
+    int32_t *counters = reinterpret_cast<int32_t *>(extra);
     Task *changed = reinterpret_cast<Task *>(extra + 256);
     uint8_t *source = reinterpret_cast<uint8_t *>(extra + 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256));
     uint8_t *rule_mask = source + align_up((size_t)ly.total_rows, 256);
@@ -301,7 +302,7 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
             rig.has_i = true;
         }
     } else {
-        if ((e = launch_fill_i32(counters, 0, 5, s)) != hipSuccess) return hip_fail(e, "serve counters");
+        if ((e = launch_fill_i32(counters, 0, 8 + kXcds, s)) != hipSuccess) return hip_fail(e, "serve counters");
         if (r.rule) {
             const float scale = (float)(1 << (r.views[0].bit_depth - 8));
             if ((e = launch_temporal_rule(ly.total_rows, mean, rig.mean_prev, rig.mean_i, rig.t_p * scale,
@@ -321,7 +322,7 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
             return hip_fail(e, "occupancy");
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess)
             return hip_fail(e, "device attribute");
-        if ((e = launch_sweep_persistent(dp, changed, counters, counters + 1, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16,
+        if ((e = launch_sweep_persistent(dp, changed, counters, counters + 8, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16,
                                          ly.wpg, std::max(1, per_cu) * std::max(1, cus), s)) != hipSuccess)
             return hip_fail(e, "serve sweep");
         if ((e = hipMemcpyAsync(sl.count_host, counters, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
