@@ -463,7 +463,7 @@ ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *
 
 ivde_status enqueue_stats(int32_t n, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
-                          const Layout &ly, char *ws, Task *tasks, int32_t *count_flat, hipStream_t s)
+                          const Layout &ly, char *ws, Task *tasks, int32_t *count_flat, hipStream_t s, bool texels)
 {
     HostConstants hc;
     ivde_status st = compose(n, cams, views, segs, labels, opt, ly, ws, nullptr, hc);
@@ -473,8 +473,8 @@ ivde_status enqueue_stats(int32_t n, const ivde_camera *cams, const ivde_image *
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    e = launch_pack(dp, extents_of(ly), ly.tex_f32, s);
-    if (e != hipSuccess) return hip_fail(e, "texel packing");
+    if (texels && (e = launch_pack(dp, extents_of(ly), ly.tex_f32, s)) != hipSuccess)
+        return hip_fail(e, "texel packing");
     e = launch_segment_sums(dp, extents_of(ly), reinterpret_cast<unsigned long long *>(ws + ly.off_sums),
                             ly.total_rows, count_flat, tasks, s);
     if (e != hipSuccess) return hip_fail(e, "segment statistics");

@@ -54,11 +54,13 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
                     void *cost_out, HostConstants &hc);
 hipError_t upload_constants(const HostConstants &hc, const Layout &ly, char *ws_base, hipStream_t s);
 Extents extents_of(const Layout &ly);
-// Constants, texels and segment statistics from the segment map alone (no
-// segment index); with tasks, the work list in row order.
+// Constants, segment statistics from the segment map alone (no segment
+// index) and, with texels, the packed texel images; with tasks, the work list
+// in row order.
 ivde_status enqueue_stats(int32_t n, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
-                          const Layout &ly, char *ws, Task *tasks, int32_t *count_flat, hipStream_t s);
+                          const Layout &ly, char *ws, Task *tasks, int32_t *count_flat, hipStream_t s,
+                          bool texels = true);
 // index_ready: the workspace already holds the segment index and work list
 // of this segmentation and layout; only the frame's images are taken in
 ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,

@@ -119,7 +119,7 @@ ivde_status ivde_segment_stats(int32_t n_views, const ivde_camera *cams, const i
     if ((st = check_tex_limits(ly)) != IVDE_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    st = enqueue_stats(n_views, cams, views, segs, &lr, &o, ly, ws, nullptr, count_out, s);
+    st = enqueue_stats(n_views, cams, views, segs, &lr, &o, ly, ws, nullptr, count_out, s, false);
     if (st != IVDE_OK) return st;
     hipError_t e;
     if (centre_out &&
