@@ -97,6 +97,40 @@ def test_window_tiny(seed, rotated, chroma, bits, radius):
     _compare(ns, radius, min_checked=0.98)
 
 
+def test_window_empty_segments_and_end_views():
+    """Two unused ids per view (empty segments: no centre, no match at any
+    level) on a 3-view rig, where the end views have one neighbour each;
+    everything else against the oracle."""
+    _case("window empty segments")
+    ns = P.tiny_problem(431, n_views=3, width=40, height=24, n_seg=10, L=65, rotated=True, chroma_shift=1,
+                        bit_depth=10)
+    ns.S = [s + 2 for s in ns.S]
+    m, hit, _ = _compare(ns, 1, min_checked=0.97)
+    m, hit = m.cpu().numpy(), hit.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(ns.S)])
+    for v in range(3):
+        empty = np.arange(off[v + 1] - 2, off[v + 1])
+        assert np.all(np.isnan(m[empty])) and np.all(hit[empty] == -1)
+    # slot 0 of the first view and slot 1 of the last have no neighbour view
+    assert np.all(np.isnan(m[: off[1], 0])) and np.all(hit[: off[1], 0] == -1)
+    assert np.all(np.isnan(m[off[2]:, 1])) and np.all(hit[off[2]:, 1] == -1)
+
+
+def test_window_single_view_and_bad_id():
+    _case("window single view, bad id")
+    ns = P.tiny_problem(432, n_views=1, width=30, height=20, n_seg=6, L=10)
+    m, hit = _gpu(ns, 1)
+    assert torch.isnan(m).all() and (hit == -1).all()
+    ns = P.tiny_problem(433, n_views=2, width=30, height=20, n_seg=6, L=10)
+    ns.seg[0] = ns.seg[0].copy()
+    ns.seg[0][4, 4] = ns.S[0] + 1
+    dv = ivde.DeviceViews(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift)
+    lr = ivde.label_range(ns.z_near, ns.z_far, ns.num_labels)
+    *_, ws = ivde.window_cost(dv, lr, 1)
+    torch.cuda.synchronize()
+    assert ivde.workspace_status(ws) == ivde.IVDE_EINVAL
+
+
 def test_window_small_arc_and_energy():
     _case("window arc + energy")
     wl = synth.make_small_arc(seed=77, n_views=5, width=192, height=108, n_segments=200, num_labels=96)
