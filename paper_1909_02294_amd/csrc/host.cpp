@@ -438,7 +438,7 @@ Extents extents_of(const Layout &ly)
 ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
                           const Layout &ly, char *ws, void *cost_out, int problem_index, Task *tasks,
-                          hipStream_t s, bool index_ready)
+                          hipStream_t s, bool index_ready, bool texels, bool worklist)
 {
     HostConstants hc;
     ivde_status st = compose(n, cams, views, segs, labels, opt, ly, ws, cost_out, hc);
@@ -454,10 +454,10 @@ ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *
     }
     e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s);
+    e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s, texels);
     if (e != hipSuccess) return hip_fail(e, "segment index");
-    e = launch_worklist(dp, extents_of(ly), problem_index, tasks, s);
-    if (e != hipSuccess) return hip_fail(e, "work list");
+    if (worklist && (e = launch_worklist(dp, extents_of(ly), problem_index, tasks, s)) != hipSuccess)
+        return hip_fail(e, "work list");
     return IVDE_OK;
 }
 

@@ -62,12 +62,14 @@ ivde_status enqueue_stats(int32_t n, const ivde_camera *cams, const ivde_image *
                           const Layout &ly, char *ws, Task *tasks, int32_t *count_flat, hipStream_t s,
                           bool texels = true);
 // index_ready: the workspace already holds the segment index and work list
-// of this segmentation and layout; only the frame's images are taken in
+// of this segmentation and layout; only the frame's images are taken in.
+// texels / worklist = false skip the packed texels / the work list for
+// callers that read only the index.
 ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels, const ivde_options *opt,
                           const Layout &ly, char *ws, void *cost_out, int problem_index, Task *tasks,
                           hipStream_t s,
-                          bool index_ready = false);
+                          bool index_ready = false, bool texels = true, bool worklist = true);
 ivde_status check_workspace(const void *workspace, size_t have, size_t need);
 ivde_status check_tex_limits(const Layout &ly);
 

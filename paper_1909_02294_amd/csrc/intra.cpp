@@ -28,10 +28,17 @@ ivde_options index_options()
 
 const ivde_label_range kIndexLabels{1.0, 2.0, 1, IVDE_REF_RIG_CENTER};
 
-// The index workspace, then the block sums of the offsets scan.
+// The index workspace, the block sums of the offsets scan, then the first
+// kAdjKeep neighbour ids of every row.
+size_t adjacency_sums_bytes(const Layout &ly)
+{
+    return align_up(sizeof(int64_t) * (size_t)((ly.total_rows + 255) / 256 + 1), 256);
+}
+
 size_t adjacency_workspace(const Layout &ly)
 {
-    return align_up(ly.workspace_bytes, 256) + align_up(sizeof(int64_t) * (size_t)((ly.total_rows + 255) / 256 + 1), 256);
+    return align_up(ly.workspace_bytes, 256) + adjacency_sums_bytes(ly) +
+           align_up(sizeof(int32_t) * kAdjKeep * (size_t)ly.total_rows, 256);
 }
 
 }  // namespace
@@ -79,17 +86,19 @@ ivde_status ivde_adjacency(int32_t n_views, const ivde_camera *cams, const ivde_
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     int64_t *block_sums = reinterpret_cast<int64_t *>(ws + align_up(ly.workspace_bytes, 256));
+    int32_t *kept = reinterpret_cast<int32_t *>(ws + align_up(ly.workspace_bytes, 256) + adjacency_sums_bytes(ly));
     Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
-    st = enqueue_front(n_views, cams, views, segs, &kIndexLabels, &o, ly, ws, nullptr, 0, tasks, s);
+    // the pixel records only: no texels, no work list
+    st = enqueue_front(n_views, cams, views, segs, &kIndexLabels, &o, ly, ws, nullptr, 0, tasks, s, false, false, false);
     if (st != IVDE_OK) return st;
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     const Extents ext = extents_of(ly);
     const float inv_scale = 1.0f / (float)(1 << (views[0].bit_depth - 8));
     hipError_t e = launch_segment_stats(dp, ext, nullptr, s);
-    if (e == hipSuccess) e = launch_adjacency(dp, ext, 0, offsets, nullptr, nullptr, 0, beta0, eps, inv_scale, s);
+    if (e == hipSuccess) e = launch_adjacency(dp, ext, 0, offsets, nullptr, nullptr, 0, beta0, eps, inv_scale, kept, s);
     if (e == hipSuccess) e = launch_scan_rows(offsets, ly.total_rows, block_sums, s);
     if (e == hipSuccess && capacity > 0)
-        e = launch_adjacency(dp, ext, 1, offsets, index, beta, capacity, beta0, eps, inv_scale, s);
+        e = launch_adjacency(dp, ext, 1, offsets, index, beta, capacity, beta0, eps, inv_scale, kept, s);
     if (e != hipSuccess) return hip_fail(e, "adjacency");
     return IVDE_OK;
 }

@@ -84,7 +84,8 @@ struct Extents {
     int n_views;
     int max_w, max_h, max_s, max_bands;
 };
-hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
+// segment index (counts, offsets, boxes, pixel records) and, with pack, the texels
+hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s, bool pack = true);
 // the bordered texel image of every view
 hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
 // a new frame over an index already built for the same segmentation:
@@ -119,8 +120,12 @@ hipError_t launch_temporal_rule(int64_t rows, const float *mean, const float *pr
 hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *source, int which, const void *from,
                                   void *to, hipStream_t s);
 // Window matching core towards views c - 1 and c + 1 for every task.
+// kept: [rows][kAdjKeep] neighbour ids written by the count pass and copied
+// by the fill pass for rows with at most kAdjKeep neighbours
+constexpr int kAdjKeep = 32;
 hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write, int64_t *offsets, int32_t *index,
-                            float *beta, int64_t capacity, float beta0, float eps, float inv_scale, hipStream_t s);
+                            float *beta, int64_t capacity, float beta0, float eps, float inv_scale, int32_t *kept,
+                            hipStream_t s);
 // In-place inclusive scan of a[1..n] with a[0] = 0; block_sums holds
 // ceil(n / 256) (at least 1) int64 of scratch.
 hipError_t launch_scan_rows(int64_t *a, int64_t n, int64_t *block_sums, hipStream_t s);

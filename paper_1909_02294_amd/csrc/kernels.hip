@@ -817,14 +817,14 @@ hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hi
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
+hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s, bool pack)
 {
     const unsigned nv = (unsigned)ext.n_views;
     {
         const int n = ext.max_s > 2 * ext.max_bands ? ext.max_s : 2 * ext.max_bands;
         hipLaunchKernelGGL(k_index_init, dim3((unsigned)((n + 255) / 256), nv), dim3(256), 0, s, dprob);
     }
-    {
+    if (pack) {
         const hipError_t e = launch_pack(dprob, ext, tex_f32, s);
         if (e != hipSuccess) return e;
     }

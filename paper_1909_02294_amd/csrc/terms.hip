@@ -465,20 +465,38 @@ __device__ __forceinline__ int min_above(const int (&c)[4], int last, int m)
     return m;
 }
 
-// WRITE = false: offsets[row + 1] = number of neighbours.  WRITE = true (after
-// the scan): the neighbour rows and their Eq. (3) weights from offsets[row],
-// entries at or beyond `capacity` skipped.
+// WRITE = false: offsets[row + 1] = number of neighbours, and the first
+// kAdjKeep neighbour ids in kept[row].  WRITE = true (after the scan): the
+// neighbour rows and their Eq. (3) weights from offsets[row], entries at or
+// beyond `capacity` skipped; rows with at most kAdjKeep neighbours copy them
+// from kept (one lane each), longer lists are extracted again.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P, int64_t *__restrict__ offsets,
                                                    int32_t *__restrict__ index, float *__restrict__ beta,
-                                                   int64_t capacity, float beta0, float eps, float inv_scale)
+                                                   int64_t capacity, float beta0, float eps, float inv_scale,
+                                                   int32_t *__restrict__ kept)
 {
     const ViewDesc &v = P->views[blockIdx.y];
     const int lane = lane_id();
     const int s = uniform(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
     if (s >= v.S) return;
-    const int p0 = v.offsets[s], p1 = v.offsets[s + 1];
     const int64_t row = v.row0 + s;
+    int32_t *keep = kept + row * kAdjKeep;
+    if (WRITE) {
+        const int64_t o = offsets[row], n = offsets[row + 1] - o;
+        if (n <= kAdjKeep) {
+            if (lane < n && o + lane < capacity) {
+                const int m = keep[lane];
+                const float4 ms = reinterpret_cast<const float4 *>(v.mean)[s];
+                const float4 mt = reinterpret_cast<const float4 *>(v.mean)[m];
+                const float d = (fabsf(ms.x - mt.x) + fabsf(ms.y - mt.y) + fabsf(ms.z - mt.z)) * inv_scale;
+                index[o + lane] = (int32_t)(v.row0 + m);
+                beta[o + lane] = beta0 / (d + eps);
+            }
+            return;
+        }
+    }
+    const int p0 = v.offsets[s], p1 = v.offsets[s + 1];
     const float *rec = v.pixrec;
     const bool cached = p1 - p0 <= kAdjCache * kWave;
     int c[kAdjCache][4];
@@ -514,6 +532,7 @@ __global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P
             const float d = (fabsf(ms.x - mt.x) + fabsf(ms.y - mt.y) + fabsf(ms.z - mt.z)) * inv_scale;
             beta[out + k] = beta0 / (d + eps);
         }
+        if (!WRITE && lane == 0 && k < kAdjKeep) keep[k] = m;
         ++k;
         last = m;
     }
@@ -717,15 +736,16 @@ hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32
 }
 
 hipError_t launch_adjacency(const Problem *dprob, const Extents &ext, int write, int64_t *offsets, int32_t *index,
-                            float *beta, int64_t capacity, float beta0, float eps, float inv_scale, hipStream_t s)
+                            float *beta, int64_t capacity, float beta0, float eps, float inv_scale, int32_t *kept,
+                            hipStream_t s)
 {
     const dim3 grid((unsigned)((ext.max_s + 3) / 4), (unsigned)ext.n_views);
     if (write)
         hipLaunchKernelGGL(k_adjacency<true>, grid, dim3(256), 0, s, dprob, offsets, index, beta, capacity, beta0, eps,
-                           inv_scale);
+                           inv_scale, kept);
     else
         hipLaunchKernelGGL(k_adjacency<false>, grid, dim3(256), 0, s, dprob, offsets, index, beta, capacity, beta0,
-                           eps, inv_scale);
+                           eps, inv_scale, kept);
     return hipGetLastError();
 }
 
