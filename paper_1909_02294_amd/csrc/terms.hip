@@ -601,7 +601,12 @@ __global__ __launch_bounds__(256) void k_scan_apply(int64_t *__restrict__ a, int
 
 // Eq. (2) with the neighbours' labels held: out[r][l] = sum over entries
 // (r, t) of beta * |l - d_t|, only over t with fixed[t] != 0 when a mask is
-// given.  One wave per (row, 64-label block); lanes are labels.
+// given.  One wave per row: the lanes load up to 64 of the row's entries at
+// once (weight and neighbour label), then every entry is read back from its
+// lane and applied to kIntraBlocks 64-label blocks, lanes being labels.
+// Each label accumulates the entries in order, as a plain loop would.
+constexpr int kIntraBlocks = 4;
+
 __global__ __launch_bounds__(256) void k_intra_cost(int64_t rows, int L, int n_lblocks,
                                                     const int64_t *__restrict__ offsets,
                                                     const int32_t *__restrict__ index, const float *__restrict__ beta,
@@ -609,21 +614,46 @@ __global__ __launch_bounds__(256) void k_intra_cost(int64_t rows, int L, int n_l
                                                     const uint8_t *__restrict__ fixed, float *__restrict__ out)
 {
     const int lane = lane_id();
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + uniform(threadIdx.x / kWave);
-    if (w >= rows * n_lblocks) return;
-    const int64_t r = w / n_lblocks;
-    const int l = (int)(w - r * n_lblocks) * kWave + lane;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + uniform(threadIdx.x / kWave);
+    if (r >= rows) return;
     const int64_t e0 = ldu(offsets + r), e1 = ldu(offsets + r + 1);
-    float acc = 0.f;
-    for (int64_t e = e0; e < e1; ++e) {
-        const int t = ldu(index + e);
-        if (t < 0 || t >= rows) continue;
-        if (fixed && !fixed[t]) continue;
-        acc = fmaf(ldu(beta + e), fabsf((float)(l - ldu(labelling + t))), acc);
+    for (int b0 = 0; b0 < n_lblocks; b0 += kIntraBlocks) {
+        float acc[kIntraBlocks];
+#pragma unroll
+        for (int k = 0; k < kIntraBlocks; ++k) acc[k] = 0.f;
+        for (int64_t c = e0; c < e1; c += kWave) {
+            const int64_t e = c + lane;
+            float bj = 0.f;
+            int dj = 0;
+            bool ok = false;
+            if (e < e1) {
+                const int t = index[e];
+                ok = t >= 0 && t < rows && (!fixed || fixed[t]);
+                if (ok) {
+                    bj = beta[e];
+                    dj = labelling[t];
+                }
+            }
+            const uint64_t use = __ballot(ok);
+            const int n = (int)min((int64_t)kWave, e1 - c);
+            for (int j = 0; j < n; ++j) {
+                if (!((use >> j) & 1)) continue;
+                const float bb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bj), j));
+                const int dd = __builtin_amdgcn_readlane(dj, j);
+#pragma unroll
+                for (int k = 0; k < kIntraBlocks; ++k) {
+                    const int l = (b0 + k) * kWave + lane;
+                    acc[k] = fmaf(bb, fabsf((float)(l - dd)), acc[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kIntraBlocks; ++k) {
+            const int l = (b0 + k) * kWave + lane;
+            if (b0 + k < n_lblocks && l < L) out[r * L + l] = acc[k];
+        }
     }
-    if (l < L) out[r * L + l] = acc;
 }
-
 
 // ------------------------------------------------------------------ depth maps
 // Sec. III-B: each pixel takes the depth of its segment's level.  The level
@@ -768,7 +798,7 @@ hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const 
 {
     if (rows <= 0) return hipSuccess;
     const int nb = (L + 63) / 64;
-    const int64_t blocks = (rows * nb + 3) / 4;
+    const int64_t blocks = (rows + 3) / 4;      // one wave per row
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_intra_cost, dim3((unsigned)blocks), dim3(256), 0, s, rows, L, nb, offsets, index, beta,
                        labelling, fixed, out);

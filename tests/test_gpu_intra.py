@@ -119,6 +119,16 @@ def test_islands_streamed_path():
     assert off[1] - off[0] > 200
 
 
+@pytest.mark.parametrize("L", [1, 64, 300])
+def test_intra_cost_level_counts_and_long_rows(L):
+    """Eq. (2) costs with 1, 64 and 300 levels (more label blocks than one
+    pass of the kernel holds) on the islands map, whose background row has
+    hundreds of entries (several 64-entry chunks)."""
+    _case(f"intra cost L={L}")
+    ns = P.islands_problem(6)
+    _compare(ns, 9.0, L=L, seed=L)
+
+
 def test_capacity_and_count_only():
     _case("intra capacity")
     ns = P.blocky_problem(9, [(30, 20), (25, 25)], [50, 40])
