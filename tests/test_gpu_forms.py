@@ -345,6 +345,40 @@ def test_server_budget_queues_and_rejects():
     srv.close()
 
 
+def test_served_empty_and_tiny_masks():
+    """A P frame with no changed segment (nothing swept: the persistent
+    sweep gets an empty task list) and one with a single changed segment
+    (fewer tasks than XCD ranges): unchanged rows are carried bit for bit and
+    the changed row equals a plain launch on that frame."""
+    _case("served empty / tiny masks")
+    wl, frames = _rig_sequence(91, 3, 96, 64, 60, 32, 3)
+    srv = ivde.Server(1 << 30, max_slots=2)
+    rig = _Rig(srv, wl, frames, ivde.F32)
+    rows = rig.dv.rows
+    rig.masks[1] = torch.zeros(rows, dtype=torch.uint8, device="cuda")
+    one = torch.zeros(rows, dtype=torch.uint8, device="cuda")
+    one[rows // 2] = 1
+    rig.masks[2] = one
+    st = [srv.wait(rig.submit(srv, i)) for i in range(3)]
+    assert st[1]["rows_recomputed"] == 0 and st[2]["rows_recomputed"] == 1
+    assert torch.equal(rig.out[1], rig.out[0])
+    keep = one == 0
+    assert torch.equal(rig.out[2][keep], rig.out[1][keep])
+    _, _, plain = _plain_frame(wl, frames[2], rig.opt)
+    assert torch.equal(rig.out[2][rows // 2], plain[rows // 2])
+    for i in range(3):
+        assert torch.equal(rig.lab[i], ivde.argmin(rig.out[i]))
+    srv.close()
+
+
+def _plain_frame(wl, fr, opt):
+    dv = ivde.DeviceViews(wl.cams, fr["Y"], fr["U"], fr["V"], wl.seg, wl.S, wl.bit_depth, wl.chroma_shift)
+    lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
+    C, _ = ivde.cost_volume(dv, lr, opt)
+    torch.cuda.synchronize()
+    return dv, lr, C
+
+
 def test_rig_reset_forces_full_frame():
     _case("reset")
     wl, frames = _rig_sequence(90, 3, 96, 64, 60, 32, 3)
