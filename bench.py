@@ -357,7 +357,7 @@ def copy_calibration(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window", "intra", "depth"], default="plain")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
