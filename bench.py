@@ -357,7 +357,8 @@ def copy_calibration(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 10 batches in batched mode; 1 frame in depth mode)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window", "intra", "depth"], default="plain")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
@@ -373,6 +374,8 @@ def main():
     ap.add_argument("--rule", action="store_true",
                     help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"depth": 1, "batched": 10}.get(args.mode, 20)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the sweep would shard "
               "by view, frame or level block, needing only the images replicated to every GPU)",
