@@ -112,9 +112,19 @@ def cpu_baseline(wl, target_seconds=15.0, seed=7):
     mean_row = per_row.mean()
     n = int(min(len(order), max(512, target_seconds * rate / mean_row)))
     dt, ev = run(order[:n])
-    return {"value": ev / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # the same oracle on one thread, over a smaller seeded sample (about 3 s)
+    n1 = int(min(n, max(32, 3.0 * (ev / dt) / cores / mean_row)))
+    oracle.set_num_threads(1)
+    try:
+        dt1, ev1 = run(order[:n1])
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": ev / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded rows of {len(counts)} ({100.0 * n / len(counts):.1f}%), {ev:.3g} evals, "
-                      f"{dt:.1f} s, FP64 ray-plane oracle with OpenMP"}
+                      f"{dt:.1f} s, FP64 ray-plane oracle with OpenMP",
+            "per_core": {"value": ev1 / dt1, "unit": "evals/s", "cores": 1,
+                         "sample": f"{n1} of the same rows, {ev1:.3g} evals, {dt1:.1f} s on one thread"}}
 
 
 def percentile(xs, q):

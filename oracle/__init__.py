@@ -78,6 +78,8 @@ def load():
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         lib.oracle_segment_stats.restype = ctypes.c_int
         lib.oracle_segment_stats.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]
@@ -91,6 +93,11 @@ def load():
 
 def num_threads() -> int:
     return int(load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for the following calls (for timing; no result depends on it)."""
+    load().oracle_set_num_threads(int(n))
 
 
 def target_matrix(n_views: int, targets="all", explicit=None) -> np.ndarray:

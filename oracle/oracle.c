@@ -140,6 +140,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads for the following calls (timing only; results do not depend on it). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Cost rows for the requested (view, segment) pairs.
  *   cost      n_rows x L          C[c][s][l]
