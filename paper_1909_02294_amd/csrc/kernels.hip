@@ -82,29 +82,45 @@ __global__ void k_index_init(const Problem *__restrict__ P)
 // full resolution (pixel (x, y) owns chroma (x >> k, y >> k)).  Texel
 // (X, Y) holds pixel (clamp(X - 1), clamp(Y - 1)): a one-texel border that
 // repeats the edge, so a bilinear sample up to one pixel outside the image
-// reads the edge value, which is the clamped sample.
+// reads the edge value, which is the clamped sample.  A thread packs
+// kPackRows texels of one column (rows blockDim.y apart), its loads issued
+// together.
+constexpr int kPackRows = 4;
+
 template <typename TexT>
-__global__ void k_pack(const Problem *__restrict__ P)
+__global__ __launch_bounds__(256) void k_pack(const Problem *__restrict__ P)
 {
     const ViewDesc &v = P->views[blockIdx.z];
+    const int W = v.W, H = v.H;
     const int X = blockIdx.x * blockDim.x + threadIdx.x;
-    const int Y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (X > v.W + 1 || Y > v.H + 1) return;
-    const int x = min(max(X - 1, 0), v.W - 1), y = min(max(Y - 1, 0), v.H - 1);
+    if (X > W + 1) return;
     const int k = P->chroma_shift, b = P->bit_depth;
-    const float c0 = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
-    const float c1 = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
-    const float c2 = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
-    TexT *t = static_cast<TexT *>(v.tex) + (int64_t)Y * v.tex_pitch + X;
-    if constexpr (sizeof(TexT) == 8) {
-        __half2 a = __floats2half2_rn(c0, c1);
-        __half2 bb = __floats2half2_rn(c2, 0.f);
-        uint2 w;
-        w.x = __builtin_bit_cast(uint32_t, a);
-        w.y = __builtin_bit_cast(uint32_t, bb);
-        *reinterpret_cast<uint2 *>(t) = w;
-    } else {
-        *reinterpret_cast<float4 *>(t) = make_float4(c0, c1, c2, 0.f);
+    const void *p0 = v.plane[0], *p1 = v.plane[1], *p2 = v.plane[2];
+    const int64_t s0 = v.pitch[0], s1 = v.pitch[1], s2 = v.pitch[2];
+    const int x = min(max(X - 1, 0), W - 1);
+    const int Y0 = blockIdx.y * (blockDim.y * kPackRows) + threadIdx.y;
+    float c0[kPackRows], c1[kPackRows], c2[kPackRows];
+#pragma unroll
+    for (int q = 0; q < kPackRows; ++q) {
+        const int Y = min(Y0 + q * (int)blockDim.y, H + 1);   // rows past the end repeat the last
+        const int y = min(max(Y - 1, 0), H - 1);
+        c0[q] = sample_plane(p0, (int64_t)y * s0 + x, b);
+        c1[q] = sample_plane(p1, (int64_t)(y >> k) * s1 + (x >> k), b);
+        c2[q] = sample_plane(p2, (int64_t)(y >> k) * s2 + (x >> k), b);
+    }
+#pragma unroll
+    for (int q = 0; q < kPackRows; ++q) {
+        const int Y = Y0 + q * (int)blockDim.y;
+        if (Y > H + 1) break;
+        TexT *t = static_cast<TexT *>(v.tex) + (int64_t)Y * v.tex_pitch + X;
+        if constexpr (sizeof(TexT) == 8) {
+            uint2 w;
+            w.x = __builtin_bit_cast(uint32_t, __floats2half2_rn(c0[q], c1[q]));
+            w.y = __builtin_bit_cast(uint32_t, __floats2half2_rn(c2[q], 0.f));
+            *reinterpret_cast<uint2 *>(t) = w;
+        } else {
+            *reinterpret_cast<float4 *>(t) = make_float4(c0[q], c1[q], c2[q], 0.f);
+        }
     }
 }
 
@@ -717,32 +733,80 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restr
 }
 
 // ------------------------------------------------------------------ argmin
-template <bool F16>
-__global__ void k_argmin(const void *__restrict__ cost, int64_t rows, int L, int32_t *__restrict__ out)
+// V consecutive costs of one row as FP32 (V = 4: one 16- or 8-byte load).
+template <bool F16, int V>
+__device__ __forceinline__ void load_costs(const void *__restrict__ cost, int64_t i, float (&x)[V])
+{
+    if constexpr (V == 4) {
+        if constexpr (F16) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(static_cast<const __half *>(cost) + i);
+            x[0] = h_lo(w.x);
+            x[1] = h_hi(w.x);
+            x[2] = h_lo(w.y);
+            x[3] = h_hi(w.y);
+        } else {
+            const float4 w = *reinterpret_cast<const float4 *>(static_cast<const float *>(cost) + i);
+            x[0] = w.x;
+            x[1] = w.y;
+            x[2] = w.z;
+            x[3] = w.w;
+        }
+    } else {
+        x[0] = F16 ? __half2float(static_cast<const __half *>(cost)[i]) : static_cast<const float *>(cost)[i];
+    }
+}
+
+// (value, label) keeps the lowest label among equal minima; NaN never wins.
+__device__ __forceinline__ void argmin_take(float x, int l, float &bv, int &bi)
+{
+    if (x != x) x = __builtin_inff();
+    if (x < bv || (x == bv && l < bi)) {
+        bv = x;
+        bi = l;
+    }
+}
+
+// One wave per kRowsPerWave rows: lane k holds labels V k + 64 V i, and the
+// loads of all the wave's rows are issued before the first comparison, so
+// a wave keeps several rows of reads in flight.  V = 4 needs L % 4 == 0 and
+// a 4-element-aligned base (checked on the host).
+constexpr int kArgminRows = 4;
+
+template <bool F16, int V>
+__global__ __launch_bounds__(256) void k_argmin(const void *__restrict__ cost, int64_t rows, int L,
+                                                int32_t *__restrict__ out)
 {
     const int lane = lane_id();
-    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (r >= rows) return;
-    float bv = __builtin_inff();
-    int bi = 0x7fffffff;
-    for (int l = lane; l < L; l += kWave) {
-        float x = F16 ? __half2float(static_cast<const __half *>(cost)[r * L + l])
-                      : static_cast<const float *>(cost)[r * L + l];
-        if (x != x) x = __builtin_inff();       // NaN never wins
-        if (x < bv || (x == bv && l < bi)) {
-            bv = x;
-            bi = l;
-        }
+    const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kArgminRows;
+    if (r0 >= rows) return;
+    float bv[kArgminRows];
+    int bi[kArgminRows];
+#pragma unroll
+    for (int q = 0; q < kArgminRows; ++q) {
+        bv[q] = __builtin_inff();
+        bi[q] = 0x7fffffff;
     }
-    for (int d = 32; d >= 1; d >>= 1) {
-        const float ov = __shfl_xor(bv, d);
-        const int oi = __shfl_xor(bi, d);
-        if (ov < bv || (ov == bv && oi < bi)) {
-            bv = ov;
-            bi = oi;
+    for (int l0 = lane * V; l0 < L; l0 += kWave * V) {
+        float x[kArgminRows][V];
+#pragma unroll
+        for (int q = 0; q < kArgminRows; ++q) {
+            const int64_t r = min(r0 + q, rows - 1);     // rows past the end repeat the last
+            load_costs<F16, V>(cost, r * L + l0, x[q]);
         }
+#pragma unroll
+        for (int q = 0; q < kArgminRows; ++q)
+#pragma unroll
+            for (int k = 0; k < V; ++k) argmin_take(x[q][k], l0 + k, bv[q], bi[q]);
     }
-    if (lane == 0) out[r] = bi == 0x7fffffff ? 0 : bi;
+#pragma unroll
+    for (int q = 0; q < kArgminRows; ++q) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            const float ov = __shfl_xor(bv[q], d);
+            const int oi = __shfl_xor(bi[q], d);
+            argmin_take(ov, oi, bv[q], bi[q]);
+        }
+        if (lane == 0 && r0 + q < rows) out[r0 + q] = bi[q] == 0x7fffffff ? 0 : bi[q];
+    }
 }
 
 // ------------------------------------------------------------------ temporal
@@ -809,7 +873,8 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
 hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
 {
     dim3 blk(64, 4);
-    dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + 3) / 4), (unsigned)ext.n_views);
+    const int rows = 4 * kPackRows;
+    dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + rows - 1) / rows), (unsigned)ext.n_views);
     if (tex_f32)
         hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
     else
@@ -959,12 +1024,20 @@ hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, con
 hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s)
 {
     if (rows <= 0) return hipSuccess;
-    const int64_t blocks = (rows + 3) / 4;
+    const int64_t per_block = 4 * kArgminRows;
+    const int64_t blocks = (rows + per_block - 1) / per_block;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (f16)
-        hipLaunchKernelGGL(k_argmin<true>, dim3((unsigned)blocks), dim3(256), 0, s, cost, rows, L, out);
+    const size_t esz = f16 ? 2 : 4;
+    const bool vec = L % 4 == 0 && reinterpret_cast<uintptr_t>(cost) % (4 * esz) == 0;
+    const dim3 g((unsigned)blocks), b(256);
+    if (f16 && vec)
+        hipLaunchKernelGGL((k_argmin<true, 4>), g, b, 0, s, cost, rows, L, out);
+    else if (f16)
+        hipLaunchKernelGGL((k_argmin<true, 1>), g, b, 0, s, cost, rows, L, out);
+    else if (vec)
+        hipLaunchKernelGGL((k_argmin<false, 4>), g, b, 0, s, cost, rows, L, out);
     else
-        hipLaunchKernelGGL(k_argmin<false>, dim3((unsigned)blocks), dim3(256), 0, s, cost, rows, L, out);
+        hipLaunchKernelGGL((k_argmin<false, 1>), g, b, 0, s, cost, rows, L, out);
     return hipGetLastError();
 }
 
