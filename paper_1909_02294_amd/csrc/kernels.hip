@@ -39,10 +39,68 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, in
                                              (int)kRsrcWord3);
 }
 
-__device__ __forceinline__ float sample_plane(const void *p, int64_t off, int bit_depth)
+// Global-memory access through pointers read from a descriptor (the
+// compiler cannot tell their address space by itself).
+#define IVDE_AS1 __attribute__((address_space(1)))
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p) { return *(const IVDE_AS1 T *)(p); }
+__device__ __forceinline__ float4 ldg(const float4 *p)
 {
-    if (bit_depth <= 8) return (float)static_cast<const uint8_t *>(p)[off];
-    return (float)static_cast<const uint16_t *>(p)[off];
+    const f32x4 v = *(const IVDE_AS1 f32x4 *)(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg(float4 *p, const float4 &v)
+{
+    f32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(IVDE_AS1 f32x4 *)(p) = w;
+}
+__device__ __forceinline__ void stg(uint2 *p, const uint2 &v)
+{
+    u32x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(IVDE_AS1 u32x2 *)(p) = w;
+}
+
+// A view's planes, read once per wave into scalar registers, so stores of
+// the kernel do not force the descriptor to be read again.
+struct Planes {
+    const void *p[3];
+    int64_t pitch[3];
+    int k;       // chroma shift
+    bool wide;   // 16-bit samples
+};
+
+__device__ __forceinline__ Planes planes_of(const Problem *P, const ViewDesc *vd)
+{
+    Planes pl;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        pl.p[i] = ldu(&vd->plane[i]);
+        pl.pitch[i] = ldu(&vd->pitch[i]);
+    }
+    pl.k = ldu(&P->chroma_shift);
+    pl.wide = ldu(&P->bit_depth) > 8;
+    return pl;
+}
+
+__device__ __forceinline__ float plane_at(const Planes &pl, int i, int64_t off)
+{
+    return pl.wide ? (float)ldg(static_cast<const uint16_t *>(pl.p[i]) + off)
+                   : (float)ldg(static_cast<const uint8_t *>(pl.p[i]) + off);
+}
+
+// Y, Cb, Cr of pixel (x, y), chroma at (x >> k, y >> k).
+__device__ __forceinline__ void yuv_at(const Planes &pl, int x, int y, float &c0, float &c1, float &c2)
+{
+    c0 = plane_at(pl, 0, (int64_t)y * pl.pitch[0] + x);
+    c1 = plane_at(pl, 1, (int64_t)(y >> pl.k) * pl.pitch[1] + (x >> pl.k));
+    c2 = plane_at(pl, 2, (int64_t)(y >> pl.k) * pl.pitch[2] + (x >> pl.k));
 }
 
 // ------------------------------------------------------------------ upload
@@ -90,36 +148,33 @@ constexpr int kPackRows = 4;
 template <typename TexT>
 __global__ __launch_bounds__(256) void k_pack(const Problem *__restrict__ P)
 {
-    const ViewDesc &v = P->views[blockIdx.z];
-    const int W = v.W, H = v.H;
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.z;
+    const int W = ldu(&vd->W), H = ldu(&vd->H);
     const int X = blockIdx.x * blockDim.x + threadIdx.x;
     if (X > W + 1) return;
-    const int k = P->chroma_shift, b = P->bit_depth;
-    const void *p0 = v.plane[0], *p1 = v.plane[1], *p2 = v.plane[2];
-    const int64_t s0 = v.pitch[0], s1 = v.pitch[1], s2 = v.pitch[2];
+    const Planes pl = planes_of(P, vd);
+    TexT *tex = static_cast<TexT *>(ldu(&vd->tex));
+    const int64_t tp = ldu(&vd->tex_pitch);
     const int x = min(max(X - 1, 0), W - 1);
     const int Y0 = blockIdx.y * (blockDim.y * kPackRows) + threadIdx.y;
     float c0[kPackRows], c1[kPackRows], c2[kPackRows];
 #pragma unroll
     for (int q = 0; q < kPackRows; ++q) {
         const int Y = min(Y0 + q * (int)blockDim.y, H + 1);   // rows past the end repeat the last
-        const int y = min(max(Y - 1, 0), H - 1);
-        c0[q] = sample_plane(p0, (int64_t)y * s0 + x, b);
-        c1[q] = sample_plane(p1, (int64_t)(y >> k) * s1 + (x >> k), b);
-        c2[q] = sample_plane(p2, (int64_t)(y >> k) * s2 + (x >> k), b);
+        yuv_at(pl, x, min(max(Y - 1, 0), H - 1), c0[q], c1[q], c2[q]);
     }
 #pragma unroll
     for (int q = 0; q < kPackRows; ++q) {
         const int Y = Y0 + q * (int)blockDim.y;
         if (Y > H + 1) break;
-        TexT *t = static_cast<TexT *>(v.tex) + (int64_t)Y * v.tex_pitch + X;
+        TexT *t = tex + (int64_t)Y * tp + X;
         if constexpr (sizeof(TexT) == 8) {
             uint2 w;
             w.x = __builtin_bit_cast(uint32_t, __floats2half2_rn(c0[q], c1[q]));
             w.y = __builtin_bit_cast(uint32_t, __floats2half2_rn(c2[q], 0.f));
-            *reinterpret_cast<uint2 *>(t) = w;
+            stg(reinterpret_cast<uint2 *>(t), w);
         } else {
-            *reinterpret_cast<float4 *>(t) = make_float4(c0[q], c1[q], c2[q], 0.f);
+            stg(reinterpret_cast<float4 *>(t), make_float4(c0[q], c1[q], c2[q], 0.f));
         }
     }
 }
@@ -133,20 +188,27 @@ __global__ __launch_bounds__(256) void k_pack(const Problem *__restrict__ P)
 constexpr int kCountTileRows = 16;
 constexpr int kCountSlots = 128;
 
-__device__ __forceinline__ void count_global(const ViewDesc &v, int id, int n, int x0, int y0, int x1, int y1)
+__device__ __forceinline__ void count_global(int32_t *counts, int32_t *bbox, int id, int n, int x0, int y0, int x1,
+                                             int y1)
 {
-    atomicAdd(&v.counts[id], n);
-    atomicMin(&v.bbox[4 * id + 0], x0);
-    atomicMin(&v.bbox[4 * id + 1], y0);
-    atomicMax(&v.bbox[4 * id + 2], x1);
-    atomicMax(&v.bbox[4 * id + 3], y1);
+    atomicAdd(&counts[id], n);
+    atomicMin(&bbox[4 * id + 0], x0);
+    atomicMin(&bbox[4 * id + 1], y0);
+    atomicMax(&bbox[4 * id + 2], x1);
+    atomicMax(&bbox[4 * id + 3], y1);
 }
 
 __global__ __launch_bounds__(256) void k_seg_count(const Problem *__restrict__ P)
 {
     __shared__ int key[kCountSlots];
     __shared__ int cnt[kCountSlots], bx0[kCountSlots], by0[kCountSlots], bx1[kCountSlots], by1[kCountSlots];
-    const ViewDesc &v = P->views[blockIdx.z];
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.z;
+    const int W = ldu(&vd->W), H = ldu(&vd->H), S = ldu(&vd->S);
+    const int32_t *seg = ldu(&vd->seg);
+    const int64_t sp = ldu(&vd->seg_pitch);
+    int32_t *counts = ldu(&vd->counts);
+    int32_t *bbox = ldu(&vd->bbox);
+    int32_t *flag = ldu(&P->flag);
     const int tid = threadIdx.y * kWave + threadIdx.x;
     if (tid < kCountSlots) {
         key[tid] = -1;
@@ -157,12 +219,19 @@ __global__ __launch_bounds__(256) void k_seg_count(const Problem *__restrict__ P
     __syncthreads();
     const int lane = threadIdx.x;
     const int x = blockIdx.x * kWave + lane;
-    for (int k = 0; k < kCountTileRows / 4; ++k) {
+    constexpr int kRowsPerWave = kCountTileRows / 4;
+    int ids[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
         const int y = blockIdx.y * kCountTileRows + 4 * k + threadIdx.y;
-        const bool in = x < v.W && y < v.H;
-        int id = in ? v.seg[(int64_t)y * v.seg_pitch + x] : -1;
-        if (in && (id < 0 || id >= v.S)) {
-            atomicOr(P->flag, 1);
+        ids[k] = x < W && y < H ? ldg(seg + (int64_t)y * sp + x) : -1;
+    }
+    for (int k = 0; k < kRowsPerWave; ++k) {
+        const int y = blockIdx.y * kCountTileRows + 4 * k + threadIdx.y;
+        const bool in = x < W && y < H;
+        int id = ids[k];
+        if (in && (id < 0 || id >= S)) {
+            atomicOr(flag, 1);
             id = -1;
         }
         const int prev = __shfl_up(id, 1);
@@ -186,12 +255,13 @@ __global__ __launch_bounds__(256) void k_seg_count(const Problem *__restrict__ P
                 atomicMax(&bx1[slot], x + len - 1);
                 atomicMax(&by1[slot], y);
             } else {
-                count_global(v, id, len, x, y, x + len - 1, y);
+                count_global(counts, bbox, id, len, x, y, x + len - 1, y);
             }
         }
     }
     __syncthreads();
-    if (tid < kCountSlots && key[tid] >= 0) count_global(v, key[tid], cnt[tid], bx0[tid], by0[tid], bx1[tid], by1[tid]);
+    if (tid < kCountSlots && key[tid] >= 0)
+        count_global(counts, bbox, key[tid], cnt[tid], bx0[tid], by0[tid], bx1[tid], by1[tid]);
 }
 
 // Exclusive scan of the counts, one 1024-thread block per view.
@@ -230,87 +300,96 @@ __global__ __launch_bounds__(1024) void k_scan(const Problem *__restrict__ P)
 }
 
 // One pixel record: position, g . p~ and the pixel's Y, Cb, Cr.
-__device__ __forceinline__ void write_record(const ViewDesc &v, int k, int b, float g0, float g1, float g2, int x,
-                                             int y, int64_t pos)
+__device__ __forceinline__ void write_record(float *rec, const Planes &pl, float g0, float g1, float g2, int x, int y,
+                                             int64_t pos)
 {
     const float fx = (float)x, fy = (float)y;
     float4 r0, r1;
     r0.x = fx;
     r0.y = fy;
     r0.z = fmaf(g0, fx, fmaf(g1, fy, g2));
-    r0.w = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
-    r1.x = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
-    r1.y = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+    yuv_at(pl, x, y, r0.w, r1.x, r1.y);
     r1.z = 0.f;
     r1.w = 0.f;
-    float4 *dst = reinterpret_cast<float4 *>(v.pixrec) + 2 * pos;
-    dst[0] = r0;
-    dst[1] = r1;
+    float4 *dst = reinterpret_cast<float4 *>(rec) + 2 * pos;
+    stg(dst, r0);
+    stg(dst + 1, r1);
 }
 
 // One wave per segment scans its box in raster order and writes the pixel
 // records in that order.  A box at most half a wave wide is covered several
 // rows per step (lane order is still raster order); wider boxes row by row
-// in 64-pixel chunks.
-__global__ void k_seg_fill(const Problem *__restrict__ P)
+// in 64-pixel chunks.  The ids of the next step are loaded while the
+// current step's records are written.
+__global__ __launch_bounds__(256) void k_seg_fill(const Problem *__restrict__ P)
 {
-    const ViewDesc &v = P->views[blockIdx.y];
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
     const int lane = lane_id();
     const int s = uniform(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
-    if (s >= v.S) return;
-    const int x0 = v.bbox[4 * s + 0], y0 = v.bbox[4 * s + 1];
-    const int x1 = v.bbox[4 * s + 2], y1 = v.bbox[4 * s + 3];
+    if (s >= ldu(&vd->S)) return;
+    const int32_t *bbox = ldu(&vd->bbox) + 4 * s;
+    const int x0 = ldu(bbox + 0), y0 = ldu(bbox + 1), x1 = ldu(bbox + 2), y1 = ldu(bbox + 3);
     if (x1 < x0) return;   // empty segment
-    const int k = P->chroma_shift, b = P->bit_depth;
-    const int base = v.offsets[s];
-    const int cap = v.offsets[s + 1];
-    const float g0 = v.g[0], g1 = v.g[1], g2 = v.g[2];
+    const int32_t *offs = ldu(&vd->offsets);
+    const int base = ldu(offs + s), cap = ldu(offs + s + 1);
+    const Planes pl = planes_of(P, vd);
+    const float g0 = ldu(&vd->g[0]), g1 = ldu(&vd->g[1]), g2 = ldu(&vd->g[2]);
+    const int32_t *seg = ldu(&vd->seg);
+    const int64_t sp = ldu(&vd->seg_pitch);
+    float *rec = ldu(&vd->pixrec);
     const int bw = x1 - x0 + 1;
+    // step t covers box rows y0 + t rows .. and columns x0 + lc (small boxes),
+    // or row y0 + t / chunks, columns from 64 (t % chunks) (wide boxes)
+    const bool small = bw <= kWave / 2;
+    const int rows = small ? kWave / bw : 1;
+    const int lr = small ? lane / bw : 0, lc = small ? lane - lr * bw : lane;
+    const int chunks = small ? 1 : (bw + kWave - 1) / kWave;
+    const int steps = small ? (y1 - y0 + rows) / rows : (y1 - y0 + 1) * chunks;
+    int r = 0, ci = 0;   // row group and chunk of the next step
+    auto next_pixel = [&](int &x, int &y) {
+        y = y0 + r * rows + lr;
+        x = x0 + ci * kWave + lc;
+        if (++ci == chunks) {
+            ci = 0;
+            ++r;
+        }
+        return lr < rows && y <= y1 && x <= x1;
+    };
+    int xn, yn;
+    bool in = next_pixel(xn, yn);
+    int id = in ? ldg(seg + (int64_t)yn * sp + xn) : -1;
     int run = 0;
-    if (bw <= kWave / 2) {
-        const int rows = kWave / bw;                   // rows per step
-        const int lr = lane / bw, lc = lane - lr * bw;
-        for (int yb = y0; yb <= y1; yb += rows) {
-            const int y = yb + lr, x = x0 + lc;
-            const bool m = lr < rows && y <= y1 && v.seg[(int64_t)y * v.seg_pitch + x] == s;
-            const uint64_t bal = __ballot(m);
-            const int pos = base + run + __builtin_popcountll(bal & ((1ull << lane) - 1));
-            if (m && pos < cap) write_record(v, k, b, g0, g1, g2, x, y, pos);
-            run += __builtin_popcountll(bal);
+    for (int t = 0; t < steps; ++t) {
+        const int x = xn, y = yn, cur = id;
+        const bool m = in && cur == s;
+        if (t + 1 < steps) {
+            in = next_pixel(xn, yn);
+            id = in ? ldg(seg + (int64_t)yn * sp + xn) : -1;
         }
-        return;
-    }
-    for (int y = y0; y <= y1; ++y) {
-        for (int xb = x0; xb <= x1; xb += kWave) {
-            const int x = xb + lane;
-            const bool m = x <= x1 && v.seg[(int64_t)y * v.seg_pitch + x] == s;
-            const uint64_t bal = __ballot(m);
-            const int pos = base + run + __builtin_popcountll(bal & ((1ull << lane) - 1));
-            if (m && pos < cap) write_record(v, k, b, g0, g1, g2, x, y, pos);
-            run += __builtin_popcountll(bal);
-        }
+        const uint64_t bal = __ballot(m);
+        const int pos = base + run + __builtin_popcountll(bal & ((1ull << lane) - 1));
+        if (m && pos < cap) write_record(rec, pl, g0, g1, g2, x, y, pos);
+        run += __builtin_popcountll(bal);
     }
 }
 
 // A new frame of the same segmentation: record positions and g . p~ stay,
 // the colours are read again (the same samples a full fill would write).
-__global__ void k_seg_colour(const Problem *__restrict__ P)
+__global__ __launch_bounds__(256) void k_seg_colour(const Problem *__restrict__ P)
 {
-    const ViewDesc &v = P->views[blockIdx.y];
-    const int64_t n = v.offsets[v.S];
-    const int k = P->chroma_shift, b = P->bit_depth;
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
+    const int64_t n = ldu(ldu(&vd->offsets) + ldu(&vd->S));
+    const Planes pl = planes_of(P, vd);
+    float4 *recs = reinterpret_cast<float4 *>(ldu(&vd->pixrec));
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float4 *rec = reinterpret_cast<float4 *>(v.pixrec) + 2 * i;
-        float4 r0 = rec[0];
-        const int x = (int)r0.x, y = (int)r0.y;
-        r0.w = sample_plane(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
+        float4 *rec = recs + 2 * i;
+        float4 r0 = ldg(rec);
         float4 r1;
-        r1.x = sample_plane(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
-        r1.y = sample_plane(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+        yuv_at(pl, (int)r0.x, (int)r0.y, r0.w, r1.x, r1.y);
         r1.z = 0.f;
         r1.w = 0.f;
-        rec[0] = r0;
-        rec[1] = r1;
+        stg(rec, r0);
+        stg(rec + 1, r1);
     }
 }
 
