@@ -39,70 +39,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, in
                                              (int)kRsrcWord3);
 }
 
-// Global-memory access through pointers read from a descriptor (the
-// compiler cannot tell their address space by itself).
-#define IVDE_AS1 __attribute__((address_space(1)))
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-template <typename T>
-__device__ __forceinline__ T ldg(const T *p) { return *(const IVDE_AS1 T *)(p); }
-__device__ __forceinline__ float4 ldg(const float4 *p)
-{
-    const f32x4 v = *(const IVDE_AS1 f32x4 *)(p);
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void stg(float4 *p, const float4 &v)
-{
-    f32x4 w;
-    w.x = v.x;
-    w.y = v.y;
-    w.z = v.z;
-    w.w = v.w;
-    *(IVDE_AS1 f32x4 *)(p) = w;
-}
-__device__ __forceinline__ void stg(uint2 *p, const uint2 &v)
-{
-    u32x2 w;
-    w.x = v.x;
-    w.y = v.y;
-    *(IVDE_AS1 u32x2 *)(p) = w;
-}
-
-// A view's planes, read once per wave into scalar registers, so stores of
-// the kernel do not force the descriptor to be read again.
-struct Planes {
-    const void *p[3];
-    int64_t pitch[3];
-    int k;       // chroma shift
-    bool wide;   // 16-bit samples
-};
-
-__device__ __forceinline__ Planes planes_of(const Problem *P, const ViewDesc *vd)
-{
-    Planes pl;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        pl.p[i] = ldu(&vd->plane[i]);
-        pl.pitch[i] = ldu(&vd->pitch[i]);
-    }
-    pl.k = ldu(&P->chroma_shift);
-    pl.wide = ldu(&P->bit_depth) > 8;
-    return pl;
-}
-
-__device__ __forceinline__ float plane_at(const Planes &pl, int i, int64_t off)
-{
-    return pl.wide ? (float)ldg(static_cast<const uint16_t *>(pl.p[i]) + off)
-                   : (float)ldg(static_cast<const uint8_t *>(pl.p[i]) + off);
-}
-
-// Y, Cb, Cr of pixel (x, y), chroma at (x >> k, y >> k).
-__device__ __forceinline__ void yuv_at(const Planes &pl, int x, int y, float &c0, float &c1, float &c2)
-{
-    c0 = plane_at(pl, 0, (int64_t)y * pl.pitch[0] + x);
-    c1 = plane_at(pl, 1, (int64_t)(y >> pl.k) * pl.pitch[1] + (x >> pl.k));
-    c2 = plane_at(pl, 2, (int64_t)(y >> pl.k) * pl.pitch[2] + (x >> pl.k));
-}
-
 // ------------------------------------------------------------------ upload
 struct UploadChunk {
     unsigned char bytes[2048];

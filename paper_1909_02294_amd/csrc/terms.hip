@@ -18,17 +18,18 @@ namespace {
 // Count, centre (centroid rounded half up) and mean colour of every segment,
 // one wave per segment over its pixel records; integer sums, so the result
 // does not depend on the summation order.
-__global__ void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__ count_flat)
+__global__ __launch_bounds__(256) void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__ count_flat)
 {
-    const ViewDesc &v = P->views[blockIdx.y];
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
     const int lane = lane_id();
     const int s = uniform(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
-    if (s >= v.S) return;
-    const int p0 = v.offsets[s], p1 = v.offsets[s + 1];
+    if (s >= ldu(&vd->S)) return;
+    const int32_t *offs = ldu(&vd->offsets);
+    const int p0 = ldu(offs + s), p1 = ldu(offs + s + 1);
     unsigned long long sx = 0, sy = 0, sc[3] = {0, 0, 0};
-    const float4 *rec = reinterpret_cast<const float4 *>(v.pixrec);
+    const float4 *rec = reinterpret_cast<const float4 *>(ldu(&vd->pixrec));
     for (int i = p0 + lane; i < p1; i += kWave) {
-        const float4 r0 = rec[2 * (int64_t)i], r1 = rec[2 * (int64_t)i + 1];
+        const float4 r0 = ldg(rec + 2 * (int64_t)i), r1 = ldg(rec + 2 * (int64_t)i + 1);
         sx += (unsigned long long)r0.x;
         sy += (unsigned long long)r0.y;
         sc[0] += (unsigned long long)r0.w;
@@ -42,16 +43,19 @@ __global__ void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__
     }
     if (lane == 0) {
         const int n = p1 - p0;
-        if (count_flat) count_flat[v.row0 + s] = n;
+        int32_t *centre = ldu(&vd->centre) + 2 * s;
+        float *mean = ldu(&vd->mean) + 4 * s;
+        if (count_flat) stg(count_flat + ldu(&vd->row0) + s, (int32_t)n);
         if (n == 0) {
-            v.centre[2 * s] = v.centre[2 * s + 1] = -1;
-            for (int c = 0; c < 4; ++c) v.mean[4 * s + c] = 0.f;
+            stg(centre, -1);
+            stg(centre + 1, -1);
+            stg(reinterpret_cast<float4 *>(mean), make_float4(0.f, 0.f, 0.f, 0.f));
         } else {
             const double dn = (double)n;
-            v.centre[2 * s] = (int)floor((double)sx / dn + 0.5);
-            v.centre[2 * s + 1] = (int)floor((double)sy / dn + 0.5);
-            for (int c = 0; c < 3; ++c) v.mean[4 * s + c] = (float)((double)sc[c] / dn);
-            v.mean[4 * s + 3] = 0.f;
+            stg(centre, (int)floor((double)sx / dn + 0.5));
+            stg(centre + 1, (int)floor((double)sy / dn + 0.5));
+            stg(reinterpret_cast<float4 *>(mean), make_float4((float)((double)sc[0] / dn), (float)((double)sc[1] / dn),
+                                                              (float)((double)sc[2] / dn), 0.f));
         }
     }
 }
@@ -65,12 +69,6 @@ __global__ void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__
 // segment.  Integer sums do not depend on the order of the additions.
 constexpr int kSumRows = 16;
 constexpr int kSumSlots = 128;
-
-__device__ __forceinline__ uint32_t plane_at(const void *p, int64_t off, int bit_depth)
-{
-    if (bit_depth <= 8) return static_cast<const uint8_t *>(p)[off];
-    return static_cast<const uint16_t *>(p)[off];
-}
 
 __device__ __forceinline__ void sums_global(unsigned long long *row, uint32_t n, uint32_t sx, uint32_t sy,
                                             uint32_t c0, uint32_t c1, uint32_t c2)
@@ -87,8 +85,13 @@ __global__ __launch_bounds__(256) void k_seg_sums(const Problem *__restrict__ P,
 {
     __shared__ int key[kSumSlots];
     __shared__ uint32_t acc[6][kSumSlots];
-    const ViewDesc &v = P->views[blockIdx.z];
-    const int b = P->bit_depth, k = P->chroma_shift;
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.z;
+    const int W = ldu(&vd->W), H = ldu(&vd->H), S = ldu(&vd->S);
+    const int32_t *seg = ldu(&vd->seg);
+    const int64_t sp = ldu(&vd->seg_pitch);
+    int32_t *flag = ldu(&P->flag);
+    const Planes pl = planes_of(P, vd);
+    const int k = pl.k;
     const int tid = threadIdx.y * kWave + threadIdx.x;
     if (tid < kSumSlots) {
         key[tid] = -1;
@@ -97,20 +100,27 @@ __global__ __launch_bounds__(256) void k_seg_sums(const Problem *__restrict__ P,
     __syncthreads();
     const int lane = threadIdx.x;
     const int x = blockIdx.x * kWave + lane;
-    unsigned long long *rows = sums + 6 * v.row0;
-    for (int r = 0; r < kSumRows / 4; ++r) {
+    unsigned long long *rows = sums + 6 * ldu(&vd->row0);
+    constexpr int kRowsPerWave = kSumRows / 4;
+    int ids[kRowsPerWave];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
         const int y = blockIdx.y * kSumRows + 4 * r + threadIdx.y;
-        const bool in = x < v.W && y < v.H;
-        int id = in ? v.seg[(int64_t)y * v.seg_pitch + x] : -1;
-        if (in && (id < 0 || id >= v.S)) {
-            atomicOr(P->flag, 1);
+        ids[r] = x < W && y < H ? ldg(seg + (int64_t)y * sp + x) : -1;
+    }
+    for (int r = 0; r < kRowsPerWave; ++r) {
+        const int y = blockIdx.y * kSumRows + 4 * r + threadIdx.y;
+        const bool in = x < W && y < H;
+        int id = ids[r];
+        if (in && (id < 0 || id >= S)) {
+            atomicOr(flag, 1);
             id = -1;
         }
         uint32_t col[3] = {0, 0, 0};
         if (id >= 0) {
-            col[0] = plane_at(v.plane[0], (int64_t)y * v.pitch[0] + x, b);
-            col[1] = plane_at(v.plane[1], (int64_t)(y >> k) * v.pitch[1] + (x >> k), b);
-            col[2] = plane_at(v.plane[2], (int64_t)(y >> k) * v.pitch[2] + (x >> k), b);
+            col[0] = plane_u(pl, 0, (int64_t)y * pl.pitch[0] + x);
+            col[1] = plane_u(pl, 1, (int64_t)(y >> k) * pl.pitch[1] + (x >> k));
+            col[2] = plane_u(pl, 2, (int64_t)(y >> k) * pl.pitch[2] + (x >> k));
         }
         // inclusive prefix sums over the wave row (at most 64 x 65535 each)
         uint32_t pre[3] = {col[0], col[1], col[2]};
@@ -163,22 +173,26 @@ __global__ __launch_bounds__(256) void k_seg_sums(const Problem *__restrict__ P,
 __global__ void k_seg_finish(const Problem *__restrict__ P, const unsigned long long *__restrict__ sums,
                              int32_t *__restrict__ count_flat)
 {
-    const ViewDesc &v = P->views[blockIdx.y];
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= v.S) return;
-    const unsigned long long *r = sums + 6 * (v.row0 + s);
+    if (s >= ldu(&vd->S)) return;
+    const int64_t row0 = ldu(&vd->row0);
+    int32_t *centre = ldu(&vd->centre) + 2 * s;
+    float *mean = ldu(&vd->mean) + 4 * s;
+    const unsigned long long *r = sums + 6 * (row0 + s);
     const unsigned long long n = r[0];
-    if (count_flat) count_flat[v.row0 + s] = (int32_t)n;
+    if (count_flat) count_flat[row0 + s] = (int32_t)n;
     if (n == 0) {
-        v.centre[2 * s] = v.centre[2 * s + 1] = -1;
-        for (int c = 0; c < 4; ++c) v.mean[4 * s + c] = 0.f;
+        stg(centre, -1);
+        stg(centre + 1, -1);
+        stg(reinterpret_cast<float4 *>(mean), make_float4(0.f, 0.f, 0.f, 0.f));
         return;
     }
     const double dn = (double)n;
-    v.centre[2 * s] = (int)floor((double)r[1] / dn + 0.5);
-    v.centre[2 * s + 1] = (int)floor((double)r[2] / dn + 0.5);
-    for (int c = 0; c < 3; ++c) v.mean[4 * s + c] = (float)((double)r[3 + c] / dn);
-    v.mean[4 * s + 3] = 0.f;
+    stg(centre, (int)floor((double)r[1] / dn + 0.5));
+    stg(centre + 1, (int)floor((double)r[2] / dn + 0.5));
+    stg(reinterpret_cast<float4 *>(mean), make_float4((float)((double)r[3] / dn), (float)((double)r[4] / dn),
+                                                      (float)((double)r[5] / dn), 0.f));
 }
 
 // Tasks in row order (view, segment, label block), for kernels that need no
@@ -441,17 +455,24 @@ __device__ __forceinline__ int wave_min(int v)
     return uniform(v);
 }
 
+// A view's segment map, read once per wave into scalar registers.
+struct SegMap {
+    const int32_t *seg;
+    int64_t pitch;
+    int W, H, S;
+};
+
 // Segment ids around pixel record i; kNoSeg outside the image, for the
 // segment itself and for ids out of range (reported by the index kernels).
-__device__ __forceinline__ void neighbours4(const ViewDesc &v, const float *rec, int i, int s, int (&c)[4])
+__device__ __forceinline__ void neighbours4(const SegMap &v, const float *rec, int i, int s, int (&c)[4])
 {
-    const float2 xy = *reinterpret_cast<const float2 *>(rec + 8 * (int64_t)i);
+    const float2 xy = ldg(reinterpret_cast<const float2 *>(rec + 8 * (int64_t)i));
     const int x = (int)xy.x, y = (int)xy.y;
-    const int32_t *row = v.seg + (int64_t)y * v.seg_pitch;
-    const int t0 = x > 0 ? row[x - 1] : kNoSeg;
-    const int t1 = x + 1 < v.W ? row[x + 1] : kNoSeg;
-    const int t2 = y > 0 ? row[x - v.seg_pitch] : kNoSeg;
-    const int t3 = y + 1 < v.H ? row[x + v.seg_pitch] : kNoSeg;
+    const int32_t *row = v.seg + (int64_t)y * v.pitch;
+    const int t0 = x > 0 ? ldg(row + x - 1) : kNoSeg;
+    const int t1 = x + 1 < v.W ? ldg(row + x + 1) : kNoSeg;
+    const int t2 = y > 0 ? ldg(row + x - v.pitch) : kNoSeg;
+    const int t3 = y + 1 < v.H ? ldg(row + x + v.pitch) : kNoSeg;
     c[0] = (t0 != s && t0 >= 0 && t0 < v.S) ? t0 : kNoSeg;
     c[1] = (t1 != s && t1 >= 0 && t1 < v.S) ? t1 : kNoSeg;
     c[2] = (t2 != s && t2 >= 0 && t2 < v.S) ? t2 : kNoSeg;
@@ -476,28 +497,37 @@ __global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P
                                                    int64_t capacity, float beta0, float eps, float inv_scale,
                                                    int32_t *__restrict__ kept)
 {
-    const ViewDesc &v = P->views[blockIdx.y];
+    const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
     const int lane = lane_id();
     const int s = uniform(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    SegMap v;
+    v.S = ldu(&vd->S);
     if (s >= v.S) return;
-    const int64_t row = v.row0 + s;
+    const int64_t row0 = ldu(&vd->row0);
+    const int64_t row = row0 + s;
+    const float4 *mean = reinterpret_cast<const float4 *>(ldu(&vd->mean));
     int32_t *keep = kept + row * kAdjKeep;
     if (WRITE) {
         const int64_t o = offsets[row], n = offsets[row + 1] - o;
         if (n <= kAdjKeep) {
             if (lane < n && o + lane < capacity) {
                 const int m = keep[lane];
-                const float4 ms = reinterpret_cast<const float4 *>(v.mean)[s];
-                const float4 mt = reinterpret_cast<const float4 *>(v.mean)[m];
+                const float4 ms = ldg(mean + s);
+                const float4 mt = ldg(mean + m);
                 const float d = (fabsf(ms.x - mt.x) + fabsf(ms.y - mt.y) + fabsf(ms.z - mt.z)) * inv_scale;
-                index[o + lane] = (int32_t)(v.row0 + m);
+                index[o + lane] = (int32_t)(row0 + m);
                 beta[o + lane] = beta0 / (d + eps);
             }
             return;
         }
     }
-    const int p0 = v.offsets[s], p1 = v.offsets[s + 1];
-    const float *rec = v.pixrec;
+    v.seg = ldu(&vd->seg);
+    v.pitch = ldu(&vd->seg_pitch);
+    v.W = ldu(&vd->W);
+    v.H = ldu(&vd->H);
+    const int32_t *voffs = ldu(&vd->offsets);
+    const int p0 = ldu(voffs + s), p1 = ldu(voffs + s + 1);
+    const float *rec = ldu(&vd->pixrec);
     const bool cached = p1 - p0 <= kAdjCache * kWave;
     int c[kAdjCache][4];
 #pragma unroll
@@ -510,7 +540,7 @@ __global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P
     }
     const int64_t out = WRITE ? offsets[row] : 0;
     float4 ms = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (WRITE) ms = reinterpret_cast<const float4 *>(v.mean)[s];
+    if (WRITE) ms = ldg(mean + s);
     int last = -1, k = 0;
     for (;;) {
         int m = kNoSeg;
@@ -527,8 +557,8 @@ __global__ __launch_bounds__(256) void k_adjacency(const Problem *__restrict__ P
         m = wave_min(m);
         if (m == kNoSeg) break;
         if (WRITE && lane == 0 && out + k < capacity) {
-            index[out + k] = (int32_t)(v.row0 + m);
-            const float4 mt = reinterpret_cast<const float4 *>(v.mean)[m];
+            index[out + k] = (int32_t)(row0 + m);
+            const float4 mt = ldg(mean + m);
             const float d = (fabsf(ms.x - mt.x) + fabsf(ms.y - mt.y) + fabsf(ms.z - mt.z)) * inv_scale;
             beta[out + k] = beta0 / (d + eps);
         }
