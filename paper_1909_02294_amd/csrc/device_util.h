@@ -17,6 +17,40 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Wave-wide minimum and sum through DPP lane moves (no LDS traffic): row
+// shifts by 1, 2, 4 and 8 leave each 16-lane row's result in its lane 15,
+// the row broadcasts 15 and 31 carry it to lane 63, which is returned to
+// every lane.  Every lane of the wave must be active.  `old` is what a lane
+// reads when its source lane lies outside the row or its row is masked off.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+    v = min(v, dpp<0x111, 0xf>(v, v));   // row_shr:1
+    v = min(v, dpp<0x112, 0xf>(v, v));   // row_shr:2
+    v = min(v, dpp<0x114, 0xf>(v, v));   // row_shr:4
+    v = min(v, dpp<0x118, 0xf>(v, v));   // row_shr:8
+    v = min(v, dpp<0x142, 0xa>(v, v));   // row_bcast:15 into rows 1 and 3
+    v = min(v, dpp<0x143, 0xc>(v, v));   // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t u)
+{
+    int v = (int)u;
+    v = (int)((uint32_t)v + (uint32_t)dpp<0x111, 0xf>(0, v));
+    v = (int)((uint32_t)v + (uint32_t)dpp<0x112, 0xf>(0, v));
+    v = (int)((uint32_t)v + (uint32_t)dpp<0x114, 0xf>(0, v));
+    v = (int)((uint32_t)v + (uint32_t)dpp<0x118, 0xf>(0, v));
+    v = (int)((uint32_t)v + (uint32_t)dpp<0x142, 0xa>(0, v));
+    v = (int)((uint32_t)v + (uint32_t)dpp<0x143, 0xc>(0, v));
+    return (uint32_t)__builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ float h_lo(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
 __device__ __forceinline__ float h_hi(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
 

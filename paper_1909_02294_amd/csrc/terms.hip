@@ -18,6 +18,32 @@ namespace {
 // Count, centre (centroid rounded half up) and mean colour of every segment,
 // one wave per segment over its pixel records; integer sums, so the result
 // does not depend on the summation order.
+// x, y, Y, Cb, Cr summed over records [p0, p1), across the wave; integer
+// sums, exact in T as long as they fit.
+template <typename T>
+__device__ __forceinline__ void record_sums(const float4 *rec, int p0, int p1, int lane, unsigned long long (&out)[5])
+{
+    T acc[5] = {0, 0, 0, 0, 0};
+    for (int i = p0 + lane; i < p1; i += kWave) {
+        const float4 r0 = ldg(rec + 2 * (int64_t)i), r1 = ldg(rec + 2 * (int64_t)i + 1);
+        acc[0] += (T)r0.x;
+        acc[1] += (T)r0.y;
+        acc[2] += (T)r0.w;
+        acc[3] += (T)r1.x;
+        acc[4] += (T)r1.y;
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = wave_sum_u32(acc[c]);
+    } else {
+        for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[c] += __shfl_xor(acc[c], d);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = (unsigned long long)acc[c];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_seg_stats(const Problem *__restrict__ P, int32_t *__restrict__ count_flat)
 {
     const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
@@ -26,21 +52,15 @@ __global__ __launch_bounds__(256) void k_seg_stats(const Problem *__restrict__ P
     if (s >= ldu(&vd->S)) return;
     const int32_t *offs = ldu(&vd->offsets);
     const int p0 = ldu(offs + s), p1 = ldu(offs + s + 1);
-    unsigned long long sx = 0, sy = 0, sc[3] = {0, 0, 0};
     const float4 *rec = reinterpret_cast<const float4 *>(ldu(&vd->pixrec));
-    for (int i = p0 + lane; i < p1; i += kWave) {
-        const float4 r0 = ldg(rec + 2 * (int64_t)i), r1 = ldg(rec + 2 * (int64_t)i + 1);
-        sx += (unsigned long long)r0.x;
-        sy += (unsigned long long)r0.y;
-        sc[0] += (unsigned long long)r0.w;
-        sc[1] += (unsigned long long)r1.x;
-        sc[2] += (unsigned long long)r1.y;
-    }
-    for (int d = 32; d >= 1; d >>= 1) {
-        sx += __shfl_xor(sx, d);
-        sy += __shfl_xor(sy, d);
-        for (int c = 0; c < 3; ++c) sc[c] += __shfl_xor(sc[c], d);
-    }
+    unsigned long long sum[5];
+    // coordinates and samples are below 2^16, so sums over at most 2^16
+    // pixels fit 32 bits (half the cross-lane traffic of 64-bit sums)
+    if (p1 - p0 <= 65536)
+        record_sums<uint32_t>(rec, p0, p1, lane, sum);
+    else
+        record_sums<unsigned long long>(rec, p0, p1, lane, sum);
+    const unsigned long long sx = sum[0], sy = sum[1], sc[3] = {sum[2], sum[3], sum[4]};
     if (lane == 0) {
         const int n = p1 - p0;
         int32_t *centre = ldu(&vd->centre) + 2 * s;
@@ -449,11 +469,7 @@ __global__ void k_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *__
 constexpr int kAdjCache = 4;            // pixel batches whose neighbour ids stay in registers
 constexpr int kNoSeg = 0x7fffffff;
 
-__device__ __forceinline__ int wave_min(int v)
-{
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
-    return uniform(v);
-}
+__device__ __forceinline__ int wave_min(int v) { return wave_min_i32(v); }
 
 // A view's segment map, read once per wave into scalar registers.
 struct SegMap {
