@@ -235,28 +235,12 @@ __global__ __launch_bounds__(1024) void k_scan(const Problem *__restrict__ P)
     if (threadIdx.x == 0) v.offsets[v.S] = carry;
 }
 
-// One pixel record: position, g . p~ and the pixel's Y, Cb, Cr.
-__device__ __forceinline__ void write_record(float *rec, const Planes &pl, float g0, float g1, float g2, int x, int y,
-                                             int64_t pos)
-{
-    const float fx = (float)x, fy = (float)y;
-    float4 r0, r1;
-    r0.x = fx;
-    r0.y = fy;
-    r0.z = fmaf(g0, fx, fmaf(g1, fy, g2));
-    yuv_at(pl, x, y, r0.w, r1.x, r1.y);
-    r1.z = 0.f;
-    r1.w = 0.f;
-    float4 *dst = reinterpret_cast<float4 *>(rec) + 2 * pos;
-    stg(dst, r0);
-    stg(dst + 1, r1);
-}
-
 // One wave per segment scans its box in raster order and writes the pixel
 // records in that order.  A box at most half a wave wide is covered several
 // rows per step (lane order is still raster order); wider boxes row by row
-// in 64-pixel chunks.  The ids of the next step are loaded while the
-// current step's records are written.
+// in 64-pixel chunks.  A pixel record is (x, y, g . p~, Y) (Cb, Cr, 0, 0).
+// The ids and colours of the next step are loaded while the current step's
+// records are written.
 __global__ __launch_bounds__(256) void k_seg_fill(const Problem *__restrict__ P)
 {
     const ViewDesc *vd = ldu(&P->views) + blockIdx.y;
@@ -291,20 +275,37 @@ __global__ __launch_bounds__(256) void k_seg_fill(const Problem *__restrict__ P)
         }
         return lr < rows && y <= y1 && x <= x1;
     };
-    int xn, yn;
-    bool in = next_pixel(xn, yn);
-    int id = in ? ldg(seg + (int64_t)yn * sp + xn) : -1;
+    // a step's id and colour loads are issued together, one step ahead
+    int xn, yn, id = -1;
+    float cy = 0.f, cu = 0.f, cv = 0.f;
+    auto fetch = [&]() {
+        const bool in = next_pixel(xn, yn);
+        if (in) {
+            id = ldg(seg + (int64_t)yn * sp + xn);
+            yuv_at(pl, xn, yn, cy, cu, cv);
+        } else {
+            id = -1;
+        }
+    };
+    fetch();
     int run = 0;
     for (int t = 0; t < steps; ++t) {
-        const int x = xn, y = yn, cur = id;
-        const bool m = in && cur == s;
-        if (t + 1 < steps) {
-            in = next_pixel(xn, yn);
-            id = in ? ldg(seg + (int64_t)yn * sp + xn) : -1;
-        }
+        const int x = xn, y = yn;
+        const bool m = id == s;
+        float4 r0, r1;
+        r0.x = (float)x;
+        r0.y = (float)y;
+        r0.z = fmaf(g0, r0.x, fmaf(g1, r0.y, g2));
+        r0.w = cy;
+        r1 = make_float4(cu, cv, 0.f, 0.f);
+        if (t + 1 < steps) fetch();
         const uint64_t bal = __ballot(m);
         const int pos = base + run + __builtin_popcountll(bal & ((1ull << lane) - 1));
-        if (m && pos < cap) write_record(rec, pl, g0, g1, g2, x, y, pos);
+        if (m && pos < cap) {
+            float4 *dst = reinterpret_cast<float4 *>(rec) + 2 * (int64_t)pos;
+            stg(dst, r0);
+            stg(dst + 1, r1);
+        }
         run += __builtin_popcountll(bal);
     }
 }
