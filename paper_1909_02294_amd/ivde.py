@@ -156,6 +156,25 @@ def _torch():
     return torch
 
 
+def _check(t, name, dtypes, shape=None, cuda=True):
+    """Reject a tensor the C entry points would misread: wrong dtype, not
+    contiguous, not on the GPU, or a shape other than `shape` (None entries
+    match any extent).  The library reads raw pointers, so a mismatch here
+    would otherwise read or write past the tensor."""
+    if not isinstance(dtypes, (tuple, list)):
+        dtypes = (dtypes,)
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+    if cuda and not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None:
+        if t.dim() != len(shape) or any(e is not None and int(a) != int(e) for a, e in zip(t.shape, shape)):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
 def _stream_ptr(stream):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -281,7 +300,7 @@ def cost_volume(dv: DeviceViews, lr: LabelRange, opt: Options, workspace=None, o
     dtype = torch.float16 if opt.cost_dtype == F16 else torch.float32
     if out is None:
         out = torch.empty((dv.rows, L), dtype=dtype, device="cuda")
-    assert out.dtype == dtype and out.is_contiguous() and out.numel() * out.element_size() >= cb
+    _check(out, "out", dtype, (dv.rows, L))
     check(lib.ivde_cost_volume(dv.n, dv.c_cams, dv.c_images, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt),
                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
@@ -291,9 +310,11 @@ def cost_volume(dv: DeviceViews, lr: LabelRange, opt: Options, workspace=None, o
 def argmin(cost, stream=None, out=None):
     torch = _torch()
     lib = load()
+    _check(cost, "cost", (torch.float32, torch.float16), (None, None))
     rows, L = cost.shape
     if out is None:
         out = torch.empty(rows, dtype=torch.int32, device=cost.device)
+    _check(out, "out", torch.int32, (rows,))
     dt = F16 if cost.dtype == torch.float16 else F32
     check(lib.ivde_argmin(rows, L, dt, ctypes.c_void_p(cost.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                           _stream_ptr(stream)))
@@ -320,7 +341,11 @@ class Batch:
         lib = load()
         self._keep = [frames, opt]
         arr = (Frame * len(frames))()
+        cdt = torch.float16 if opt.cost_dtype == F16 else torch.float32
         for i, (dv, lr, cost, lab) in enumerate(frames):
+            _check(cost, f"frame {i} cost", cdt, (dv.rows, lr.num_labels))
+            if lab is not None:
+                _check(lab, f"frame {i} labels", torch.int32, (dv.rows,))
             arr[i].n_views = dv.n
             arr[i].cams = ctypes.cast(dv.c_cams, ctypes.POINTER(Camera))
             arr[i].views = ctypes.cast(dv.c_images, ctypes.POINTER(Image))
@@ -381,9 +406,22 @@ class Server:
         self._rigs[rid.value] = (dv.n, sum(dv.S), lr.num_labels, opt.cost_dtype)
         return rid.value
 
+    def _check_outputs(self, rig, cost_out, label_out, mask=None):
+        torch = _torch()
+        if rig not in self._rigs:
+            return          # the library reports the unknown rig
+        _, R, L, dt = self._rigs[rig]
+        if cost_out is not None:
+            _check(cost_out, "cost_out", torch.float16 if dt == F16 else torch.float32, (R, L))
+        if label_out is not None:
+            _check(label_out, "label_out", torch.int32, (R,))
+        if mask is not None:
+            _check(mask, "mask", torch.uint8, (R,))
+
     def submit(self, rig: int, images, mask=None, cost_out=None, label_out=None) -> int:
         """images: a ctypes Image array (DeviceViews.c_images of the frame);
         mask: device uint8 tensor [rows] or None (recompute every row)."""
+        self._check_outputs(rig, cost_out, label_out, mask)
         t = ctypes.c_uint64(0)
         check(load().ivde_stream_submit(self.handle, int(rig), images,
                                         ctypes.c_void_p(mask.data_ptr()) if mask is not None else None,
@@ -395,6 +433,7 @@ class Server:
 
     def submit_rule(self, rig: int, images, iframe=False, cost_out=None, label_out=None) -> int:
         """A frame whose changed rows the server derives by the temporal rule."""
+        self._check_outputs(rig, cost_out, label_out)
         t = ctypes.c_uint64(0)
         check(load().ivde_stream_submit_rule(
             self.handle, int(rig), images, int(bool(iframe)),
@@ -499,7 +538,10 @@ def window_cost(dv: DeviceViews, lr: LabelRange, radius=1, stream=None):
 def window_energy(m, hit, labelling, K=30.0, stream=None):
     """ivde_window_energy: [rows, L] float32."""
     torch = _torch()
+    _check(m, "m", torch.float32, (None, 2, None))
     rows, _, L = m.shape
+    _check(hit, "hit", torch.int32, (rows, 2, L))
+    _check(labelling, "labelling", torch.int32, (rows,))
     out = torch.empty((rows, L), dtype=torch.float32, device=m.device)
     check(load().ivde_window_energy(rows, L, ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(hit.data_ptr()),
                                     ctypes.c_void_p(labelling.data_ptr()), float(K), ctypes.c_void_p(out.data_ptr()),
@@ -528,7 +570,11 @@ def segment_stats(dv: DeviceViews, stream=None):
 def temporal_rule(mean, mean_prev, mean_iframe=None, t_p=3.0, t_i=1.0, bit_depth=8, stream=None):
     """ivde_temporal_rule: uint8 [rows] with 0 recompute, 1 previous frame, 2 I frame."""
     torch = _torch()
+    _check(mean, "mean", torch.float32, (None, 4))
     rows = mean.shape[0]
+    _check(mean_prev, "mean_prev", torch.float32, (rows, 4))
+    if mean_iframe is not None:
+        _check(mean_iframe, "mean_iframe", torch.float32, (rows, 4))
     out = torch.empty(rows, dtype=torch.uint8, device=mean.device)
     check(load().ivde_temporal_rule(rows, ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(mean_prev.data_ptr()),
                                     ctypes.c_void_p(mean_iframe.data_ptr()) if mean_iframe is not None else None,
@@ -568,7 +614,13 @@ def adjacency(dv: DeviceViews, beta0: float, eps: float = 1.0, capacity=None, st
 def intra_cost(offsets, index, beta, labelling, num_labels: int, fixed=None, stream=None):
     """ivde_intra_cost: float32 [rows, num_labels]."""
     torch = _torch()
+    _check(offsets, "offsets", torch.int64, (None,))
     rows = offsets.shape[0] - 1
+    _check(index, "index", torch.int32, (None,))
+    _check(beta, "beta", torch.float32, (index.shape[0],))
+    _check(labelling, "labelling", torch.int32, (rows,))
+    if fixed is not None:
+        _check(fixed, "fixed", torch.uint8, (rows,))
     out = torch.empty((rows, int(num_labels)), dtype=torch.float32, device=offsets.device)
     check(load().ivde_intra_cost(rows, int(num_labels), ctypes.c_void_p(offsets.data_ptr()),
                                  ctypes.c_void_p(index.data_ptr()), ctypes.c_void_p(beta.data_ptr()),
@@ -629,6 +681,7 @@ def depth_map(dv: DeviceViews, lr: LabelRange, labels, stream=None):
     n_px = sum(int(c.width) * int(c.height) for c in dv.c_cams)
     out = torch.empty(n_px, dtype=torch.float32, device="cuda")
     lab = labels if hasattr(labels, "data_ptr") else torch.from_numpy(np.ascontiguousarray(labels, np.int32)).cuda()
+    _check(lab, "labels", torch.int32, (dv.rows,))
     check(load().ivde_depth_map(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.c_void_p(lab.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out

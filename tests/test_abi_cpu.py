@@ -259,3 +259,21 @@ def test_depth_map_and_footprint_argument_checks(lib):
     assert r.value > 2 * n * S * L * 2 + n * w * h * 4 and q.value >= 256
     assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 20, ctypes.byref(r),
                                      ctypes.byref(q)) == ivde.IVDE_EINVAL
+
+
+def test_binding_rejects_tensors_the_library_would_misread():
+    """The Python binding passes raw pointers, so it checks dtype,
+    contiguity and shape first (checked here on CPU tensors)."""
+    torch = pytest.importorskip("torch")
+    ok = torch.zeros((5, 8), dtype=torch.float32)
+    assert ivde._check(ok, "cost", (torch.float32, torch.float16), (None, 8), cuda=False) is ok
+    with pytest.raises(ValueError, match="dtype"):
+        ivde._check(ok.to(torch.float64), "cost", (torch.float32, torch.float16), cuda=False)
+    with pytest.raises(ValueError, match="contiguous"):
+        ivde._check(ok.t(), "cost", torch.float32, cuda=False)
+    with pytest.raises(ValueError, match="shape"):
+        ivde._check(ok, "cost", torch.float32, (5, 9), cuda=False)
+    with pytest.raises(ValueError, match="shape"):
+        ivde._check(ok, "cost", torch.float32, (5,), cuda=False)
+    with pytest.raises(ValueError, match="GPU"):
+        ivde._check(ok, "cost", torch.float32)

@@ -58,3 +58,16 @@ def test_argmin_unaligned_base(half):
     assert view.data_ptr() % 16 != 0
     got = ivde.argmin(view).cpu().numpy()
     np.testing.assert_array_equal(got, _expected(flat[1:].reshape(rows, L)))
+
+
+def test_argmin_rejects_misread_tables():
+    print("[case] argmin argument checks", flush=True)
+    c = torch.zeros((6, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        ivde.argmin(c.double())
+    with pytest.raises(ValueError):
+        ivde.argmin(c.t())
+    with pytest.raises(ValueError):
+        ivde.argmin(c, out=torch.empty(6, dtype=torch.int64, device="cuda"))
+    with pytest.raises(ValueError):
+        ivde.argmin(c, out=torch.empty(5, dtype=torch.int32, device="cuda"))
