@@ -10,8 +10,8 @@ Inputs are resident in HBM before the timed region.  Prints one JSON line.
 
   --mode plain    (default) the line above
   --mode batched  16 frames of the same generator with uneven segment and
-                  label counts: one persistent-kernel launch in a hipGraph
-                  against 16 sequential plain launches
+                  label counts: one sweep launch over all frames in a
+                  hipGraph against 16 sequential single-frame calls
   --mode served   the serving loop on a Poisson stream from three rigs
   --mode copycal  a device copy of known size (calibrates HBM counters)
   --mode window   the paper's own 3x3 centre-window term
@@ -206,7 +206,7 @@ def bench_plain(args):
             "bound": "alu", "achieved": alu_tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": alu_tops / ALU_PEAK_TOPS,
             "traffic": counters["hbm_bytes_per_launch"] if counters else None,
-            "kernel": "k_sweep_j1 (bilinear, half texels, FP32 store)",
+            "kernel": "k_sweep_persistent_j1 (bilinear, half texels, FP32 store)",
             "ops_per_eval": OPS_PER_BILINEAR_EVAL, "evals_per_launch": evals,
             "l2_hit_rate": counters["l2_hit_rate"] if counters else None,
         },

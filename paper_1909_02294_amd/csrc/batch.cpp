@@ -4,8 +4,8 @@
 // Every frame keeps its own region of the batch workspace (packed images,
 // segment index, constants); their task lists are laid out back to back so
 // that the concatenation is one queue.  Frames are ordered by decreasing
-// work so the queue drains large tasks first.  The persistent kernel runs
-// the same per-task code as the plain launch, so each frame's cost volume is
+// work so the queue drains large tasks first.  The sweep kernel runs the
+// same per-task code as ivde_cost_volume, so each frame's cost volume is
 // bitwise equal to what ivde_cost_volume returns for it.
 #include <hip/hip_runtime.h>
 

@@ -239,6 +239,7 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
     ly.off_centre = take(sizeof(int32_t) * 2 * (size_t)ly.total_rows);
     ly.off_mean = take(sizeof(float) * 4 * (size_t)ly.total_rows);
     ly.off_sums = take(sizeof(uint64_t) * 6 * (size_t)ly.total_rows);
+    ly.off_cursors = take(sizeof(int32_t) * (kXcds + 1));
     ly.workspace_bytes = off;
     ly.cost_bytes = (size_t)ly.total_rows * ly.L * (ly.f16 ? 2 : 4);
     return ly;
@@ -553,7 +554,8 @@ ivde_status ivde_cost_volume(int32_t n_views, const ivde_camera *cams, const ivd
     if (opt->sweep_events[0] && opt->sweep_events[1] &&
         (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[0]), s)) != hipSuccess)
         return hip_fail(e, "event record");
-    e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, opt->sampling == IVDE_BILINEAR, ly.tex_f32, ly.f16, ly.wpg, s);
+    e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, opt->sampling == IVDE_BILINEAR, ly.tex_f32, ly.f16, ly.wpg,
+                     reinterpret_cast<int32_t *>(ws + ly.off_cursors), s);
     if (e != hipSuccess) return hip_fail(e, "sweep");
     if (opt->sweep_events[0] && opt->sweep_events[1] &&
         (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[1]), s)) != hipSuccess)

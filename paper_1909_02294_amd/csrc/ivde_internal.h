@@ -93,8 +93,12 @@ hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hi
 hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
 hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem_index, Task *tasks,
                            hipStream_t s);
+// The sweep over tasks[0, n_tasks): enough resident groups to fill every CU
+// take tasks from per-XCD cursors.  counters: kXcds + 1 device ints of
+// scratch (the cursors, then the task count), set by this call.
 hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J,
-                        int bilinear, int tex_f32, int f16out, int waves_per_group, hipStream_t s);
+                        int bilinear, int tex_f32, int f16out, int waves_per_group, int32_t *counters,
+                        hipStream_t s);
 // cursors: kXcds zeroed counters, one per contiguous range of the task list
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
                                    int32_t *cursors, int64_t max_tasks, int J, int bilinear, int tex_f32,

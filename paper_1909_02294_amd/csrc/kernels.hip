@@ -685,46 +685,17 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
     }
 }
 
-// Plain launch: one wave per task.  Block b runs on XCD b mod 8; the
-// remapping gives each XCD a contiguous stretch of the spatially ordered
-// task list, so its L2 holds the image bands those tasks gather from.
+// The sweep launch: a grid that fits on the GPU at once, whose waves pull
+// tasks from per-XCD cursors until the device task count (written by an
+// earlier kernel) is exhausted.  A wave whose home range is empty helps with
+// the others, so no XCD idles while another has work (with one XCD per view
+// in a view-major task list, views whose gathers cost more no longer set
+// the kernel's end).
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
-__device__ __forceinline__ void sweep_plain_body(const Problem *__restrict__ probs, const Task *__restrict__ tasks,
-                                                 int64_t n_tasks, int per_xcd)
-{
-    const int wpg = blockDim.x / kWave;
-    const int b = blockIdx.x;
-    const int64_t lb = (int64_t)(b & 7) * per_xcd + (b >> 3);
-    const int64_t t = lb * wpg + uniform(threadIdx.x / kWave);
-    if (t >= n_tasks) return;
-    const Task task = ldu_task(tasks + t);
-    sweep_task<J, BIL, TEXF32, F16OUT>(probs + task.problem, task);
-}
-
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
-__global__ __launch_bounds__(256) void k_sweep(const Problem *__restrict__ probs, const Task *__restrict__ tasks,
-                                               int64_t n_tasks, int per_xcd)
-{
-    sweep_plain_body<J, BIL, TEXF32, F16OUT>(probs, tasks, n_tasks, per_xcd);
-}
-
-// One label per lane with half texels fits 64 VGPRs without spilling; at 8
-// waves per SIMD it hides gather latency best (measured on the 8-view 1080p
-// workload).
-template <bool BIL, bool F16OUT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_j1(
-    const Problem *__restrict__ probs, const Task *__restrict__ tasks, int64_t n_tasks, int per_xcd)
-{
-    sweep_plain_body<1, BIL, false, F16OUT>(probs, tasks, n_tasks, per_xcd);
-}
-
-// Persistent launch: waves pull tasks from a shared cursor until the device
-// task count (written by an earlier kernel) is exhausted.
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
-__global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restrict__ probs,
-                                                          const Task *__restrict__ tasks,
-                                                          const int32_t *__restrict__ n_tasks,
-                                                          int32_t *__restrict__ cursors, int64_t max_tasks)
+__device__ __forceinline__ void sweep_persistent_body(const Problem *__restrict__ probs,
+                                                      const Task *__restrict__ tasks,
+                                                      const int32_t *__restrict__ n_tasks,
+                                                      int32_t *__restrict__ cursors, int64_t max_tasks)
 {
     const int lane = lane_id();
     const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
@@ -746,6 +717,32 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restr
             sweep_task<J, BIL, TEXF32, F16OUT>(probs + task.problem, task);
         }
     }
+}
+
+template <int J, bool BIL, bool TEXF32, bool F16OUT>
+__global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restrict__ probs,
+                                                          const Task *__restrict__ tasks,
+                                                          const int32_t *__restrict__ n_tasks,
+                                                          int32_t *__restrict__ cursors, int64_t max_tasks)
+{
+    sweep_persistent_body<J, BIL, TEXF32, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
+}
+
+// One label per lane with half texels fits 64 VGPRs; at 8 waves per SIMD it
+// hides gather latency best (measured on the 8-view 1080p workload).
+template <bool BIL, bool F16OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_persistent_j1(
+    const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
+    int32_t *__restrict__ cursors, int64_t max_tasks)
+{
+    sweep_persistent_body<1, BIL, false, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
+}
+
+// Cursors of the sweep to zero, then the task count.
+__global__ void k_sweep_counters(int32_t *__restrict__ counters, int32_t n_tasks)
+{
+    if (threadIdx.x < kXcds) counters[threadIdx.x] = 0;
+    if (threadIdx.x == kXcds) counters[kXcds] = n_tasks;
 }
 
 // ------------------------------------------------------------------ argmin
@@ -944,27 +941,15 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
 }
 
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
-static hipError_t sweep_plain(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int wpg, hipStream_t s)
-{
-    const int64_t groups = (n_tasks + wpg - 1) / wpg;
-    const int64_t per_xcd = (groups + 7) / 8;
-    const int64_t grid = per_xcd * 8;
-    if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    if constexpr (J == 1 && !TEXF32)
-        hipLaunchKernelGGL((k_sweep_j1<BIL, F16OUT>), dim3((unsigned)grid), dim3(64 * wpg), 0, s, dprobs, tasks,
-                           n_tasks, (int)per_xcd);
-    else
-        hipLaunchKernelGGL((k_sweep<J, BIL, TEXF32, F16OUT>), dim3((unsigned)grid), dim3(64 * wpg), 0, s, dprobs,
-                           tasks, n_tasks, (int)per_xcd);
-    return hipGetLastError();
-}
-
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
 static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursors,
                              int64_t max_tasks, int wpg, int n_groups, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep_persistent<J, BIL, TEXF32, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
-                       dprobs, tasks, n_tasks, cursors, max_tasks);
+    if constexpr (J == 1 && !TEXF32)
+        hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
+                           dprobs, tasks, n_tasks, cursors, max_tasks);
+    else
+        hipLaunchKernelGGL((k_sweep_persistent<J, BIL, TEXF32, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0,
+                           s, dprobs, tasks, n_tasks, cursors, max_tasks);
     return hipGetLastError();
 }
 
@@ -982,24 +967,14 @@ static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int
         return f16out ? FN<J, false, false, true>(__VA_ARGS__) : FN<J, false, false, false>(__VA_ARGS__); \
     } while (0)
 
-hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int bilinear,
-                        int tex_f32, int f16out, int wpg, hipStream_t s)
-{
-    if (n_tasks <= 0) return hipSuccess;
-    switch (J) {
-    case 1: IVDE_DISPATCH_FLAGS(sweep_plain, 1, dprobs, tasks, n_tasks, wpg, s);
-    case 2: IVDE_DISPATCH_FLAGS(sweep_plain, 2, dprobs, tasks, n_tasks, wpg, s);
-    case 4: IVDE_DISPATCH_FLAGS(sweep_plain, 4, dprobs, tasks, n_tasks, wpg, s);
-    case 8: IVDE_DISPATCH_FLAGS(sweep_plain, 8, dprobs, tasks, n_tasks, wpg, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
 static hipError_t occ(int wpg, int *per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<J, BIL, TEXF32, F16OUT>,
-                                                        64 * wpg, 0);
+    if constexpr (J == 1 && !TEXF32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent_j1<BIL, F16OUT>, 64 * wpg, 0);
+    else
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<J, BIL, TEXF32, F16OUT>,
+                                                            64 * wpg, 0);
 }
 
 hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16out, int wpg, int *per_cu)
@@ -1035,6 +1010,23 @@ hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, con
     case 8: IVDE_DISPATCH_FLAGS(sweep_pers, 8, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int bilinear,
+                        int tex_f32, int f16out, int wpg, int32_t *counters, hipStream_t s)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    if (n_tasks > 0x7fffffff) return hipErrorInvalidValue;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = sweep_persistent_occupancy(J, bilinear, tex_f32, f16out, wpg, &per_cu)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep_counters, dim3(1), dim3(64), 0, s, counters, (int32_t)n_tasks);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int n_groups = std::max(1, cus) * std::max(1, per_cu);
+    return launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, n_tasks, J, bilinear, tex_f32, f16out,
+                                   wpg, n_groups, s);
 }
 
 hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s)

@@ -15,7 +15,7 @@
 // and polls completion events.  Requests of different rigs overlap on the
 // device; frames of one rig are ordered by an event dependency on the rig's
 // previous frame, because each frame starts from that frame's volume.  Every
-// row is computed by the same per-task kernel code as the plain launch, so a
+// row is computed by the same per-task kernel code as ivde_cost_volume, so a
 // frame's result does not depend on what else is in flight.
 #include <hip/hip_runtime.h>
 
@@ -277,7 +277,7 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     const int bil = rig.opt.sampling == IVDE_BILINEAR;
     char *extra = arena_base + r.work_off;
-    // [0] tasks kept, [2..4] rule counts, [8, 8 + kXcds) sweep cursors
+    // [0] tasks kept, [2..4] rule counts, [8, 8 + kXcds) sweep cursors, [8 + kXcds] task count of a full sweep
     int32_t *counters = reinterpret_cast<int32_t *>(extra);
     Task *changed = reinterpret_cast<Task *>(extra + 256);
     uint8_t *source = reinterpret_cast<uint8_t *>(extra + 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256));
@@ -290,7 +290,8 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
     if (r.rule && (e = launch_segment_stats(dp, extents_of(ly), nullptr, s)) != hipSuccess)
         return hip_fail(e, "serve segment statistics");
     if (full) {
-        if ((e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16, ly.wpg, s)) != hipSuccess)
+        if ((e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16, ly.wpg, counters + 8, s)) !=
+            hipSuccess)
             return hip_fail(e, "serve sweep");
         sl.count_host[0] = (int32_t)ly.n_tasks;
         if (r.rule) {
