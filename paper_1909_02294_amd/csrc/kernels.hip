@@ -1,6 +1,6 @@
 // gfx950 kernels of libivde: image packing, segment index, spatial work
-// list, the plane-sweep cost kernel (plain and persistent), argmin and the
-// temporal task compaction.
+// list, the plane-sweep cost kernel (one persistent launch with per-XCD task
+// cursors), argmin and the temporal task compaction.
 //
 // The sweep kernel maps one wavefront to one (view, segment, label block)
 // task.  Lanes are labels: lane i of block b owns labels 64 J b + 64 j + i,
@@ -13,7 +13,7 @@
 // texel gathers of the 64 lanes fall along the pixel's epipolar line in the
 // target and go through buffer loads (out-of-range reads return zero, never
 // fault).  Per-row results are produced entirely inside one wave in a fixed
-// order, so plain, batched and served launches give bitwise equal costs.
+// order, so single-frame, batched and served calls give bitwise equal costs.
 #include <algorithm>
 
 #include <hip/hip_fp16.h>
