@@ -190,3 +190,77 @@ def random_energy_terms(seed, rows=9, L=4, p_hit=0.6, adj=True, unary=True, fixe
         beta = np.array([w[(r, t)] for r in range(rows) for t in sorted(lists[r])], np.float32)
     return dict(rows=rows, num_labels=L, unary=U, m=m, hit=hit, K=30.0, offsets=off, index=idx, beta=beta,
                 fixed=fixed, quantum=quantum)
+
+
+def facing_problem(seed, width=12, height=8, n_seg=6, L=5, bit_depth=8, chroma_shift=0, bilinear=False):
+    """Four cameras placed so that 3-D points fall behind cameras (the paper's
+    cameras are arbitrarily positioned, Sec. III-A): views 0 and 1 look along
+    +z from near the origin, view 2 looks back at them from z = 3.2 (level
+    points beyond it lie behind it), and view 3 looks along +z from z = 3.0,
+    among the level planes (levels nearer than its own position give
+    tau <= 0 for its pixels).  Random images and Voronoi segments."""
+    rng = np.random.default_rng(seed)
+    f = 1.1 * width
+    cams = [
+        synth.look_at([0.0, 0.0, 0.0], [0.0, 0.0, 5.0], width, height, f),
+        synth.look_at([0.3, 0.0, 0.1], [0.0, 0.0, 4.0], width, height, f * 1.03),
+        synth.look_at([0.15, 0.05, 3.2], [0.1, 0.0, 0.0], width, height, f * 0.97),
+        synth.look_at([-0.25, 0.02, 3.0], [0.0, 0.0, 8.0], width, height, f),
+    ]
+    Y, U, V = random_images(rng, cams, bit_depth, chroma_shift)
+    seg, S = [], []
+    for _ in cams:
+        m, s = random_segments(rng, width, height, n_seg)
+        seg.append(m)
+        S.append(s)
+    return SimpleNamespace(cams=cams, Y=Y, U=U, V=V, seg=seg, S=S, bit_depth=bit_depth,
+                           chroma_shift=chroma_shift, z_near=1.0, z_far=4.5, num_labels=L, bilinear=bilinear)
+
+
+def behind_geometry(ns, depth_ref="rig"):
+    """FP64 geometry of every (view, pixel, label, target) sample, computed
+    here with numpy and independently of both implementations: per view the
+    share of (pixel, label) whose level point has tau <= 0; the share of
+    (pixel, label, target) samples with tau > 0 behind the target
+    (camera-frame z <= 0); and how many of those behind-target samples would
+    land inside the target if the sign of z were ignored (so the test of the
+    sign decides their validity)."""
+    n = len(ns.cams)
+    centres = np.array([c.center for c in ns.cams])
+    axes = np.array([c.axis for c in ns.cams])
+    if depth_ref == "rig":
+        Cr_all = np.repeat(centres.mean(0)[None], n, 0)
+        a = axes.mean(0)
+        nr_all = np.repeat((a / np.linalg.norm(a))[None], n, 0)
+    elif depth_ref == "own":
+        Cr_all, nr_all = centres, axes
+    else:
+        Cr_all = np.repeat(centres[int(depth_ref)][None], n, 0)
+        nr_all = np.repeat(axes[int(depth_ref)][None], n, 0)
+    rho = 1 / ns.z_far + np.arange(ns.num_labels) / max(ns.num_labels - 1, 1) * (1 / ns.z_near - 1 / ns.z_far)
+    z = 1 / rho
+    out = dict(tau_nonpos=[], behind=0, behind_flip_inside=0, samples=0)
+    for c, cam_c in enumerate(ns.cams):
+        h, w = cam_c.height, cam_c.width
+        ys, xs = np.mgrid[0:h, 0:w].astype(np.float64)
+        p = np.stack([xs.ravel(), ys.ravel(), np.ones(h * w)])
+        d = (cam_c.R.T @ np.linalg.inv(cam_c.K) @ p).T                  # (P, 3)
+        nd = d @ nr_all[c]
+        tau = (z[None, :] - (centres[c] - Cr_all[c]) @ nr_all[c]) / nd[:, None]   # (P, L)
+        out["tau_nonpos"].append(float((tau <= 0).mean()))
+        X = centres[c][None, None, :] + tau[..., None] * d[:, None, :]              # (P, L, 3)
+        for c2, cam_t in enumerate(ns.cams):
+            if c2 == c:
+                continue
+            Xc = X @ cam_t.R.T + cam_t.t
+            front = tau > 0
+            behind = front & (Xc[..., 2] <= 0)
+            hh = Xc @ cam_t.K.T
+            with np.errstate(divide="ignore", invalid="ignore"):
+                u, v = hh[..., 0] / hh[..., 2], hh[..., 1] / hh[..., 2]
+            inside = (u >= 0) & (u <= cam_t.width - 1) & (v >= 0) & (v <= cam_t.height - 1)
+            out["samples"] += tau.size
+            out["behind"] += int(behind.sum())
+            out["behind_flip_inside"] += int((behind & inside).sum())
+    out["behind_share"] = out["behind"] / max(out["samples"], 1)
+    return out
