@@ -396,12 +396,14 @@ ivde_status ivde_intra_cost(int64_t rows, int32_t num_labels, const int64_t *off
  * is painted onto its pixels).  label_of_row: device int32 [rows] (rows
  * ordered as in ivde_cost_volume); depth_out: device float, the views one
  * after another, each W x H in rows of W.  A pixel gets the depth of its
- * segment's level, 1 / (1/z_far + l/(L-1) (1/z_near - 1/z_far)) in FP64
- * stored as FP32, or NaN for a segment id or level out of range.  Only
- * sizes are read from cams. */
+ * segment's level, 1 / (1/z_far + l/(L-1) (1/z_near - 1/z_far)), formed in
+ * FP64 on the host and stored as FP32, or NaN for a segment id or level out
+ * of range.  workspace: device memory of at least 4 * num_labels bytes,
+ * 4-byte aligned, that receives the level-depth table (in use until the
+ * stream completes).  Only sizes are read from cams. */
 ivde_status ivde_depth_map(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
-                           const ivde_label_range *labels, const int32_t *label_of_row,
-                           float *depth_out, ivde_stream stream);
+                           const ivde_label_range *labels, const int32_t *label_of_row, void *workspace,
+                           size_t workspace_bytes, float *depth_out, ivde_stream stream);
 
 /* ---------------------------------------------------------------- depth optimisation (host) */
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "../../include/ivde.h"
 #include "host_common.h"
@@ -14,8 +15,8 @@ using namespace ivde;
 extern "C" {
 
 ivde_status ivde_depth_map(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
-                           const ivde_label_range *labels, const int32_t *label_of_row, float *depth_out,
-                           ivde_stream stream)
+                           const ivde_label_range *labels, const int32_t *label_of_row, void *workspace,
+                           size_t workspace_bytes, float *depth_out, ivde_stream stream)
 {
     if (n_views < 1 || n_views > kMaxViews || !cams || !segs || !labels || !label_of_row || !depth_out) {
         set_error("depth_map: 1..%d views, cameras, segmentations, a label range, labels and an output", kMaxViews);
@@ -23,9 +24,19 @@ ivde_status ivde_depth_map(int32_t n_views, const ivde_camera *cams, const ivde_
     }
     if (!(labels->z_near > 0 && labels->z_far > 0 && std::isfinite(labels->z_near) && std::isfinite(labels->z_far) &&
           labels->z_near != labels->z_far) ||
-        labels->num_labels < 1) {
-        set_error("depth_map: positive, distinct, finite z_near and z_far and num_labels >= 1 are required");
+        labels->num_labels < 1 || labels->num_labels > 8192) {
+        set_error("depth_map: positive, distinct, finite z_near and z_far and num_labels in [1, 8192] are required");
         return IVDE_EINVAL;
+    }
+    const int L = labels->num_labels;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 4) {
+        set_error("depth_map: a 4-byte aligned workspace is required");
+        return IVDE_EINVAL;
+    }
+    if (workspace_bytes < sizeof(float) * (size_t)L) {
+        set_error("depth_map: workspace too small: %zu bytes given, %zu needed", workspace_bytes,
+                  sizeof(float) * (size_t)L);
+        return IVDE_ENOMEM;
     }
     PaintViews pv{};
     int64_t row0 = 0, out0 = 0;
@@ -49,8 +60,22 @@ ivde_status ivde_depth_map(int32_t n_views, const ivde_camera *cams, const ivde_
         out0 += (int64_t)c.width * c.height;
         max_px = std::max(max_px, c.width * c.height);
     }
-    hipError_t e = launch_paint_depth(pv, n_views, max_px, label_of_row, labels->num_labels, labels->z_near,
-                                      labels->z_far, depth_out, static_cast<hipStream_t>(stream));
+    // level depths in FP64, one rounding per operation (separate statements,
+    // so no multiply-add is contracted), stored as FP32
+    std::vector<float> depth(L);
+    const double inv_far = 1.0 / labels->z_far;
+    const double span = 1.0 / labels->z_near - inv_far;
+    for (int l = 0; l < L; ++l) {
+        const double frac = L > 1 ? (double)l / (double)(L - 1) : 0.0;
+        const double step = frac * span;
+        const double rho = inv_far + step;
+        depth[l] = (float)(1.0 / rho);
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    float *table = static_cast<float *>(workspace);
+    hipError_t e = launch_upload(table, depth.data(), sizeof(float) * (size_t)L, s);
+    if (e != hipSuccess) return hip_fail(e, "level-depth upload");
+    e = launch_paint_depth(pv, n_views, max_px, label_of_row, L, table, depth_out, s);
     if (e != hipSuccess) return hip_fail(e, "depth map");
     return IVDE_OK;
 }

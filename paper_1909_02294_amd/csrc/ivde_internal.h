@@ -144,7 +144,7 @@ struct PaintViews {
     int32_t W[kMaxViews], H[kMaxViews], S[kMaxViews];
 };
 hipError_t launch_paint_depth(const PaintViews &pv, int n_views, int max_pixels, const int32_t *labels, int L,
-                              double z_near, double z_far, float *out, hipStream_t s);
+                              const float *level_depth, float *out, hipStream_t s);
 hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
                          float *m_out, int32_t *hit_out, hipStream_t s);
 hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32_t *hit, const int32_t *labelling,

@@ -850,6 +850,12 @@ __global__ void k_copy_words(const uint32_t *__restrict__ src, uint32_t *__restr
         dst[i] = src[i];
 }
 
+__global__ void k_copy_halves(const uint16_t *__restrict__ src, uint16_t *__restrict__ dst, int64_t n2)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void k_copy_bytes(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
@@ -1062,19 +1068,27 @@ hipError_t launch_compact_tasks(const Problem *dprob, const Task *all, int64_t n
 hipError_t launch_copy_rows(const void *src, void *dst, int64_t bytes, hipStream_t s)
 {
     if (bytes <= 0) return hipSuccess;
-    if (bytes % 4) return hipErrorInvalidValue;
-    if (bytes % 16 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst);
+    if (bytes % 2 || a % 2) return hipErrorInvalidValue;
+    if (bytes % 16 == 0 && a % 16 == 0) {
         const int64_t n16 = bytes / 16;
         int64_t blocks = (n16 + 255) / 256;
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint4 *>(src),
                            static_cast<uint4 *>(dst), n16);
-    } else {
+    } else if (bytes % 4 == 0 && a % 4 == 0) {
         const int64_t n4 = bytes / 4;
         int64_t blocks = (n4 + 255) / 256;
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint32_t *>(src),
                            static_cast<uint32_t *>(dst), n4);
+    } else {
+        // half-precision volumes with an odd number of entries
+        const int64_t n2 = bytes / 2;
+        int64_t blocks = (n2 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_copy_halves, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint16_t *>(src),
+                           static_cast<uint16_t *>(dst), n2);
     }
     return hipGetLastError();
 }

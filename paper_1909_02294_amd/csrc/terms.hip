@@ -447,16 +447,18 @@ __global__ void k_temporal_rule(int64_t rows, const float *__restrict__ mean, co
     }
 }
 
-// Copy the rows whose source is `which` from one volume to another.
-__global__ void k_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *__restrict__ source, int which,
-                                  const uint8_t *__restrict__ from, uint8_t *__restrict__ to)
+// Copy the rows whose source is `which` from one volume to another, one
+// element of T (4 bytes, or 2 for half-precision rows of odd length) per
+// thread.
+template <typename T>
+__global__ void k_copy_rows_where(int64_t rows, int row_elems, const uint8_t *__restrict__ source, int which,
+                                  const T *__restrict__ from, T *__restrict__ to)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one 4-byte word per thread
-    const int words = row_bytes / 4;
-    if (i >= rows * words) return;
-    const int64_t r = i / words;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * row_elems) return;
+    const int64_t r = i / row_elems;
     if (source[r] != which) return;
-    reinterpret_cast<uint32_t *>(to)[i] = reinterpret_cast<const uint32_t *>(from)[i];
+    to[i] = from[i];
 }
 
 
@@ -702,28 +704,22 @@ __global__ __launch_bounds__(256) void k_intra_cost(int64_t rows, int L, int n_l
 }
 
 // ------------------------------------------------------------------ depth maps
-// Sec. III-B: each pixel takes the depth of its segment's level.  The level
-// depth 1 / (1 / z_far + l / (L - 1) (1 / z_near - 1 / z_far)) is formed in
-// FP64 with one rounding per operation (no contraction) and stored as FP32;
-// NaN marks an out-of-range segment id or level.
+// Sec. III-B: each pixel takes the depth of its segment's level, read from
+// the level-depth table the host composed in FP64; NaN marks an out-of-range
+// segment id or level.
 __global__ __launch_bounds__(256) void k_paint_depth(PaintViews pv, const int32_t *__restrict__ labels, int L,
-                                                     double z_near, double z_far, float *__restrict__ out)
+                                                     const float *__restrict__ level_depth, float *__restrict__ out)
 {
     const int v = blockIdx.y;
     const int W = pv.W[v], H = pv.H[v], S = pv.S[v];
     const int64_t n = (int64_t)W * H;
-    const double inv_far = __ddiv_rn(1.0, z_far);
-    const double span = __dsub_rn(__ddiv_rn(1.0, z_near), inv_far);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t y = i / W, x = i - y * W;
         const int s = pv.seg[v][y * pv.pitch[v] + x];
         float z = __builtin_nanf("");
         if (s >= 0 && s < S) {
             const int l = labels[pv.row0[v] + s];
-            if (l >= 0 && l < L) {
-                const double frac = L > 1 ? __ddiv_rn((double)l, (double)(L - 1)) : 0.0;
-                z = (float)__ddiv_rn(1.0, __dadd_rn(inv_far, __dmul_rn(frac, span)));
-            }
+            if (l >= 0 && l < L) z = level_depth[l];
         }
         out[pv.out0[v] + i] = z;
     }
@@ -770,12 +766,19 @@ hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *so
                                   void *to, hipStream_t s)
 {
     if (rows <= 0) return hipSuccess;
-    if (row_bytes % 4) return hipErrorInvalidValue;
-    const int64_t n = rows * (row_bytes / 4);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(from) | reinterpret_cast<uintptr_t>(to);
+    if (row_bytes <= 0 || row_bytes % 2 || a % 2) return hipErrorInvalidValue;
+    const bool words = row_bytes % 4 == 0 && a % 4 == 0;
+    const int elems = words ? row_bytes / 4 : row_bytes / 2;
+    const int64_t n = rows * elems;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_copy_rows_where, dim3((unsigned)blocks), dim3(256), 0, s, rows, row_bytes, source, which,
-                       static_cast<const uint8_t *>(from), static_cast<uint8_t *>(to));
+    if (words)
+        hipLaunchKernelGGL(k_copy_rows_where<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, rows, elems, source,
+                           which, static_cast<const uint32_t *>(from), static_cast<uint32_t *>(to));
+    else
+        hipLaunchKernelGGL(k_copy_rows_where<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, rows, elems, source,
+                           which, static_cast<const uint16_t *>(from), static_cast<uint16_t *>(to));
     return hipGetLastError();
 }
 
@@ -852,11 +855,11 @@ hipError_t launch_intra_cost(int64_t rows, int L, const int64_t *offsets, const 
 }
 
 hipError_t launch_paint_depth(const PaintViews &pv, int n_views, int max_pixels, const int32_t *labels, int L,
-                              double z_near, double z_far, float *out, hipStream_t s)
+                              const float *level_depth, float *out, hipStream_t s)
 {
     if (n_views <= 0 || max_pixels <= 0) return hipSuccess;
     const unsigned bx = (unsigned)std::min<int64_t>(((int64_t)max_pixels + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_paint_depth, dim3(bx, (unsigned)n_views), dim3(256), 0, s, pv, labels, L, z_near, z_far, out);
+    hipLaunchKernelGGL(k_paint_depth, dim3(bx, (unsigned)n_views), dim3(256), 0, s, pv, labels, L, level_depth, out);
     return hipGetLastError();
 }
 

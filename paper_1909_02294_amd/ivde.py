@@ -108,7 +108,7 @@ SIGNATURES = {
     "ivde_adjacency_size": (_I32, [_I32, _P, _P, _I32, _P]),
     "ivde_adjacency": (_I32, [_I32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
     "ivde_intra_cost": (_I32, [_I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
-    "ivde_depth_map": (_I32, [_I32, _P, _P, _P, _P, _P, _P]),
+    "ivde_depth_map": (_I32, [_I32, _P, _P, _P, _P, _P, _SZ, _P, _P]),
     "ivde_energy_value": (_I32, [_P, _P, _P]),
     "ivde_expansion": (_I32, [_P, _P, _P, _I32, _I32, _P, _P]),
     "ivde_optimize": (_I32, [_P, _I32, _I32, _I32, _P, _P]),
@@ -682,6 +682,9 @@ def depth_map(dv: DeviceViews, lr: LabelRange, labels, stream=None):
     out = torch.empty(n_px, dtype=torch.float32, device="cuda")
     lab = labels if hasattr(labels, "data_ptr") else torch.from_numpy(np.ascontiguousarray(labels, np.int32)).cuda()
     _check(lab, "labels", torch.int32, (dv.rows,))
+    table = torch.empty(int(lr.num_labels), dtype=torch.float32, device="cuda")
     check(load().ivde_depth_map(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.c_void_p(lab.data_ptr()),
-                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+                                ctypes.c_void_p(table.data_ptr()), table.numel() * 4, ctypes.c_void_p(out.data_ptr()),
+                                _stream_ptr(stream)))
+    out._ivde_keep = table          # the table is read until the stream completes
     return out

@@ -465,21 +465,27 @@ def make_small_arc(seed=12345, n_views=4, width=160, height=96, n_segments=150,
                              bit_depth=bit_depth, chroma_shift=chroma_shift)
 
 
-def make_batch_frames(n_frames=16, seed=None, width=1920, height=1080, n_views=8,
-                     seg_range=(5000, 40000), label_choices=(128, 256)):
-    """Batching workload: `n_frames` independent arc-rig frames with segment
-    counts U{seg_range} and label counts drawn from `label_choices`."""
+def iter_batch_frames(n_frames=16, seed=None, width=1920, height=1080, n_views=8,
+                      seg_range=(5000, 40000), label_choices=(128, 256)):
+    """Batching workload, one frame at a time: `n_frames` independent
+    arc-rig frames with segment counts U{seg_range} and label counts drawn
+    from `label_choices`.  Frame i is the same for any n_frames > i."""
     seed = SEED_BATCH if seed is None else seed
     rng = np.random.default_rng(seed)
-    out = []
     for i, s in enumerate(np.random.SeedSequence(seed).spawn(n_frames)):
         S = int(rng.integers(seg_range[0], seg_range[1] + 1))
         L = int(rng.choice(label_choices))
-        out.append(make_arc_workload(f"batch-frame{i}", int(s.generate_state(1)[0]),
-                                     n_views=n_views, width=width, height=height,
-                                     n_segments=S, num_labels=L,
-                                     f=1400.0 * width / 1920.0))
-    return out
+        yield make_arc_workload(f"batch-frame{i}", int(s.generate_state(1)[0]),
+                                n_views=n_views, width=width, height=height,
+                                n_segments=S, num_labels=L,
+                                f=1400.0 * width / 1920.0)
+
+
+def make_batch_frames(n_frames=16, seed=None, width=1920, height=1080, n_views=8,
+                      seg_range=(5000, 40000), label_choices=(128, 256)):
+    """Batching workload: `n_frames` independent arc-rig frames with segment
+    counts U{seg_range} and label counts drawn from `label_choices`."""
+    return list(iter_batch_frames(n_frames, seed, width, height, n_views, seg_range, label_choices))
 
 
 def true_depth(wl: Workload, view: int):

@@ -79,3 +79,93 @@ def tie_aware(G, O, tol=1e-5):
     O = np.asarray(O, np.float64)
     ga = np.argmin(G, 1)
     return float((O[np.arange(len(O)), ga] <= O.min(1) + tol).mean())
+
+
+EDGE = 1.0 / 64.0
+
+
+def position_error_bound(ns):
+    """Bound on the FP32 error of a projected coordinate, in pixels: the
+    sweep forms u, v from FP32 constants of the projection, three multiply-
+    adds and one reciprocal, a few roundings on coordinates below the larger
+    image side; four units in the last place of that side."""
+    side = max(max(c.width, c.height) for c in ns.cams) + 2
+    return 4.0 * side * 2.0 ** -23
+
+
+def band_distance(ns, rows, labels):
+    """For each (row, label) pair: the smallest distance, in pixels, of any
+    of the segment's FP64 projected samples (in front of both cameras, any
+    target) to an edge of the bilinear validity band [-1/64, W - 1 + 1/64] x
+    [-1/64, H - 1 + 1/64], with the rig-centre depth reference.  A sample
+    closer to the edge than the FP32 position error may be valid on one side
+    and not on the other, which moves that entry by up to one pixel's share
+    of the segment mean."""
+    n = len(ns.cams)
+    off = np.concatenate([[0], np.cumsum(np.asarray(ns.S))])
+    centres = np.array([c.center for c in ns.cams])
+    a = np.array([c.axis for c in ns.cams]).mean(0)
+    nr, Cr = a / np.linalg.norm(a), centres.mean(0)
+    rho = 1 / ns.z_far + np.arange(ns.num_labels) / max(ns.num_labels - 1, 1) * (1 / ns.z_near - 1 / ns.z_far)
+    lists = {}
+
+    def pixels(c, s):
+        if c not in lists:
+            flat = np.asarray(ns.seg[c]).ravel()
+            order = np.argsort(flat, kind="stable")
+            start = np.concatenate([[0], np.cumsum(np.bincount(flat, minlength=ns.S[c]))])
+            lists[c] = (order, start)
+        order, start = lists[c]
+        idx = order[start[s]:start[s + 1]]
+        w = ns.cams[c].width
+        return idx % w, idx // w
+
+    rows = np.asarray(rows)
+    labels = np.asarray(labels)
+    out = np.full(len(rows), np.inf)
+    for row in np.unique(rows):
+        sel = np.flatnonzero(rows == row)
+        c = int(np.searchsorted(off, row, side="right") - 1)
+        cam = ns.cams[c]
+        xs, ys = pixels(c, int(row - off[c]))
+        p = np.stack([xs.astype(float), ys.astype(float), np.ones(len(xs))])
+        d = (cam.R.T @ np.linalg.inv(cam.K) @ p).T
+        for i in sel:
+            tau = (1 / rho[labels[i]] - (centres[c] - Cr) @ nr) / (d @ nr)
+            X = centres[c] + tau[:, None] * d
+            for c2 in range(n):
+                if c2 == c:
+                    continue
+                t = ns.cams[c2]
+                Xc = X @ t.R.T + t.t
+                h = Xc @ t.K.T
+                ok = (tau > 0) & (Xc[:, 2] > 0)
+                if not ok.any():
+                    continue
+                u, v = h[ok, 0] / h[ok, 2], h[ok, 1] / h[ok, 2]
+                dist = np.minimum.reduce([np.abs(u + EDGE), np.abs(u - (t.width - 1 + EDGE)),
+                                          np.abs(v + EDGE), np.abs(v - (t.height - 1 + EDGE))])
+                out[i] = min(out[i], float(dist.min()))
+    return out
+
+
+def assert_large_errors_explained(ns, G, O, rows=None, thresh=1e-3, label=""):
+    """Every entry with |G - O| > thresh must have an FP64 sample within the
+    FP32 position error of the bilinear validity edge (band_distance).
+    Returns (number of such entries, largest error)."""
+    G = np.asarray(G, np.float64)
+    O = np.asarray(O, np.float64)
+    err = np.abs(G - O)
+    r, l = np.nonzero(err > thresh)
+    if rows is not None:
+        r_glob = np.asarray(rows)[r]
+    else:
+        r_glob = r
+    if len(r):
+        dist = band_distance(ns, r_glob, l)
+        eps = position_error_bound(ns)
+        bad = dist > eps
+        assert not bad.any(), (f"{label}: {int(bad.sum())} of {len(r)} entries above {thresh} have no sample within "
+                               f"{eps:.2e} px of the validity edge (worst at distance {dist.max():.3g} px, "
+                               f"error {err[r[bad], l[bad]].max():.3g})")
+    return len(r), float(err.max())

@@ -247,10 +247,15 @@ def test_depth_map_and_footprint_argument_checks(lib):
     cams, segs = _cams(n, w, h), _segs(n, S, w, h)
     big = ctypes.c_void_p(0x100000)
     bad = ivde.label_range(2.0, 2.0, L)
-    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(bad), big, big, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(bad), big, big, 4 * L, big, None) == ivde.IVDE_EINVAL
     lr = ivde.label_range(1.0, 5.0, L)
-    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), None, big, None) == ivde.IVDE_EINVAL
-    assert lib.ivde_depth_map(0, cams, segs, ctypes.byref(lr), big, big, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), None, big, 4 * L, big, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_depth_map(0, cams, segs, ctypes.byref(lr), big, big, 4 * L, big, None) == ivde.IVDE_EINVAL
+    # the level-depth table needs 4 L bytes of 4-byte aligned workspace
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), big, None, 4 * L, big, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), big, ctypes.c_void_p(0x100002), 4 * L, big,
+                              None) == ivde.IVDE_EINVAL
+    assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), big, big, 4 * L - 4, big, None) == ivde.IVDE_ENOMEM
     r, q = ctypes.c_size_t(), ctypes.c_size_t()
     opt = ivde.options(ivde.BILINEAR, ivde.F16)
     assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, ctypes.byref(r),

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_common import compare, run_oracle, tie_aware
+from tests.gpu_common import assert_large_errors_explained, compare, run_oracle, tie_aware
 
 pytestmark = pytest.mark.gpu
 
@@ -97,16 +97,21 @@ def test_batched_mixed_label_counts_other_shapes():
         b.close()
 
 
+@pytest.mark.timeout(1200)
 def test_batched_full_size_1080p_frames():
-    """The batching workload at full size: three 8-view 1920x1080 frames with
-    their own segment and label counts, one persistent launch replayed from a
-    hipGraph in the autotuned shape, as the benchmark times it.  Every frame
-    is bitwise its plain launch, and 2000 seeded rows per frame are checked
-    against the oracle (frame 0 holds a row whose two best levels differ by
-    4e-7 in the oracle, below the FP32 accumulation error, so the sample is
-    large enough for the 99.9% agreement bar to allow such rows)."""
+    """The batching workload at full size: all 16 8-view 1920x1080 frames the
+    benchmark times, with their own segment and label counts, in one
+    persistent launch replayed from a hipGraph in the autotuned shape.  Every
+    frame is bitwise its plain launch, and a seeded 2% of each frame's rows
+    is checked against the oracle (strict argmin agreement over the 16
+    frames' samples at 99.9%, and per frame at least 99.5%: a frame's sample
+    of a few hundred rows can hold a row whose two best levels differ by less
+    than the FP32 accumulation error)."""
     _case("batched full size")
-    wls = synth.make_batch_frames(3)
+    wls = []
+    for i, wl in enumerate(synth.iter_batch_frames(16)):
+        wls.append(wl)
+        print(f"[case] batch frame {i} generated: {sum(wl.S)} segments, {wl.num_labels} labels", flush=True)
     assert {wl.num_labels for wl in wls} == {128, 256} and all(wl.seg[0].shape == (1080, 1920) for wl in wls)
     dvs = [ivde.DeviceViews.from_workload(wl) for wl in wls]
     lrs = [ivde.label_range(wl.z_near, wl.z_far, wl.num_labels) for wl in wls]
@@ -123,15 +128,20 @@ def test_batched_full_size_1080p_frames():
     torch.cuda.synchronize()
     b.close()
     rng = np.random.default_rng(21)
+    agree, total = 0, 0
     for i, (wl, c, l, r) in enumerate(zip(wls, costs, labs, ref)):
         assert torch.equal(c, r), f"frame {i}"
         assert torch.equal(l, ivde.argmin(r)), f"frame {i}"
-        rows = np.sort(rng.choice(c.shape[0], 2000, replace=False))
+        rows = np.sort(rng.choice(c.shape[0], max(1, c.shape[0] // 50), replace=False))
         G = c[torch.from_numpy(rows).cuda()].double().cpu().numpy()
-        # the mean and argmin bars only: a bilinear sample on the validity
-        # boundary can move one small segment's entry by one pixel's share
-        res = compare(G, run_oracle(wl, rows=rows), label=f"frame {i}")
-        print(f"frame {i}: segments {sum(wl.S)} labels {wl.num_labels} {res}", flush=True)
+        O = run_oracle(wl, rows=rows)
+        res = compare(G, O, argmin_min=0.995, label=f"frame {i}")
+        n_big, worst = assert_large_errors_explained(wl, G, O, rows=rows, label=f"frame {i}")
+        agree += int((np.argmin(G, 1) == np.argmin(O, 1)).sum())
+        total += len(rows)
+        print(f"frame {i}: segments {sum(wl.S)} labels {wl.num_labels} rows {len(rows)} {res} "
+              f"above 1e-3: {n_big}", flush=True)
+    assert agree / total >= 0.999, (agree, total)
 
 
 def test_autotune():
@@ -173,27 +183,35 @@ def test_precision_small_512_labels():
     assert np.abs(G16 - G32).max() <= 2.0 ** -12
 
 
+@pytest.mark.timeout(900)
 def test_precision_4k_full_size():
     """The precision workload at full size: the 8-view arc rig at 4096x2160,
     40000 segments per view, 512 labels, bilinear, FP32 accumulation; FP32
-    and FP16 storage against the FP64 oracle on 2000 seeded rows."""
+    and FP16 storage against the FP64 oracle on 6000 seeded rows.  Mean
+    error and strict argmin agreement at the stated bars (FP16: the FP16
+    bars); every entry off by more than 1e-3 (FP32) or 2e-3 (FP16: 1e-3 plus
+    the 2^-12 storage rounding and margin) must hold a sample within the FP32
+    position error of the bilinear validity edge, and the largest error is
+    reported."""
     _case("precision 4k")
     wl = synth.make_arc_workload("arc-8x4096x2160", synth.SEED_PRECISION, width=4096, height=2160,
                                  f=1400.0 * 4096 / 1920, n_segments=40000, num_labels=512)
     rng = np.random.default_rng(1)
     dv = ivde.DeviceViews.from_workload(wl)
-    rows = np.sort(rng.choice(dv.rows, 2000, replace=False))
+    rows = np.sort(rng.choice(dv.rows, 6000, replace=False))
     O = run_oracle(wl, rows=rows)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
     idx = torch.from_numpy(rows).cuda()
     res = {}
-    for name, dt in (("f32", ivde.F32), ("f16", ivde.F16)):
+    for name, dt, thresh in (("f32", ivde.F32, 1e-3), ("f16", ivde.F16, 2e-3)):
         C, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, dt))
         G = C[idx].double().cpu().numpy()
         res[name] = compare(G, O, f16=dt == ivde.F16, label=name)
         res[name]["tie_aware"] = _tie_aware(G, O)
+        res[name]["above_thresh"], _ = assert_large_errors_explained(wl, G, O, rows=rows, thresh=thresh,
+                                                                     label=name)
         del C
-    print(f"precision 4k: {res}")
+    print(f"precision 4k: {res}", flush=True)
 
 
 # ---------------------------------------------------------------- serving

@@ -137,3 +137,39 @@ def test_server_rule_frames_match_oracle(dtype):
         total_checked += keep.sum()
         prev, mean_prev = want, mean
     assert total_checked >= 0.99 * len(frames) * outs[0].shape[0]
+
+
+def test_server_fp16_odd_label_and_row_counts():
+    """FP16 storage with an odd number of levels and of rows: every row of
+    the resident volume, every I-frame copy and every cost_out copy is a
+    whole number of 2-byte entries but not of 4-byte words.  Rule frames and
+    masked frames must equal the same frames served with FP32 storage after
+    rounding (the FP16 store rounds the FP32 result)."""
+    _case("served fp16 odd L and rows")
+    wl = synth.make_small_arc(seed=63, n_views=3, width=128, height=80, n_segments=139, num_labels=47)
+    assert sum(wl.S) % 2 == 1 and wl.num_labels % 2 == 1
+    frames = synth.make_sequence(wl, 4, seed=64)
+    dv = ivde.DeviceViews.from_workload(wl)
+    lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
+    outs = {}
+    for dtype, tdt in ((ivde.F16, torch.float16), (ivde.F32, torch.float32)):
+        srv = ivde.Server(1 << 30, max_slots=2)
+        rid_rule = srv.register(dv, lr, ivde.options(ivde.BILINEAR, dtype))
+        rid_mask = srv.register(dv, lr, ivde.options(ivde.BILINEAR, dtype))
+        got = []
+        for i, fr in enumerate(frames):
+            img = ivde.DeviceViews(wl.cams, fr["Y"], fr["U"], fr["V"], wl.seg, wl.S, wl.bit_depth, wl.chroma_shift)
+            a = torch.empty((dv.rows, wl.num_labels), dtype=tdt, device="cuda")
+            b = torch.empty((dv.rows, wl.num_labels), dtype=tdt, device="cuda")
+            la = torch.empty(dv.rows, dtype=torch.int32, device="cuda")
+            st = srv.wait(srv.submit_rule(rid_rule, img.c_images, iframe=(i == 0), cost_out=a, label_out=la))
+            assert st["status"] == 0
+            m = None if fr["mask"] is None else torch.from_numpy(np.concatenate(fr["mask"]).astype(np.uint8)).cuda()
+            st = srv.wait(srv.submit(rid_mask, img.c_images, m, b))
+            assert st["status"] == 0
+            assert torch.equal(la, ivde.argmin(a))
+            got.append((a.clone(), b.clone()))
+        srv.close()
+        outs[dtype] = got
+    for (a16, b16), (a32, b32) in zip(outs[ivde.F16], outs[ivde.F32]):
+        assert torch.equal(a16, a32.half()) and torch.equal(b16, b32.half())
