@@ -17,6 +17,14 @@ ARGMIN_AGREE = 0.999
 ARGMIN_AGREE_F16 = 0.99
 TIE_F16 = 2.0 ** -11
 TIE_AWARE_MIN = 0.999
+# The oracle forms each entry as an FP64 sum of n per-pixel costs in [0, 1]
+# divided by n: its error is below n 2^-53 <= 1.2e-12 for segments of up to
+# 10^4 pixels.  Labels whose oracle costs differ by less than that are tied
+# as far as the oracle can tell (a rectified rig makes such ties exactly: a
+# label just short of a plane's integer disparity towards one neighbour and
+# the label just past it towards the other sum the same pixel differences),
+# so strict agreement accepts any label of the oracle's tie set.
+TIE_F64 = 1.2e-12
 
 
 def run_gpu(ns, sampling=None, cost_dtype=ivde.F32, targets=ivde.TARGETS_ALL, target_mask=None,
@@ -62,14 +70,25 @@ def compare(G, O, f16=False, argmin_min=None, label=""):
     sent_o = np.all(O == 1.0, axis=1)
     sent_g = np.all(G == 1.0, axis=1)
     assert np.array_equal(sent_o, sent_g), f"{label}: sentinel rows differ"
-    ag = (np.argmin(G, 1) == np.argmin(O, 1)).mean()
+    ag = strict_agreement(G, O)
     assert ag >= argmin_min, f"{label}: argmin agreement {ag:.5f} < {argmin_min}"
-    out = dict(mean_err=float(err.mean()), max_err=float(err.max()), argmin_agree=float(ag))
+    out = dict(mean_err=float(err.mean()), max_err=float(err.max()), argmin_agree=float(ag),
+               f64_tie_rows=int((np.sort(O, 1)[:, 1] - O.min(1) <= TIE_F64).sum()) if O.shape[1] > 1 else 0)
     if f16:
         ta = tie_aware(G, O, TIE_F16)
         assert ta >= TIE_AWARE_MIN, f"{label}: tie-aware argmin agreement {ta:.5f} < {TIE_AWARE_MIN}"
         out["tie_aware"] = ta
     return out
+
+
+def strict_agreement(G, O):
+    """Share of rows whose GPU argmin (lowest label among minima) is the
+    oracle's, or one the oracle cannot tell from its minimum (TIE_F64)."""
+    G = np.asarray(G, np.float64)
+    O = np.asarray(O, np.float64)
+    ga, oa = np.argmin(G, 1), np.argmin(O, 1)
+    tied = O[np.arange(len(O)), ga] <= O.min(1) + TIE_F64
+    return float(((ga == oa) | tied).mean())
 
 
 def tie_aware(G, O, tol=1e-5):
