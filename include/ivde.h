@@ -178,6 +178,26 @@ ivde_status ivde_cost_volume(int32_t n_views, const ivde_camera *cams,
 ivde_status ivde_argmin(int64_t rows, int32_t num_labels, int32_t cost_dtype,
                         const void *cost, int32_t *label_out, ivde_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): ivde_cost_volume
+ * without a workspace argument.  The workspace lives in a fixed array of the
+ * library in device memory, IVDE_NOALLOC_SCRATCH_BYTES (64 MiB) on every GPU
+ * the library runs on, held until the process ends; the call allocates no
+ * device memory.  Problems whose ivde_cost_volume_size workspace exceeds
+ * that size are refused with IVDE_ENOMEM before anything is enqueued (for
+ * example 3 views of 320 x 240 need about 10 MiB; 8 views of 1920 x 1080 do
+ * not fit).  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind; each call clears what it needs with kernels on its own
+ * stream, so calls on one GPU must not overlap (calls on different streams
+ * that overlap in time race on the array).  Segment ids out of range are
+ * skipped as in ivde_cost_volume but cannot be queried afterwards (there is
+ * no workspace to pass to ivde_workspace_status).  Results are bitwise those
+ * of ivde_cost_volume with the same arguments. */
+#define IVDE_NOALLOC_SCRATCH_BYTES (64u << 20)
+ivde_status ivde_cost_volume_noalloc(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
+                                     const ivde_segmentation *segs, const ivde_label_range *labels,
+                                     const ivde_options *opt, void *cost_out, ivde_stream stream);
+
 /* After the stream that ran ivde_cost_volume with this workspace has
  * completed: IVDE_EINVAL if a segment id was out of range, else IVDE_OK.
  * Synchronises `stream`. */

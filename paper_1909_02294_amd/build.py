@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libivde.so")
-SOURCES = ["kernels.hip", "terms.hip", "host.cpp", "batch.cpp", "server.cpp", "autotune.cpp", "window.cpp", "intra.cpp", "graphcut.cpp", "depth.cpp"]
+SOURCES = ["kernels.hip", "terms.hip", "host.cpp", "batch.cpp", "server.cpp", "autotune.cpp", "window.cpp", "intra.cpp", "graphcut.cpp", "depth.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

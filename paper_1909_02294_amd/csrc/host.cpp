@@ -509,6 +509,27 @@ ivde_status check_tex_limits(const Layout &ly)
     return IVDE_OK;
 }
 
+ivde_status enqueue_cost_volume(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                                const ivde_segmentation *segs, const ivde_label_range *labels,
+                                const ivde_options *opt, const Layout &ly, char *ws, void *cost_out, hipStream_t s)
+{
+    Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
+    ivde_status st = enqueue_front(n, cams, views, segs, labels, opt, ly, ws, cost_out, 0, tasks, s);
+    if (st != IVDE_OK) return st;
+    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    hipError_t e;
+    if (opt->sweep_events[0] && opt->sweep_events[1] &&
+        (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[0]), s)) != hipSuccess)
+        return hip_fail(e, "event record");
+    e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, opt->sampling == IVDE_BILINEAR, ly.tex_f32, ly.f16, ly.wpg,
+                     reinterpret_cast<int32_t *>(ws + ly.off_cursors), s);
+    if (e != hipSuccess) return hip_fail(e, "sweep");
+    if (opt->sweep_events[0] && opt->sweep_events[1] &&
+        (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[1]), s)) != hipSuccess)
+        return hip_fail(e, "event record");
+    return IVDE_OK;
+}
+
 }  // namespace ivde
 
 using namespace ivde;
@@ -544,23 +565,8 @@ ivde_status ivde_cost_volume(int32_t n_views, const ivde_camera *cams, const ivd
     const Layout ly = plan_layout(n_views, cams, segs, labels, opt, views[0].bit_depth);
     if ((st = check_workspace(workspace, workspace_bytes, ly.workspace_bytes)) != IVDE_OK) return st;
     if ((st = check_tex_limits(ly)) != IVDE_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char *ws = static_cast<char *>(workspace);
-    Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
-    st = enqueue_front(n_views, cams, views, segs, labels, opt, ly, ws, cost_out, 0, tasks, s);
-    if (st != IVDE_OK) return st;
-    const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
-    hipError_t e;
-    if (opt->sweep_events[0] && opt->sweep_events[1] &&
-        (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[0]), s)) != hipSuccess)
-        return hip_fail(e, "event record");
-    e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, opt->sampling == IVDE_BILINEAR, ly.tex_f32, ly.f16, ly.wpg,
-                     reinterpret_cast<int32_t *>(ws + ly.off_cursors), s);
-    if (e != hipSuccess) return hip_fail(e, "sweep");
-    if (opt->sweep_events[0] && opt->sweep_events[1] &&
-        (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[1]), s)) != hipSuccess)
-        return hip_fail(e, "event record");
-    return IVDE_OK;
+    return enqueue_cost_volume(n_views, cams, views, segs, labels, opt, ly, static_cast<char *>(workspace), cost_out,
+                               static_cast<hipStream_t>(stream));
 }
 
 ivde_status ivde_argmin(int64_t rows, int32_t num_labels, int32_t cost_dtype, const void *cost, int32_t *label_out,

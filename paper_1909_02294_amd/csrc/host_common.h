@@ -72,6 +72,11 @@ ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *
                           hipStream_t s,
                           bool index_ready = false, bool texels = true, bool worklist = true);
 ivde_status check_workspace(const void *workspace, size_t have, size_t need);
+// The plain cost volume into a validated workspace `ws` laid out as `ly`:
+// constants, segment index, work list and the sweep, enqueued on `s`.
+ivde_status enqueue_cost_volume(int32_t n, const ivde_camera *cams, const ivde_image *views,
+                                const ivde_segmentation *segs, const ivde_label_range *labels,
+                                const ivde_options *opt, const Layout &ly, char *ws, void *cost_out, hipStream_t s);
 ivde_status check_tex_limits(const Layout &ly);
 
 }  // namespace ivde

@@ -19,6 +19,7 @@ REF_RIG_CENTER, REF_OWN = -1, -2
 NEAREST, BILINEAR = 0, 1
 F32, F16 = 0, 1
 TARGETS_ALL, TARGETS_NEAREST_LR, TARGETS_EXPLICIT = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20     # IVDE_NOALLOC_SCRATCH_BYTES
 
 
 class IvdeError(RuntimeError):
@@ -85,6 +86,7 @@ _I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 SIGNATURES = {
     "ivde_cost_volume_size": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P]),
     "ivde_cost_volume": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P]),
+    "ivde_cost_volume_noalloc": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
     "ivde_argmin": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
     "ivde_workspace_status": (_I32, [_P, _P]),
     "ivde_batch_size": (_I32, [_I32, _P, _P, _P]),
@@ -305,6 +307,21 @@ def cost_volume(dv: DeviceViews, lr: LabelRange, opt: Options, workspace=None, o
                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out, workspace
+
+
+def cost_volume_noalloc(dv: DeviceViews, lr: LabelRange, opt: Options, out=None, stream=None):
+    """ivde_cost_volume_noalloc: the cost volume with the library's fixed
+    device scratch array as workspace; the call itself allocates no device
+    memory (pass `out` to allocate nothing here either)."""
+    torch = _torch()
+    L = lr.num_labels
+    dtype = torch.float16 if opt.cost_dtype == F16 else torch.float32
+    if out is None:
+        out = torch.empty((dv.rows, L), dtype=dtype, device="cuda")
+    _check(out, "out", dtype, (dv.rows, L))
+    check(load().ivde_cost_volume_noalloc(dv.n, dv.c_cams, dv.c_images, dv.c_segs, ctypes.byref(lr),
+                                          ctypes.byref(opt), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
 
 
 def argmin(cost, stream=None, out=None):

@@ -282,3 +282,31 @@ def test_binding_rejects_tensors_the_library_would_misread():
         ivde._check(ok, "cost", torch.float32, (5,), cuda=False)
     with pytest.raises(ValueError, match="GPU"):
         ivde._check(ok, "cost", torch.float32)
+
+
+def test_noalloc_refuses_problems_beyond_its_scratch_array(lib):
+    """ivde_cost_volume_noalloc checks the workspace a problem needs against
+    its fixed scratch array before touching any device memory."""
+    n, w, h, S, L = 8, 1920, 1080, 100, 64
+    cams, segs = _cams(n, w, h), _segs(n, S, w, h)
+    imgs = (ivde.Image * n)()
+    for i in range(n):
+        for p in range(3):
+            imgs[i].plane[p] = 0x2000          # never dereferenced: the call is refused first
+            imgs[i].pitch[p] = w
+        imgs[i].bit_depth, imgs[i].chroma_shift = 10, 1
+    lr = ivde.label_range(1.5, 10.0, L)
+    opt = ivde.options(ivde.BILINEAR, ivde.F32)
+    wb = ctypes.c_size_t()
+    assert lib.ivde_cost_volume_size(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, None,
+                                     ctypes.byref(wb)) == ivde.IVDE_OK
+    assert wb.value > ivde.NOALLOC_SCRATCH_BYTES
+    m = re.search(r"#define IVDE_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == ivde.NOALLOC_SCRATCH_BYTES
+    st = lib.ivde_cost_volume_noalloc(n, cams, imgs, segs, ctypes.byref(lr), ctypes.byref(opt),
+                                      ctypes.c_void_p(0x3000), None)
+    assert st == ivde.IVDE_ENOMEM
+    assert b"scratch" in lib.ivde_last_error()
+    # a null output is an argument error, found first
+    assert lib.ivde_cost_volume_noalloc(n, cams, imgs, segs, ctypes.byref(lr), ctypes.byref(opt), None,
+                                        None) == ivde.IVDE_EINVAL
