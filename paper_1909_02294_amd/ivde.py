@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libivde.so")
+# IVDE_LIB selects another build of the same library (the host-sanitizer build)
+LIB_PATH = os.environ.get("IVDE_LIB") or os.path.join(HERE, "libivde.so")
 
 IVDE_OK, IVDE_EINVAL, IVDE_ENOMEM, IVDE_EBUDGET, IVDE_EHIP, IVDE_EBUSY, IVDE_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 REF_RIG_CENTER, REF_OWN = -1, -2
