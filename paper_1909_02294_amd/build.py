@@ -29,9 +29,17 @@ SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
 
 
-def _compile(src: str, sanitize: bool = False) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + (".san.o" if sanitize else ".o"))
-    cmd = [HIPCC, *COMMON, *(SAN_HOST if sanitize else []), "-c", os.path.join(CSRC, src), "-o", obj]
+# Measurement build (libivde_stage.so): the one-label-per-lane sweep stages
+# target footprints of up to this many texels per wave in LDS.
+STAGE_LIB = os.path.join(HERE, "libivde_stage.so")
+STAGE_TEXELS = 624
+
+
+def _compile(src: str, sanitize: bool = False, stage_texels: int = 0) -> str:
+    tag = ".san" if sanitize else f".stage{stage_texels}" if stage_texels else ""
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + tag + ".o")
+    extra = [f"-DIVDE_STAGE_TEXELS={stage_texels}"] if stage_texels else []
+    cmd = [HIPCC, *COMMON, *(SAN_HOST if sanitize else []), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -41,14 +49,15 @@ def _compile(src: str, sanitize: bool = False) -> str:
     return obj
 
 
-def build(verbose: bool = False, sanitize: bool = False) -> str:
-    """Compile every source and link libivde.so (or, with sanitize, the
-    host-sanitizer build libivde_san.so) next to this file."""
+def build(verbose: bool = False, sanitize: bool = False, stage_texels: int = 0) -> str:
+    """Compile every source and link libivde.so next to this file; with
+    sanitize, the host-sanitizer build libivde_san.so; with stage_texels,
+    the LDS-staging measurement build libivde_stage.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, sanitize), srcs))
-    lib = SAN_LIB if sanitize else LIB
+        objs = list(ex.map(lambda s: _compile(s, sanitize, stage_texels), srcs))
+    lib = SAN_LIB if sanitize else STAGE_LIB if stage_texels else LIB
     tmp = lib + ".tmp"
     link_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"] \
         if sanitize else []
@@ -78,4 +87,5 @@ def sanitize_env() -> dict:
 
 
 if __name__ == "__main__":
-    build(verbose=True, sanitize="--sanitize" in sys.argv)
+    build(verbose=True, sanitize="--sanitize" in sys.argv,
+          stage_texels=STAGE_TEXELS if "--stage" in sys.argv else 0)

@@ -87,6 +87,11 @@ __device__ __forceinline__ float2 ldg(const float2 *p)
     const f32x2 v = *(const IVDE_AS1 f32x2 *)(p);
     return make_float2(v.x, v.y);
 }
+__device__ __forceinline__ uint2 ldg2u(const uint2 *p)
+{
+    const u32x2 v = *(const IVDE_AS1 u32x2 *)(p);
+    return make_uint2(v.x, v.y);
+}
 __device__ __forceinline__ float4 ldg(const float4 *p)
 {
     const f32x4 v = *(const IVDE_AS1 f32x4 *)(p);

@@ -368,6 +368,47 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
                 gmax = std::fmax(gmax, std::fabs(gpv));
             }
         d.front_all = sig_pos && gmin > 1e-4 * gmax;
+        // With every point in front of camera v, the points of view v at all
+        // labels fill the part of its viewing frustum (the rays through the
+        // image rectangle) between the nearest and the farthest level plane: a
+        // convex solid whose corners are the four corner rays at those two
+        // planes.  Depth in a target camera is affine in the point, so when all
+        // eight corners lie in front of the target (with a margin for the FP32
+        // evaluation), every point does and the sweep needs no depth test for
+        // that target.
+        d.front_targets = 0;
+        if (d.front_all) {
+            double zmin = INFINITY, zmax = 0.0;
+            for (int l = 0; l < L; ++l) {
+                zmin = std::fmin(zmin, zl[l]);
+                zmax = std::fmax(zmax, zl[l]);
+            }
+            double corner[8][3];
+            int k = 0;
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                    const double p[3] = {cx ? cams[v].width - 1.0 : 0.0, cy ? cams[v].height - 1.0 : 0.0, 1.0};
+                    double dir[3];
+                    mv3(Mv, p, dir);
+                    const double nd = nv[0] * dir[0] + nv[1] * dir[1] + nv[2] * dir[2];
+                    for (int zi = 0; zi < 2; ++zi, ++k) {
+                        const double tau = ((zi ? zmax : zmin) - delta) / nd;
+                        for (int i = 0; i < 3; ++i) corner[k][i] = C[3 * v + i] + tau * dir[i];
+                    }
+                }
+            for (int c2 = 0; c2 < n; ++c2) {
+                if (c2 == v) continue;
+                double dmin = INFINITY, dmax = 0.0;
+                for (int q = 0; q < 8; ++q) {
+                    double xc[3];
+                    mv3(cams[c2].R, corner[q], xc);
+                    const double depth = xc[2] + cams[c2].t[2];
+                    dmin = std::fmin(dmin, depth);
+                    dmax = std::fmax(dmax, std::fabs(depth));
+                }
+                if (std::isfinite(dmin) && dmin > 1e-3 * dmax) d.front_targets |= 1u << c2;
+            }
+        }
         // pairs: H = K2 R2 M_c, e = K2 (R2 C_c + t2), both shifted by one
         // pixel in x and y (rows 0 and 1 gain row 2) to address the target's
         // bordered texel image, whose texel (x + 1, y + 1) is pixel (x, y)

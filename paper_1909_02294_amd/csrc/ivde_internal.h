@@ -34,6 +34,7 @@ struct ViewDesc {
     float *mean;               // [4 S] mean Y, Cb, Cr of the segment, 0
     int32_t n_bands;
     int32_t front_all;         // every pixel at every label lies in front of this camera
+    uint32_t front_targets;    // bit c2: with front_all, every such point also lies in front of view c2
     int32_t n_targets;
     int32_t targets[kMaxViews];
     float g[4];                // g_c = K_c^-T R_c n_r (g . p~ = n_r . ray direction)

@@ -31,6 +31,16 @@ namespace {
 #define IVDE_INFLIGHT 4
 #endif
 
+// LDS texels each wave of the one-label-per-lane sweep may stage a target
+// footprint into (0: none, the default).  32 waves per CU share 160 KB, so
+// 624 is the most that keeps full occupancy; on the 8-view 1080p workload
+// about 11% of (task, target) footprints fit that and the staged sweep was
+// measured slower than the gathers it replaces, so it is built only for
+// measurement (build.py's stage_texels).
+#ifndef IVDE_STAGE_TEXELS
+#define IVDE_STAGE_TEXELS 0
+#endif
+
 constexpr uint32_t kRsrcWord3 = 0x00020000u;   // raw buffer, gfx9 family
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, int64_t bytes)
@@ -415,6 +425,19 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
+#define IVDE_AS3 __attribute__((address_space(3)))
+
+// Byte address of an LDS object in the LDS aperture.
+[[maybe_unused]] __device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(const IVDE_AS3 void *)p; }
+
+// Two consecutive 8-byte texels at LDS byte address a (8-byte aligned).
+[[maybe_unused]] __device__ __forceinline__ uint4 lds_pair(uint32_t a)
+{
+    const IVDE_AS3 u32x2 *t = (const IVDE_AS3 u32x2 *)(uintptr_t)a;
+    const u32x2 x = t[0], y = t[1];
+    return make_uint4(x.x, x.y, y.x, y.y);
+}
+
 // Target samples of one evaluation, as loaded.
 template <bool BIL, bool TEXF32>
 struct Sample;
@@ -447,17 +470,22 @@ struct Target {
     __amdgpu_buffer_rsrc_t rs;
     float lo, hi_x, hi_y;
     uint32_t tp;
-    int rowB;
+    uint32_t rowB;        // bytes per texel row
     float e0, e1, e2;
+    // staged footprint (half texels in LDS): byte address of texel (0, 0)
+    // of the target image relative to the stage, and bytes per stage row
+    uint32_t sbase, srowB;
 };
 
 // Projects one (pixel, label) into the target, decides validity and issues
-// the texel loads: h = q + w e with w = sigma (g . p~) = 1 / tau.  When the
-// host has shown that every pixel and label of the view lies in front of
-// the source camera (FRONT), the w > 0 test is skipped.  Out-of-image
+// the texel loads: h = q + w e with w = sigma (g . p~) = 1 / tau.  FRONT
+// says what the host has shown: 0 nothing (test w > 0, the point in front of
+// the source camera, and h_z > 0, in front of the target), 1 every pixel and
+// label of the view lies in front of the source camera (test h_z > 0 only),
+// 2 and also in front of this target (no test).  Out-of-image
 // coordinates are clamped, so every load is in bounds; the buffer
 // descriptor bounds them again.
-template <bool BIL, bool TEXF32, bool FRONT>
+template <bool BIL, bool TEXF32, int FRONT, bool STAGED = false>
 __device__ __forceinline__ void project_issue(const Target &T, float qx, float qy, float qz, float w,
                                               Sample<BIL, TEXF32> &smp, Weights &wt, bool &valid)
 {
@@ -467,7 +495,7 @@ __device__ __forceinline__ void project_issue(const Target &T, float qx, float q
     const float hz = fmaf(w, T.e2, qz);
     const float r = __builtin_amdgcn_rcpf(hz);
     const float u = hx * r, v = hy * r;
-    valid = FRONT ? (hz > 0.f) : ((w > 0.f) & (hz > 0.f));
+    valid = FRONT == 2 ? true : FRONT == 1 ? (hz > 0.f) : ((w > 0.f) & (hz > 0.f));
     if constexpr (BIL) {
         // clamp into the valid band; the sample is valid iff nothing moved.
         // Clamped coordinates are positive (truncation is floor) and keep
@@ -481,15 +509,22 @@ __device__ __forceinline__ void project_issue(const Target &T, float qx, float q
         wt.w01 = ax - wt.w11;
         wt.w10 = ay - wt.w11;
         wt.w00 = (1.f - ax) - wt.w10;
+        if constexpr (STAGED && !TEXF32) {
+            // the footprint staged in LDS, rows of srowB bytes
+            const uint32_t a = mad_u24(x0, (uint32_t)kTexB, mad_u24(y0, T.srowB, T.sbase));
+            smp.a = lds_pair(a);
+            smp.b = lds_pair(a + T.srowB);
+            return;
+        }
         const int off = (int)(mad_u24(y0, T.tp, x0) * kTexB);
         if constexpr (!TEXF32) {
             smp.a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
-            smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, T.rowB, 0));
+            smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
         } else {
             smp.a0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
             smp.a1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, 0, 0));
-            smp.b0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, T.rowB, 0));
-            smp.b1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, T.rowB, 0));
+            smp.b0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
+            smp.b1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, (int)T.rowB, 0));
         }
     } else {
         const float fx = floorf(u + 0.5f), fy = floorf(v + 0.5f);
@@ -554,7 +589,7 @@ __device__ __forceinline__ float consume(const Sample<BIL, TEXF32> &smp, const W
 // PU pixels x J labels per step: all gathers of the step are issued before
 // the first is consumed, so a wave keeps PU J of them in flight.  The
 // accumulation order per label is the pixel order either way.
-template <int J, int PU, bool BIL, bool TEXF32, bool FRONT>
+template <int J, int PU, bool BIL, bool TEXF32, int FRONT, bool STAGED = false>
 __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int i0, int i1, const float (&H)[9],
                                              const Target &T, const float (&sig)[J], float (&acc)[J],
                                              uint64_t (&acci)[J], int (&cnt)[J])
@@ -578,7 +613,8 @@ __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int 
             const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8]));
 #pragma unroll
             for (int j = 0; j < J; ++j)
-                project_issue<BIL, TEXF32, FRONT>(T, qx, qy, qz, sig[j] * gp, smp[p][j], wt[p][j], val[p][j]);
+                project_issue<BIL, TEXF32, FRONT, STAGED>(T, qx, qy, qz, sig[j] * gp, smp[p][j], wt[p][j],
+                                                          val[p][j]);
         }
         // keep the scheduler from sinking the loads back next to their uses
         if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
@@ -597,12 +633,74 @@ __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int 
             }
         }
     }
-    if constexpr (PU > 1) sweep_pixels<J, 1, BIL, TEXF32, FRONT>(pix, i, i1, H, T, sig, acc, acci, cnt);
+    if constexpr (PU > 1) sweep_pixels<J, 1, BIL, TEXF32, FRONT, STAGED>(pix, i, i1, H, T, sig, acc, acci, cnt);
 }
 
 // One task: labels [64 J b, 64 J (b + 1)) of row (view, seg).
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
-__device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const Task task)
+// The box of target texels that one task's samples can touch in target c2,
+// when every level point of the view lies in front of both cameras: the
+// points of the segment's pixel box between the task's first and last level
+// fill a convex solid (the box's viewing frustum between two level planes)
+// whose eight corners are the box corners at those two levels; a projection
+// with positive depth keeps it convex, so the projected corners bound every
+// sample, and clamping to the validity band (monotone) keeps them in the box.
+// One texel of margin covers FP32 rounding, one more the second bilinear
+// tap.  If the box fits `budget` texels, the wave copies it (rows of bw
+// texels) into its LDS stage and returns true.
+template <int J>
+__device__ __forceinline__ bool stage_footprint(const ViewDesc *vc, const ViewDesc *vt, int s, int l_lo, int l_hi,
+                                                const float *sigma_row, const float (&H)[9], Target &T,
+                                                uint2 *stage, int budget)
+{
+    const int lane = lane_id();
+    const int32_t *bb = ldu(&vc->bbox) + 4 * s;
+    const int bx0 = ldu(bb), by0 = ldu(bb + 1), bx1 = ldu(bb + 2), by1 = ldu(bb + 3);
+    if (bx1 < bx0) return false;   // empty segment
+    const int k = lane & 7;
+    const float cx = (float)((k & 1) ? bx1 : bx0), cy = (float)((k & 2) ? by1 : by0);
+    const float gp = fmaf(ldu(&vc->g[0]), cx, fmaf(ldu(&vc->g[1]), cy, ldu(&vc->g[2])));
+    const float w = sigma_row[(k & 4) ? l_hi : l_lo] * gp;
+    const float hx = fmaf(w, T.e0, fmaf(H[0], cx, fmaf(H[1], cy, H[2])));
+    const float hy = fmaf(w, T.e1, fmaf(H[3], cx, fmaf(H[4], cy, H[5])));
+    const float hz = fmaf(w, T.e2, fmaf(H[6], cx, fmaf(H[7], cy, H[8])));
+    const float r = __builtin_amdgcn_rcpf(hz);
+    const int ix = (int)floorf(__builtin_amdgcn_fmed3f(hx * r, T.lo, T.hi_x));
+    const int iy = (int)floorf(__builtin_amdgcn_fmed3f(hy * r, T.lo, T.hi_y));
+    const bool corner = lane < 8;
+    const int xmin = wave_min_i32(corner ? ix : 0x7fffffff), xmax = -wave_min_i32(corner ? -ix : 0x7fffffff);
+    const int ymin = wave_min_i32(corner ? iy : 0x7fffffff), ymax = -wave_min_i32(corner ? -iy : 0x7fffffff);
+    const int W = ldu(&vt->W), Ht = ldu(&vt->H);
+    const int X0 = max(xmin - 1, 0), X1 = min(xmax + 2, W + 1);
+    const int Y0 = max(ymin - 1, 0), Y1 = min(ymax + 2, Ht + 1);
+    const int bw = X1 - X0 + 1, area = bw * (Y1 - Y0 + 1);
+    if (area > budget) return false;
+    // copy, row-major with pitch bw; stage index t = row * bw + column
+    const uint2 *src = static_cast<const uint2 *>(ldu(&vt->tex)) + (int64_t)Y0 * T.tp + X0;
+    const float inv_bw = __builtin_amdgcn_rcpf((float)bw);
+    for (int t0 = 0; t0 < area; t0 += 4 * kWave) {
+        uint2 val[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + q * kWave + lane;
+            // t < 2^10: the product is within 1e-4 of row + (column + 1/2) / bw
+            const int row = (int)(((float)t + 0.5f) * inv_bw);
+            val[q] = t < area ? ldg2u(src + (int64_t)row * T.tp + (t - row * bw)) : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + q * kWave + lane;
+            if (t < area) stage[t] = val[q];
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);    // lgkmcnt(0): the stage is written before it is read
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    T.srowB = (uint32_t)bw * 8u;
+    T.sbase = lds_addr(stage) - (uint32_t)(Y0 * bw + X0) * 8u;
+    return true;
+}
+
+template <int J, bool BIL, bool TEXF32, bool F16OUT, int STAGE = 0>
+__device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const Task task, uint2 *stage = nullptr)
 {
     constexpr int kTexB = TEXF32 ? 16 : 8;
     constexpr int PU = IVDE_INFLIGHT / J > 0 ? IVDE_INFLIGHT / J : 1;
@@ -622,6 +720,7 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
     const int64_t row0 = ldu(&vc->row0);
 
     const int front_all = ldu(&vc->front_all);
+    const uint32_t front_targets = ldu(&vc->front_targets);
 
     int lab[J];
     float sig[J], best[J];
@@ -658,10 +757,21 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
             acci[j] = 0;
             cnt[j] = 0;
         }
-        if (front_all)
-            sweep_pixels<J, PU, BIL, TEXF32, true>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+        bool staged = false;
+        if constexpr (STAGE > 0 && J == 1 && BIL && !TEXF32) {
+            if (front_all && ((front_targets >> c2) & 1u) && p1 > p0) {
+                const int l_lo = task.lblock * kWave, l_hi = min(l_lo + kWave - 1, L - 1);
+                staged = stage_footprint<J>(vc, vt, s, l_lo, l_hi, sigma + c * L, H, T, stage, STAGE);
+                if (staged) sweep_pixels<J, PU, BIL, TEXF32, 2, true>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+            }
+        }
+        if (staged) {
+        } else if (front_all && ((front_targets >> c2) & 1u))
+            sweep_pixels<J, PU, BIL, TEXF32, 2>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+        else if (front_all)
+            sweep_pixels<J, PU, BIL, TEXF32, 1>(pix, p0, p1, H, T, sig, acc, acci, cnt);
         else
-            sweep_pixels<J, PU, BIL, TEXF32, false>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+            sweep_pixels<J, PU, BIL, TEXF32, 0>(pix, p0, p1, H, T, sig, acc, acci, cnt);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (cnt[j] > 0) {
@@ -691,11 +801,12 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
 // the others, so no XCD idles while another has work (with one XCD per view
 // in a view-major task list, views whose gathers cost more no longer set
 // the kernel's end).
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
+template <int J, bool BIL, bool TEXF32, bool F16OUT, int STAGE = 0>
 __device__ __forceinline__ void sweep_persistent_body(const Problem *__restrict__ probs,
                                                       const Task *__restrict__ tasks,
                                                       const int32_t *__restrict__ n_tasks,
-                                                      int32_t *__restrict__ cursors, int64_t max_tasks)
+                                                      int32_t *__restrict__ cursors, int64_t max_tasks,
+                                                      uint2 *stage = nullptr)
 {
     const int lane = lane_id();
     const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
@@ -714,7 +825,7 @@ __device__ __forceinline__ void sweep_persistent_body(const Problem *__restrict_
             t = uniform(__shfl(t, 0));
             if (t >= n) break;
             const Task task = ldu_task(tasks + lo + t);
-            sweep_task<J, BIL, TEXF32, F16OUT>(probs + task.problem, task);
+            sweep_task<J, BIL, TEXF32, F16OUT, STAGE>(probs + task.problem, task, stage);
         }
     }
 }
@@ -735,7 +846,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
     int32_t *__restrict__ cursors, int64_t max_tasks)
 {
+#if IVDE_STAGE_TEXELS > 0
+    __shared__ uint2 stage[4][IVDE_STAGE_TEXELS];
+    sweep_persistent_body<1, BIL, false, F16OUT, IVDE_STAGE_TEXELS>(probs, tasks, n_tasks, cursors, max_tasks,
+                                                                    stage[threadIdx.x / kWave]);
+#else
     sweep_persistent_body<1, BIL, false, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
+#endif
 }
 
 // Cursors of the sweep to zero, then the task count.
