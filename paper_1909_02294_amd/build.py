@@ -71,6 +71,84 @@ def build(verbose: bool = False, sanitize: bool = False, stage_texels: int = 0) 
     return lib
 
 
+MIX_JSON = LIB + ".sweep_mix.json"
+SWEEP_SYMBOL = "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil"
+
+
+def sweep_mix(verbose: bool = False) -> dict:
+    """Instruction counts of the sweep's hot loop, from the gfx950 assembly
+    of this build: the one-label-per-lane bilinear FP32-store kernel's
+    four-pixel loop (8 buffer gathers) for target views proven in front of
+    every level point (the fewest compares of its three such loops).
+    Written next to the library for the benchmark's issue model."""
+    import json
+    import re
+    import tempfile
+
+    with tempfile.TemporaryDirectory() as td:
+        asm = os.path.join(td, "kernels.s")
+        r = subprocess.run([HIPCC, *COMMON, "--cuda-device-only", "-S", "-o", asm, os.path.join(CSRC, "kernels.hip")],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"assembly of kernels.hip failed:\n{r.stderr}")
+        text = open(asm).read()
+    start = text.index(SWEEP_SYMBOL + ":")
+    end = text.index(".Lfunc_end", start)
+    blocks, name, body = {}, None, []
+    for line in text[start:end].splitlines():
+        m = re.match(r"^(\.LBB\w+):", line)
+        if m or line.startswith("; %bb."):     # labelled and fall-through blocks
+            if name:
+                blocks[name] = body
+            name, body = (m.group(1) if m else None), []
+        elif name:
+            ins = line.split(";")[0].strip()
+            if ins and not ins.startswith("."):
+                body.append(ins)
+    if name:
+        blocks[name] = body
+    loops = []
+    for name, body in blocks.items():
+        if body and body[-1].split()[0].startswith("s_cbranch") and body[-1].split()[-1] == name:
+            ops = [b.split()[0] for b in body]
+            if sum(o == "buffer_load_dwordx4" for o in ops) == 8:
+                loops.append((sum(o.startswith("v_cmp") for o in ops), name, ops))
+    if not loops:
+        raise RuntimeError("sweep loop not found in the assembly")
+    _, name, ops = min(loops)
+    counts = {}
+    for o in ops:
+        counts[o] = counts.get(o, 0) + 1
+    mix = {"kernel": SWEEP_SYMBOL, "loop": name, "pixels_per_iteration": 4,
+           "valu_instructions": sum(v for k, v in counts.items() if k.startswith("v_")),
+           "gathers": counts.get("buffer_load_dwordx4", 0), "counts": dict(sorted(counts.items()))}
+    with open(MIX_JSON, "w") as fh:
+        json.dump(mix, fh, indent=1)
+    if verbose:
+        print(f"sweep loop {name}: {mix['valu_instructions']} VALU instructions, {mix['gathers']} gathers per "
+              f"4 pixels -> {MIX_JSON}")
+    return mix
+
+
+CALIB_LIB = os.path.join(HERE, "libivde_calib.so")
+
+
+def build_calib(verbose: bool = False) -> str:
+    """libivde_calib.so: the calibration kernels behind the benchmark's
+    roofline (instruction issue costs, shader clock, gather rate)."""
+    os.makedirs(BUILD, exist_ok=True)
+    obj = _compile("calib.hip")
+    tmp = CALIB_LIB + ".tmp"
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, obj], capture_output=True,
+                       text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, CALIB_LIB)
+    if verbose:
+        print(f"built {CALIB_LIB}")
+    return CALIB_LIB
+
+
 def sanitize_env() -> dict:
     """Environment that runs Python against libivde_san.so: the ASan runtime
     preloaded (the interpreter itself is not instrumented), leaks not
