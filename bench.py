@@ -13,6 +13,9 @@ Inputs are resident in HBM before the timed region.  Prints one JSON line.
                   label counts: one sweep launch over all frames in a
                   hipGraph against 16 sequential single-frame calls
   --mode served   the serving loop on a Poisson stream from three rigs
+  --mode shapes   the sweep rate by segment count and level count (the
+                  batching workload's shape classes), autotuned per class
+  --mode precision  4096x2160, 512 levels: FP16 against FP32 cost storage
   --mode copycal  a device copy of known size (calibrates HBM counters)
   --mode window   the paper's own 3x3 centre-window term
   --mode intra    the intra-view term: adjacency, weights, per-label costs
@@ -453,7 +456,9 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 20; 10 batches in batched mode; 1 frame in depth mode)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["plain", "batched", "served", "copycal", "window", "intra", "depth"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batched", "served", "shapes", "precision", "copycal", "window", "intra",
+                                       "depth"],
+                    default="plain")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--labels-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
@@ -466,9 +471,19 @@ def main():
     ap.add_argument("--threads", type=int, default=0, help="depth: host threads (default min(16, cores))")
     ap.add_argument("--rule", action="store_true",
                     help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")
+    ap.add_argument("--chunk-evals", type=int, default=0,
+                    help="served: evaluations per launch of a full-frame sweep (0: library default, <0: one launch)")
+    ap.add_argument("--no-uncut", action="store_true",
+                    help="served: skip the comparison run with full sweeps in one launch")
+    ap.add_argument("--device-frames", action="store_true",
+                    help="served: frames resident on the device before submission (no upload in the latency)")
+    ap.add_argument("--served-frames", type=int, default=6, help="served: distinct frames per rig")
+    ap.add_argument("--tune-cache", default=None,
+                    help="batched, shapes: JSON file caching tuned launch shapes per shape class "
+                         "(default: kept in memory for this run)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"depth": 1, "batched": 10}.get(args.mode, 20)
+        args.steps = {"depth": 1, "batched": 10, "precision": 5, "shapes": 5}.get(args.mode, 20)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the sweep would shard "
               "by view, frame or level block, needing only the images replicated to every GPU)",
@@ -491,6 +506,12 @@ def main():
     elif args.mode == "batched":
         from paper_1909_02294_amd import benchforms
         out = benchforms.bench_batched(args)
+    elif args.mode == "shapes":
+        from paper_1909_02294_amd import benchforms
+        out = benchforms.bench_shapes(args)
+    elif args.mode == "precision":
+        from paper_1909_02294_amd import benchforms
+        out = benchforms.bench_precision(args)
     else:
         from paper_1909_02294_amd import benchforms
         out = benchforms.bench_served(args)

@@ -244,6 +244,12 @@ typedef struct {
     void *arena;              /* device memory; its size is the HBM budget */
     size_t arena_bytes;
     int32_t max_slots;        /* requests in flight on the device at once (1..16) */
+    int32_t reserved;         /* must be 0 */
+    int64_t chunk_evals;      /* a full-frame sweep runs as launches of about this many
+                                 pixel-label-target evaluations, and the next launch is
+                                 enqueued only while no other rig's uncut frame is in
+                                 flight, so short frames wait at most one launch behind a
+                                 full one; 0: 4e9 (about 4 ms on MI355X); < 0: one launch */
 } ivde_server_config;
 
 typedef struct {
@@ -268,13 +274,15 @@ ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out)
 
 /* Arena bytes a rig holds while registered (resident: segment maps, the
  * rig's workspace sized for 16-bit images, two cost volumes, two mean-colour
- * tables) and one of its frames holds while admitted (per_request, for
- * images of bit_depth bits): an arena of resident + k per_request bytes runs
- * k of its frames at once. */
+ * tables) and one of its frames holds while admitted, for images of
+ * bit_depth bits and the given chroma_shift: per_request for frames in
+ * device memory, per_host_request for frames handed over in host memory
+ * (plus the staged planes and mask).  An arena of resident + k per_request
+ * bytes runs k of its frames at once.  Any output may be NULL. */
 ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams,
                                   const ivde_segmentation *segs, const ivde_label_range *labels,
-                                  const ivde_options *opt, int32_t bit_depth, size_t *resident,
-                                  size_t *per_request);
+                                  const ivde_options *opt, int32_t bit_depth, int32_t chroma_shift,
+                                  size_t *resident, size_t *per_request, size_t *per_host_request);
 
 /* Registers a rig: its cameras, fixed segmentation (device maps, read
  * during this call only), label range and options.  Reserves the rig's
@@ -306,6 +314,26 @@ ivde_status ivde_stream_submit_rule(ivde_server *srv, int32_t rig_id, const ivde
                                     int32_t iframe, void *cost_out, int32_t *label_out,
                                     uint64_t *ticket);
 ivde_status ivde_rig_set_temporal(ivde_server *srv, int32_t rig_id, float t_p, float t_i);
+
+#define IVDE_SUBMIT_MASK 0          /* changed_mask decides; NULL: every row */
+#define IVDE_SUBMIT_RULE 1          /* as ivde_stream_submit_rule, iframe = 0 */
+#define IVDE_SUBMIT_RULE_IFRAME 2   /* as ivde_stream_submit_rule, iframe = 1 */
+
+/* Submits one frame whose planes are in HOST memory, as camera frames
+ * arrive: host_views[v].plane[i] are host pointers (pinned memory from
+ * hipHostMalloc lets the copies run asynchronously; pageable memory is
+ * accepted but its copies may block the server's scheduler), and in
+ * IVDE_SUBMIT_MASK mode changed_mask is a host uint8 [sum_c S_c] array or
+ * NULL (rule modes take NULL).  At admission the server copies the planes
+ * and the mask into the request's working set on the request's own stream,
+ * ahead of its kernels, so the upload overlaps the rig's previous frame and
+ * is part of the frame's latency (submit_us to done_us).  The host buffers
+ * must stay unchanged until the request completes.  Every view must have
+ * the same bit depth and chroma format.  Otherwise as ivde_stream_submit
+ * (cost_out and label_out are device memory). */
+ivde_status ivde_stream_submit_host(ivde_server *srv, int32_t rig_id, const ivde_image *host_views,
+                                    int32_t mode, const uint8_t *changed_mask, void *cost_out,
+                                    int32_t *label_out, uint64_t *ticket);
 /* IVDE_EBUSY while pending; otherwise fills `st` and forgets the ticket. */
 ivde_status ivde_stream_poll(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st);
 ivde_status ivde_stream_wait(ivde_server *srv, uint64_t ticket, ivde_frame_stats *st);

@@ -14,9 +14,23 @@
 // each a slot (its own HIP stream, default priority), enqueues its kernels
 // and polls completion events.  Requests of different rigs overlap on the
 // device; frames of one rig are ordered by an event dependency on the rig's
-// previous frame, because each frame starts from that frame's volume.  Every
-// row is computed by the same per-task kernel code as ivde_cost_volume, so a
-// frame's result does not depend on what else is in flight.
+// previous frame, because each frame starts from that frame's volume, and a
+// frame's kernels are enqueued only once its predecessor's are.  Every row is
+// computed by the same per-task kernel code as ivde_cost_volume, so a frame's
+// result does not depend on what else is in flight.
+//
+// Full-frame sweeps (I frames) are cut into launches of about chunk_evals
+// evaluations.  The persistent sweep holds every CU until its task list is
+// drained, so one launch over a whole I frame would make the short frames of
+// other rigs that arrive meanwhile wait for all of it.  The scheduler
+// enqueues the next launch of a cut sweep only after the previous one has
+// completed and while no uncut request is in flight, so a P frame admitted
+// during an I frame waits at most for the launch that is running.
+//
+// Frames may also be handed over in host memory (ivde_stream_submit_host):
+// the planes and the mask are copied into the request's working set on its
+// stream right at admission, ahead of everything else, so the upload
+// overlaps the rig's previous frame and counts in the frame's latency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -118,17 +132,25 @@ struct Rig {
 struct Request {
     uint64_t ticket = 0;
     int rig = -1;
-    std::vector<ivde_image> views;
-    const uint8_t *mask = nullptr;
+    std::vector<ivde_image> views;         // device images the kernels read
+    const uint8_t *mask = nullptr;         // device changed mask, NULL: every row
     bool rule = false;                     // derive the mask by the temporal rule
     bool iframe = false;                   // rule mode: compute every row and make this the I frame
+    bool host = false;                     // planes and mask were handed over in host memory
+    std::vector<ivde_image> host_views;
+    const uint8_t *host_mask = nullptr;
     void *cost_out = nullptr;
     int32_t *label_out = nullptr;
     ivde_frame_stats st{};
     Layout ly{};                           // depends on the frame's bit depth
-    size_t work_bytes = 0;
+    size_t work_bytes = 0;                 // working set, plus the staged planes of a host frame
     int slot = -1;
     size_t work_off = 0;
+    bool started = false;                  // its first kernels are enqueued
+    bool enqueued = false;                 // all its work and its completion events are enqueued
+    bool full = false;                     // every row is swept
+    int64_t chunk_tasks = 0;               // > 0: the full sweep runs in launches of this many tasks
+    int64_t chunk_next = 0;                // first task of the next launch
     bool done = false;
 };
 
@@ -155,9 +177,37 @@ size_t working_set(const Layout &ly)
     return 256 + align_up(sizeof(Task) * (size_t)ly.n_tasks, 256) + 2 * align_up((size_t)ly.total_rows, 256);
 }
 
+// Device bytes of a host frame's staged planes (each plane packed, rows of
+// its width) and its mask.
+size_t host_staging(int n, const ivde_camera *cams, int bit_depth, int chroma_shift, int64_t rows)
+{
+    const size_t esz = bit_depth > 8 ? 2 : 1;
+    size_t b = 0;
+    for (int v = 0; v < n; ++v) {
+        const size_t W = (size_t)cams[v].width, H = (size_t)cams[v].height;
+        const size_t cw = (W + chroma_shift) >> chroma_shift, ch = (H + chroma_shift) >> chroma_shift;
+        b += align_up(W * H * esz, 256) + 2 * align_up(cw * ch * esz, 256);
+    }
+    return b + align_up((size_t)rows, 256);
+}
+
+// Pixel-label-target evaluations of a full sweep of a rig.
+int64_t frame_evals(int n, const ivde_camera *cams, const ivde_label_range &labels, const ivde_options &opt)
+{
+    int64_t e = 0;
+    for (int c = 0; c < n; ++c) {
+        const int targets = opt.targets == IVDE_TARGETS_NEAREST_LR ? (c > 0) + (c < n - 1) : n - 1;
+        e += (int64_t)cams[c].width * cams[c].height * labels.num_labels * targets;
+    }
+    return e;
+}
+
+constexpr int64_t kDefaultChunkEvals = 4000000000LL;
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t chunk = nullptr;            // completion of the latest launch of a cut sweep
     int32_t *count_host = nullptr;         // pinned [8]: compacted tasks, cursor, rule counts
     uint64_t ticket = 0;
     bool busy = false;
@@ -169,9 +219,11 @@ struct ivde_server {
     int device = 0;
     char *arena_base = nullptr;
     Arena arena;
+    int64_t chunk_evals = kDefaultChunkEvals;   // <= 0: full sweeps in one launch
     std::vector<Slot> slots;
     std::vector<Rig> rigs;
     std::deque<uint64_t> queue;
+    std::vector<uint64_t> active;          // admitted, not all work enqueued yet; admission order
     std::map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
     std::mutex mu;
@@ -181,7 +233,12 @@ struct ivde_server {
 
     void run();
     bool try_admit(Request &r);
-    ivde_status enqueue(Request &r, Slot &sl, Rig &rig);
+    void progress();
+    ivde_status start(Request &r, Slot &sl, Rig &rig);
+    ivde_status pump(Request &r, Slot &sl, Rig &rig);
+    ivde_status finish(Request &r, Slot &sl, Rig &rig);
+    bool uncut_in_flight(uint64_t except) const;
+    void abort(Request &r, Slot &sl, ivde_status st);
     void complete(Slot &sl);
     void fail(Request &r, ivde_status st);
     bool any_busy() const
@@ -213,10 +270,15 @@ void ivde_server::run()
             }
             break;
         }
-        // completions
+        progress();
+        // completions of requests whose work is all enqueued
         bool inflight = false;
         for (Slot &sl : slots) {
             if (!sl.busy) continue;
+            if (!reqs[sl.ticket].enqueued) {
+                inflight = true;
+                continue;
+            }
             const hipError_t q = hipEventQuery(sl.done);
             if (q != hipErrorNotReady) complete(sl);   // done, or failed (status recorded)
             else inflight = true;
@@ -231,9 +293,10 @@ void ivde_server::run()
     }
 }
 
+// Reserves a slot and the working set; a host frame's planes and mask start
+// uploading at once on the slot's stream.
 bool ivde_server::try_admit(Request &r)
 {
-    Rig &rig = rigs[r.rig];
     int free_slot = -1;
     for (size_t i = 0; i < slots.size(); ++i)
         if (!slots[i].busy) {
@@ -249,20 +312,88 @@ bool ivde_server::try_admit(Request &r)
     sl.busy = true;
     sl.ticket = r.ticket;
     r.st.start_us = now_us();
-    ivde_status st = enqueue(r, sl, rig);
-    if (st != IVDE_OK) {
-        r.st.status = st;
-        // nothing may still be running from a failed enqueue: wait it out
-        (void)hipStreamSynchronize(sl.stream);
-        complete(sl);
+    active.push_back(r.ticket);
+    if (r.host) {
+        const Rig &rig = rigs[r.rig];
+        char *stage = arena_base + r.work_off + align_up(working_set(r.ly), 256);
+        hipError_t e = hipSuccess;
+        for (int v = 0; v < rig.n && e == hipSuccess; ++v) {
+            const ivde_image &h = r.host_views[v];
+            const size_t esz = h.bit_depth > 8 ? 2 : 1;
+            for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+                const int k = i ? h.chroma_shift : 0;
+                const size_t w = ((size_t)rig.cams[v].width + k) >> k, hh = ((size_t)rig.cams[v].height + k) >> k;
+                e = hipMemcpy2DAsync(stage, w * esz, h.plane[i], (size_t)h.pitch[i] * esz, w * esz, hh,
+                                     hipMemcpyHostToDevice, sl.stream);
+                r.views[v].plane[i] = stage;
+                r.views[v].pitch[i] = (int64_t)w;
+                stage += align_up(w * hh * esz, 256);
+            }
+        }
+        if (e == hipSuccess && r.host_mask) {
+            e = hipMemcpyAsync(stage, r.host_mask, (size_t)r.ly.total_rows, hipMemcpyHostToDevice, sl.stream);
+            r.mask = reinterpret_cast<const uint8_t *>(stage);
+        }
+        if (e != hipSuccess) abort(r, sl, hip_fail(e, "serve upload"));
     }
     return true;
 }
 
-ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
+// True if a request other than `except` whose work is enqueued in one piece
+// (a P frame, or a full frame too small to cut) has not completed.
+bool ivde_server::uncut_in_flight(uint64_t except) const
+{
+    for (const Slot &sl : slots) {
+        if (!sl.busy || sl.ticket == except) continue;
+        const Request &q = reqs.at(sl.ticket);
+        if (q.started && q.chunk_tasks == 0 && !q.done) return true;
+    }
+    return false;
+}
+
+// Starts admitted requests whose rig has no earlier request still being
+// enqueued, and enqueues the next launch of cut sweeps whose previous launch
+// has completed while no uncut request is in flight.
+void ivde_server::progress()
+{
+    std::vector<int> pending_rigs;   // rigs with an earlier request not all enqueued
+    for (size_t i = 0; i < active.size();) {
+        Request &r = reqs[active[i]];
+        Slot &sl = slots[r.slot];
+        Rig &rig = rigs[r.rig];
+        const bool after_pending =
+            std::find(pending_rigs.begin(), pending_rigs.end(), r.rig) != pending_rigs.end();
+        if (!r.enqueued && !r.started && !after_pending) {
+            const ivde_status st = start(r, sl, rig);
+            if (st != IVDE_OK) abort(r, sl, st);
+        } else if (!r.enqueued && r.started && hipEventQuery(sl.chunk) != hipErrorNotReady &&
+                   !uncut_in_flight(r.ticket)) {
+            const ivde_status st = pump(r, sl, rig);
+            if (st != IVDE_OK) abort(r, sl, st);
+        }
+        if (r.enqueued) {
+            active.erase(active.begin() + (std::ptrdiff_t)i);
+        } else {
+            pending_rigs.push_back(r.rig);
+            ++i;
+        }
+    }
+}
+
+// A request whose enqueue failed: nothing of it may still run when its
+// memory is released.
+void ivde_server::abort(Request &r, Slot &sl, ivde_status st)
+{
+    r.st.status = st;
+    (void)hipStreamSynchronize(sl.stream);
+    r.started = r.enqueued = true;
+}
+
+ivde_status ivde_server::start(Request &r, Slot &sl, Rig &rig)
 {
     hipStream_t s = sl.stream;
     hipError_t e;
+    r.started = true;
     if (rig.last_valid && (e = hipStreamWaitEvent(s, rig.last, 0)) != hipSuccess) return hip_fail(e, "rig order");
     char *ws = rig.ws;
     const Layout &ly = r.ly;
@@ -284,24 +415,20 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
     uint8_t *rule_mask = source + align_up((size_t)ly.total_rows, 256);
     float *mean = reinterpret_cast<float *>(ws + ly.off_mean);
     const size_t mean_bytes = (size_t)ly.total_rows * 16;
-    const bool full = r.rule ? (r.iframe || !rig.has_prev || !rig.has_i) : (!r.mask || !rig.has_prev);
+    r.full = r.rule ? (r.iframe || !rig.has_prev || !rig.has_i) : (!r.mask || !rig.has_prev);
     const uint8_t *mask = r.mask;
     for (int k = 0; k < 8; ++k) sl.count_host[k] = 0;
     if (r.rule && (e = launch_segment_stats(dp, extents_of(ly), nullptr, s)) != hipSuccess)
         return hip_fail(e, "serve segment statistics");
-    if (full) {
+    if (r.full) {
+        sl.count_host[0] = (int32_t)ly.n_tasks;
+        const int64_t evals = frame_evals(rig.n, rig.cams.data(), rig.labels, rig.opt);
+        const int64_t pieces = chunk_evals > 0 ? (evals + chunk_evals - 1) / chunk_evals : 1;
+        r.chunk_tasks = pieces > 1 && ly.n_tasks > 1 ? (ly.n_tasks + pieces - 1) / pieces : 0;
+        if (r.chunk_tasks > 0) return pump(r, sl, rig);
         if ((e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, bil, ly.tex_f32, ly.f16, ly.wpg, counters + 8, s)) !=
             hipSuccess)
             return hip_fail(e, "serve sweep");
-        sl.count_host[0] = (int32_t)ly.n_tasks;
-        if (r.rule) {
-            // this frame becomes the I frame of the rule
-            if ((e = launch_copy_rows(rig.cost, rig.cost_i, (int64_t)rig.cost_bytes, s)) != hipSuccess ||
-                (e = launch_copy_rows(mean, rig.mean_i, (int64_t)mean_bytes, s)) != hipSuccess ||
-                (e = launch_copy_rows(mean, rig.mean_prev, (int64_t)mean_bytes, s)) != hipSuccess)
-                return hip_fail(e, "serve I frame state");
-            rig.has_i = true;
-        }
     } else {
         if ((e = launch_fill_i32(counters, 0, 8 + kXcds, s)) != hipSuccess) return hip_fail(e, "serve counters");
         if (r.rule) {
@@ -332,6 +459,42 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
         if (r.rule && (e = launch_copy_rows(mean, rig.mean_prev, (int64_t)mean_bytes, s)) != hipSuccess)
             return hip_fail(e, "serve mean colours");
     }
+    return finish(r, sl, rig);
+}
+
+// The next launch of a cut full sweep; after the last one, the frame's tail.
+ivde_status ivde_server::pump(Request &r, Slot &sl, Rig &rig)
+{
+    const Layout &ly = r.ly;
+    const Problem *dp = reinterpret_cast<const Problem *>(rig.ws + ly.off_problem);
+    const Task *tasks = reinterpret_cast<const Task *>(rig.ws + ly.off_tasks);
+    int32_t *counters = reinterpret_cast<int32_t *>(arena_base + r.work_off);
+    const int64_t n = std::min(r.chunk_tasks, ly.n_tasks - r.chunk_next);
+    hipError_t e = launch_sweep(dp, tasks + r.chunk_next, n, ly.J, rig.opt.sampling == IVDE_BILINEAR, ly.tex_f32,
+                                ly.f16, ly.wpg, counters + 8, sl.stream);
+    if (e != hipSuccess) return hip_fail(e, "serve sweep");
+    r.chunk_next += n;
+    if ((e = hipEventRecord(sl.chunk, sl.stream)) != hipSuccess) return hip_fail(e, "serve event");
+    return r.chunk_next >= ly.n_tasks ? finish(r, sl, rig) : IVDE_OK;
+}
+
+// The frame's work after its sweep: the I-frame state of the rule, argmin,
+// the copy out, and the completion events.
+ivde_status ivde_server::finish(Request &r, Slot &sl, Rig &rig)
+{
+    hipStream_t s = sl.stream;
+    hipError_t e;
+    const Layout &ly = r.ly;
+    if (r.full && r.rule) {
+        // this frame becomes the I frame of the rule
+        float *mean = reinterpret_cast<float *>(rig.ws + ly.off_mean);
+        const int64_t mean_bytes = ly.total_rows * 16;
+        if ((e = launch_copy_rows(rig.cost, rig.cost_i, (int64_t)rig.cost_bytes, s)) != hipSuccess ||
+            (e = launch_copy_rows(mean, rig.mean_i, mean_bytes, s)) != hipSuccess ||
+            (e = launch_copy_rows(mean, rig.mean_prev, mean_bytes, s)) != hipSuccess)
+            return hip_fail(e, "serve I frame state");
+        rig.has_i = true;
+    }
     if (r.label_out &&
         (e = launch_argmin(rig.cost, ly.f16, ly.total_rows, rig.labels.num_labels, r.label_out, s)) != hipSuccess)
         return hip_fail(e, "serve argmin");
@@ -342,6 +505,7 @@ ivde_status ivde_server::enqueue(Request &r, Slot &sl, Rig &rig)
     rig.last_valid = true;
     rig.has_prev = true;
     r.st.rows_total = ly.total_rows;
+    r.enqueued = true;
     return IVDE_OK;
 }
 
@@ -382,6 +546,10 @@ ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out)
         set_error("server: need an arena, at least 256 bytes, and 1..16 slots");
         return IVDE_EINVAL;
     }
+    if (cfg->reserved != 0) {
+        set_error("server: the reserved field must be 0");
+        return IVDE_EINVAL;
+    }
     if (reinterpret_cast<uintptr_t>(cfg->arena) % 256) {
         set_error("server: the arena must be 256-byte aligned");
         return IVDE_EINVAL;
@@ -399,10 +567,12 @@ ivde_status ivde_server_create(const ivde_server_config *cfg, ivde_server **out)
     }
     s->arena_base = static_cast<char *>(cfg->arena);
     s->arena.init(cfg->arena_bytes);
+    s->chunk_evals = cfg->chunk_evals == 0 ? kDefaultChunkEvals : cfg->chunk_evals;
     s->slots.resize(cfg->max_slots);
     for (Slot &sl : s->slots) {
         if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.chunk, hipEventDisableTiming)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void **>(&sl.count_host), 8 * sizeof(int32_t), hipHostMallocDefault)) !=
                 hipSuccess) {
             ivde_server_destroy(s);
@@ -475,16 +645,21 @@ ivde_status ivde_rig_register(ivde_server *srv, int32_t n_views, const ivde_came
 }
 
 static ivde_status submit(ivde_server *srv, int32_t rig_id, const ivde_image *views, const uint8_t *changed_mask,
-                          bool rule, bool iframe, void *cost_out, int32_t *label_out, uint64_t *ticket);
+                          bool rule, bool iframe, bool host, void *cost_out, int32_t *label_out, uint64_t *ticket);
 
 ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
                                   const ivde_label_range *labels, const ivde_options *opt, int32_t bit_depth,
-                                  size_t *resident, size_t *per_request)
+                                  int32_t chroma_shift, size_t *resident, size_t *per_request,
+                                  size_t *per_host_request)
 {
     ivde_status st = validate_problem(n_views, cams, nullptr, segs, labels, opt, false);
     if (st != IVDE_OK) return st;
     if (bit_depth < 8 || bit_depth > 16) {
         set_error("bit_depth must be 8..16");
+        return IVDE_EINVAL;
+    }
+    if (chroma_shift != 0 && chroma_shift != 1) {
+        set_error("chroma_shift must be 0 or 1");
         return IVDE_EINVAL;
     }
     ivde_options o = *opt;
@@ -494,19 +669,38 @@ ivde_status ivde_server_footprint(int32_t n_views, const ivde_camera *cams, cons
     const Layout ly = plan_layout(n_views, cams, segs, labels, &o, bit_depth);
     if (resident) *resident = align_up(resident_bytes(n_views, cams, big, nullptr, nullptr), 256);
     if (per_request) *per_request = align_up(working_set(ly), 256);
+    if (per_host_request)
+        *per_host_request = align_up(working_set(ly), 256) +
+                            align_up(host_staging(n_views, cams, bit_depth, chroma_shift, ly.total_rows), 256);
     return IVDE_OK;
 }
 
 ivde_status ivde_stream_submit(ivde_server *srv, int32_t rig_id, const ivde_image *views, const uint8_t *changed_mask,
                                void *cost_out, int32_t *label_out, uint64_t *ticket)
 {
-    return submit(srv, rig_id, views, changed_mask, false, false, cost_out, label_out, ticket);
+    return submit(srv, rig_id, views, changed_mask, false, false, false, cost_out, label_out, ticket);
 }
 
 ivde_status ivde_stream_submit_rule(ivde_server *srv, int32_t rig_id, const ivde_image *views, int32_t iframe,
                                     void *cost_out, int32_t *label_out, uint64_t *ticket)
 {
-    return submit(srv, rig_id, views, nullptr, true, iframe != 0, cost_out, label_out, ticket);
+    return submit(srv, rig_id, views, nullptr, true, iframe != 0, false, cost_out, label_out, ticket);
+}
+
+ivde_status ivde_stream_submit_host(ivde_server *srv, int32_t rig_id, const ivde_image *host_views, int32_t mode,
+                                    const uint8_t *changed_mask, void *cost_out, int32_t *label_out,
+                                    uint64_t *ticket)
+{
+    if (mode != IVDE_SUBMIT_MASK && mode != IVDE_SUBMIT_RULE && mode != IVDE_SUBMIT_RULE_IFRAME) {
+        set_error("stream_submit_host: unknown mode %d", mode);
+        return IVDE_EINVAL;
+    }
+    if (mode != IVDE_SUBMIT_MASK && changed_mask) {
+        set_error("stream_submit_host: the rule modes take no mask");
+        return IVDE_EINVAL;
+    }
+    return submit(srv, rig_id, host_views, changed_mask, mode != IVDE_SUBMIT_MASK, mode == IVDE_SUBMIT_RULE_IFRAME,
+                  true, cost_out, label_out, ticket);
 }
 
 ivde_status ivde_rig_set_temporal(ivde_server *srv, int32_t rig_id, float t_p, float t_i)
@@ -528,7 +722,7 @@ ivde_status ivde_rig_set_temporal(ivde_server *srv, int32_t rig_id, float t_p, f
 }  // extern "C"
 
 static ivde_status submit(ivde_server *srv, int32_t rig_id, const ivde_image *views, const uint8_t *changed_mask,
-                          bool rule, bool iframe, void *cost_out, int32_t *label_out, uint64_t *ticket)
+                          bool rule, bool iframe, bool host, void *cost_out, int32_t *label_out, uint64_t *ticket)
 {
     if (!srv || !views || !ticket) {
         set_error("stream_submit: null argument");
@@ -545,6 +739,9 @@ static ivde_status submit(ivde_server *srv, int32_t rig_id, const ivde_image *vi
     Request r;
     r.ly = plan_layout(rig.n, rig.cams.data(), rig.segs.data(), &rig.labels, &rig.opt, views[0].bit_depth);
     r.work_bytes = working_set(r.ly);
+    if (host)
+        r.work_bytes = align_up(r.work_bytes, 256) + host_staging(rig.n, rig.cams.data(), views[0].bit_depth,
+                                                                  views[0].chroma_shift, r.ly.total_rows);
     // with nothing queued or in flight the free space cannot grow: refuse now
     if (r.work_bytes > srv->arena.largest() && srv->queue.empty() && !srv->any_busy()) {
         set_error("stream_submit: the request's working set (%zu bytes) can never fit the arena", r.work_bytes);
@@ -553,7 +750,13 @@ static ivde_status submit(ivde_server *srv, int32_t rig_id, const ivde_image *vi
     r.ticket = srv->next_ticket++;
     r.rig = rig_id;
     r.views.assign(views, views + rig.n);
-    r.mask = changed_mask;
+    r.host = host;
+    if (host) {
+        r.host_views = r.views;
+        r.host_mask = changed_mask;
+    } else {
+        r.mask = changed_mask;
+    }
     r.rule = rule;
     r.iframe = iframe;
     r.cost_out = cost_out;
@@ -660,6 +863,7 @@ void ivde_server_destroy(ivde_server *srv)
     for (Slot &sl : srv->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.chunk) (void)hipEventDestroy(sl.chunk);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.count_host) (void)hipHostFree(sl.count_host);
     }

@@ -7,6 +7,8 @@ if libivde.so is missing or no GPU is present, calls raise.
 from __future__ import annotations
 
 import ctypes
+import json
+import math
 import os
 
 import numpy as np
@@ -20,6 +22,7 @@ REF_RIG_CENTER, REF_OWN = -1, -2
 NEAREST, BILINEAR = 0, 1
 F32, F16 = 0, 1
 TARGETS_ALL, TARGETS_NEAREST_LR, TARGETS_EXPLICIT = 0, 1, 2
+SUBMIT_MASK, SUBMIT_RULE, SUBMIT_RULE_IFRAME = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20     # IVDE_NOALLOC_SCRATCH_BYTES
 
 
@@ -61,7 +64,8 @@ class Frame(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32)]
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("chunk_evals", ctypes.c_int64)]
 
 
 class FrameStats(ctypes.Structure):
@@ -104,7 +108,8 @@ SIGNATURES = {
     "ivde_server_destroy": (None, [_P]),
     "ivde_autotune": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _I32, _P, _P, _I32]),
     "ivde_stream_submit_rule": (_I32, [_P, _I32, _P, _I32, _P, _P, _P]),
-    "ivde_server_footprint": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P]),
+    "ivde_server_footprint": (_I32, [_I32, _P, _P, _P, _P, _I32, _I32, _P, _P, _P]),
+    "ivde_stream_submit_host": (_I32, [_P, _I32, _P, _I32, _P, _P, _P, _P]),
     "ivde_rig_set_temporal": (_I32, [_P, _I32, ctypes.c_float, ctypes.c_float]),
     "ivde_segment_stats_size": (_I32, [_I32, _P, _P, _I32, _P]),
     "ivde_segment_stats": (_I32, [_I32, _P, _P, _P, _P, _SZ, _P, _P, _P, _P]),
@@ -396,21 +401,49 @@ class Batch:
 
 
 # ---------------------------------------------------------------- serving form
-def server_footprint(dv: DeviceViews, lr: LabelRange, opt: Options):
-    """(resident bytes, per-request bytes) a rig needs in a server arena."""
-    r, q = ctypes.c_size_t(), ctypes.c_size_t()
+def server_footprint(dv: DeviceViews, lr: LabelRange, opt: Options, host=False):
+    """(resident bytes, per-request bytes) a rig needs in a server arena;
+    host=True: per-request bytes of a frame handed over in host memory."""
+    r, q, qh = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     check(load().ivde_server_footprint(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt), dv.bit_depth,
-                                       ctypes.byref(r), ctypes.byref(q)))
-    return r.value, q.value
+                                       dv.chroma_shift, ctypes.byref(r), ctypes.byref(q), ctypes.byref(qh)))
+    return r.value, (qh.value if host else q.value)
+
+
+class HostFrame:
+    """One frame's planes in pinned host memory (as a camera rig delivers
+    them) and the C descriptors pointing at them, for Server.submit_host."""
+
+    def __init__(self, n, Y, U, V, bit_depth, chroma_shift, mask=None):
+        torch = _torch()
+        self.n = int(n)
+        self.bit_depth, self.chroma_shift = int(bit_depth), int(chroma_shift)
+
+        def pin(a):
+            a = np.ascontiguousarray(a)
+            if a.dtype == np.uint16:
+                a = a.view(np.int16)
+            return torch.from_numpy(a).pin_memory()
+
+        self.planes = [[pin(a) for a in (y, u, v)] for y, u, v in zip(Y, U, V)]
+        self.mask = None if mask is None else pin(np.ascontiguousarray(mask, np.uint8))
+        self.c_images = (Image * self.n)()
+        for i in range(self.n):
+            for p, t in enumerate(self.planes[i]):
+                self.c_images[i].plane[p] = t.data_ptr()
+                self.c_images[i].pitch[p] = t.shape[1]
+            self.c_images[i].bit_depth, self.c_images[i].chroma_shift = self.bit_depth, self.chroma_shift
 
 
 class Server:
     """ivde_server over a torch-allocated arena (its size is the budget)."""
 
-    def __init__(self, arena_bytes, max_slots=4):
+    def __init__(self, arena_bytes, max_slots=4, chunk_evals=0):
+        """chunk_evals: evaluations per launch of a full-frame sweep (0: the
+        library's default, < 0: one launch)."""
         lib = load()
         self.arena = alloc_bytes(arena_bytes)
-        cfg = ServerConfig(self.arena.data_ptr(), self.arena.numel(), int(max_slots))
+        cfg = ServerConfig(self.arena.data_ptr(), self.arena.numel(), int(max_slots), 0, int(chunk_evals))
         h = ctypes.c_void_p()
         check(lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
@@ -447,6 +480,23 @@ class Server:
                                         ctypes.c_void_p(label_out.data_ptr()) if label_out is not None else None,
                                         ctypes.byref(t)))
         self._inflight[t.value] = (images, mask, cost_out, label_out)   # keep alive
+        return t.value
+
+    def submit_host(self, rig: int, frame: HostFrame, mode=SUBMIT_MASK, cost_out=None, label_out=None) -> int:
+        """A frame in host memory (HostFrame); the server uploads it.  mode
+        SUBMIT_MASK uses frame.mask (None: every row), SUBMIT_RULE and
+        SUBMIT_RULE_IFRAME the temporal rule."""
+        self._check_outputs(rig, cost_out, label_out)
+        mask = frame.mask if mode == SUBMIT_MASK else None
+        if mask is not None and rig in self._rigs and mask.numel() != self._rigs[rig][1]:
+            raise ValueError(f"mask: expected {self._rigs[rig][1]} rows, got {mask.numel()}")
+        t = ctypes.c_uint64(0)
+        check(load().ivde_stream_submit_host(
+            self.handle, int(rig), frame.c_images, int(mode),
+            ctypes.c_void_p(mask.data_ptr()) if mask is not None else None,
+            ctypes.c_void_p(cost_out.data_ptr()) if cost_out is not None else None,
+            ctypes.c_void_p(label_out.data_ptr()) if label_out is not None else None, ctypes.byref(t)))
+        self._inflight[t.value] = (frame, cost_out, label_out)   # keep the host buffers alive
         return t.value
 
     def submit_rule(self, rig: int, images, iframe=False, cost_out=None, label_out=None) -> int:
@@ -532,6 +582,56 @@ def autotune(dv: DeviceViews, lr: LabelRange, opt: Options, reps=2, stream=None)
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
                             _stream_ptr(stream), int(reps), ctypes.byref(best), times, len(AUTOTUNE_SHAPES)))
     table = {s: (float(t) if t >= 0 else None) for s, t in zip(AUTOTUNE_SHAPES, times)}
+    return best, table
+
+
+def shape_class(dv: DeviceViews, lr: LabelRange, opt: Options) -> str:
+    """The class of problems that share a tuned launch shape: what the
+    sweep's speed depends on.  Sampling, storage type, texel format (images
+    up to 11 bits pack into FP16 texels), levels rounded up to a 64-level
+    block, pixels per segment to the nearest power of two (per-task overhead
+    against per-pixel work), and targets per view."""
+    npx = sum(c.width * c.height for c in dv.cams)
+    px = npx / max(1, sum(dv.S))
+    if opt.targets == TARGETS_NEAREST_LR:
+        tg = 2 if dv.n > 2 else 1
+    elif opt.targets == TARGETS_EXPLICIT:
+        tg = "x"
+    else:
+        tg = dv.n - 1
+    return (f"{'bil' if opt.sampling == BILINEAR else 'nn'}-{'f16' if opt.cost_dtype == F16 else 'f32'}"
+            f"-tex{'16' if dv.bit_depth <= 11 else '32'}-L{(lr.num_labels + 63) // 64 * 64}"
+            f"-px{2 ** int(round(math.log2(max(px, 1.0))))}-t{tg}")
+
+
+_TUNE_MEMO = {}
+
+
+def autotune_cached(dv: DeviceViews, lr: LabelRange, opt: Options, cache_path=None, reps=2, stream=None):
+    """The launch shape for this problem's shape class: from the cache (a
+    JSON file at cache_path, or this process's memory if None) when the
+    class has been tuned, else tuned now on this problem by ivde_autotune
+    and stored.  Returns (Options, the timing table or None if cached)."""
+    key = shape_class(dv, lr, opt)
+    cache = _TUNE_MEMO
+    if cache_path is not None:
+        try:
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        except FileNotFoundError:
+            cache = {}
+    hit = cache.get(key)
+    if hit is not None:
+        return options(opt.sampling, opt.cost_dtype, opt.targets, getattr(opt, "_mask", None),
+                       labels_per_lane=hit["labels_per_lane"], waves_per_group=hit["waves_per_group"]), None
+    best, table = autotune(dv, lr, opt, reps=reps, stream=stream)
+    cache[key] = {"labels_per_lane": best.labels_per_lane, "waves_per_group": best.waves_per_group,
+                  "us": {f"{k[0]}x{k[1]}": v for k, v in table.items()}}
+    if cache_path is not None:
+        tmp = f"{cache_path}.tmp{os.getpid()}"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
     return best, table
 
 

@@ -182,8 +182,20 @@ def test_batch_and_server_argument_checks(lib):
     assert lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ivde.IVDE_EINVAL
     cfg = ivde.ServerConfig(0x10000, 1 << 20, 99)
     assert lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ivde.IVDE_EINVAL
+    cfg = ivde.ServerConfig(0x10000, 1 << 20, 2, 1, 0)     # reserved must be 0
+    assert lib.ivde_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ivde.IVDE_EINVAL
     st = ivde.FrameStats()
     assert lib.ivde_stream_poll(None, 1, ctypes.byref(st)) == ivde.IVDE_EINVAL
+    t = ctypes.c_uint64()
+    imgs = _imgs(2, 16)
+    for mode in (ivde.SUBMIT_MASK, ivde.SUBMIT_RULE, ivde.SUBMIT_RULE_IFRAME):
+        assert lib.ivde_stream_submit_host(None, 0, imgs, mode, None, None, None, ctypes.byref(t)) == ivde.IVDE_EINVAL
+    # unknown mode, and a mask with a rule mode, are refused before the server is looked at
+    assert lib.ivde_stream_submit_host(None, 0, imgs, 7, None, None, None, ctypes.byref(t)) == ivde.IVDE_EINVAL
+    mask = (ctypes.c_uint8 * 8)()
+    assert lib.ivde_stream_submit_host(None, 0, imgs, ivde.SUBMIT_RULE, mask, None, None,
+                                       ctypes.byref(t)) == ivde.IVDE_EINVAL
+    assert b"mask" in lib.ivde_last_error()
     assert lib.ivde_batch_run(None, None, 0) == ivde.IVDE_EINVAL
 
 
@@ -256,14 +268,20 @@ def test_depth_map_and_footprint_argument_checks(lib):
     assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), big, ctypes.c_void_p(0x100002), 4 * L, big,
                               None) == ivde.IVDE_EINVAL
     assert lib.ivde_depth_map(n, cams, segs, ctypes.byref(lr), big, big, 4 * L - 4, big, None) == ivde.IVDE_ENOMEM
-    r, q = ctypes.c_size_t(), ctypes.c_size_t()
+    r, q, qh = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     opt = ivde.options(ivde.BILINEAR, ivde.F16)
-    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, ctypes.byref(r),
-                                     ctypes.byref(q)) == ivde.IVDE_OK
+    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, 1, ctypes.byref(r),
+                                     ctypes.byref(q), ctypes.byref(qh)) == ivde.IVDE_OK
     # resident holds two FP16 volumes, the maps and a workspace; a frame holds at least its counters
     assert r.value > 2 * n * S * L * 2 + n * w * h * 4 and q.value >= 256
-    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 20, ctypes.byref(r),
-                                     ctypes.byref(q)) == ivde.IVDE_EINVAL
+    # a host frame also holds its staged planes (2-byte Y and two 4:2:0 chroma planes per view) and mask
+    assert qh.value >= q.value + n * (w * h * 2 + 2 * (w // 2) * (h // 2) * 2) + n * S
+    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, 0, None, None,
+                                     None) == ivde.IVDE_OK
+    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 20, 1, ctypes.byref(r),
+                                     ctypes.byref(q), None) == ivde.IVDE_EINVAL
+    assert lib.ivde_server_footprint(n, cams, segs, ctypes.byref(lr), ctypes.byref(opt), 10, 2, ctypes.byref(r),
+                                     ctypes.byref(q), None) == ivde.IVDE_EINVAL
 
 
 def test_binding_rejects_tensors_the_library_would_misread():
