@@ -229,7 +229,7 @@ def bench_plain(args):
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
     base = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=args.labels_per_lane,
-                        waves_per_group=args.waves_per_group)
+                        waves_per_group=args.waves_per_group, pixels_per_step=args.pixels_per_step)
     cb, wb = ivde.sizes(dv, lr, base)
     ws = ivde.alloc_bytes(wb)
     cost = torch.empty((dv.rows, wl.num_labels), dtype=torch.float32, device="cuda")
@@ -238,7 +238,8 @@ def bench_plain(args):
     step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     sweep_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     opts = [ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=args.labels_per_lane,
-                         waves_per_group=args.waves_per_group, sweep_events=e) for e in sweep_ev]
+                         waves_per_group=args.waves_per_group, sweep_events=e,
+                         pixels_per_step=args.pixels_per_step) for e in sweep_ev]
     stream = torch.cuda.current_stream()
 
     def step(opt):
@@ -471,13 +472,19 @@ def main():
     ap.add_argument("--threads", type=int, default=0, help="depth: host threads (default min(16, cores))")
     ap.add_argument("--rule", action="store_true",
                     help="served: the GPU derives each P frame's rows from the temporal rule instead of a mask")
-    ap.add_argument("--chunk-evals", type=int, default=0,
-                    help="served: evaluations per launch of a full-frame sweep (0: library default, <0: one launch)")
+    ap.add_argument("--chunk-evals", default="0",
+                    help="served: evaluations per launch of a full-frame sweep (0: library default, <0: one "
+                         "launch); a comma-separated list runs the temporal pass once per value")
     ap.add_argument("--no-uncut", action="store_true",
                     help="served: skip the comparison run with full sweeps in one launch")
     ap.add_argument("--device-frames", action="store_true",
                     help="served: frames resident on the device before submission (no upload in the latency)")
     ap.add_argument("--served-frames", type=int, default=6, help="served: distinct frames per rig")
+    ap.add_argument("--shape-segments", default="5000,10000,20000,40000", help="shapes: segments per view")
+    ap.add_argument("--shape-labels", default="128,256", help="shapes: level counts")
+    ap.add_argument("--no-tune", action="store_true", help="shapes: the default launch shape only")
+    ap.add_argument("--compare-px", action="store_true", help="shapes: also time the pixel-pair sweep")
+    ap.add_argument("--pixels-per-step", type=int, default=0, help="plain: 1 one-pixel sweep, 2 pixel pairs")
     ap.add_argument("--tune-cache", default=None,
                     help="batched, shapes: JSON file caching tuned launch shapes per shape class "
                          "(default: kept in memory for this run)")

@@ -127,9 +127,15 @@ typedef struct {
 
 /* Options.  labels_per_lane (1, 2, 4 or 8) and waves_per_group (1, 2 or 4)
  * are launch-shape knobs; 0 picks the tuned default.  They never change a
- * result.  sweep_events, if both non-NULL, are hipEvent_t handles the call
- * records on its stream immediately before and after the sweep kernel (for
- * timing that kernel alone). */
+ * result.  pixels_per_step 2 runs the pixel-pair sweep (each wave step two
+ * pixels at 32 levels instead of one pixel at 64: half the epipolar span
+ * per gather); it exists for one label per lane and images of up to 11
+ * bits, elsewhere the one-pixel sweep runs; 0 picks the default, 1 the
+ * one-pixel sweep.  Both sweeps compute the same quantity but add a
+ * segment's pixels in a different order, so their FP32 results may differ
+ * in the last bits.  sweep_events, if both non-NULL, are hipEvent_t handles
+ * the call records on its stream immediately before and after the sweep
+ * kernel (for timing that kernel alone). */
 typedef struct {
     int32_t sampling;         /* IVDE_NEAREST or IVDE_BILINEAR */
     int32_t cost_dtype;       /* IVDE_F32 or IVDE_F16 storage */
@@ -138,6 +144,7 @@ typedef struct {
     int32_t labels_per_lane;
     int32_t waves_per_group;
     void *sweep_events[2];
+    int32_t pixels_per_step;  /* 0, 1 or 2 */
 } ivde_options;
 
 /* ---------------------------------------------------------------- plain form */
@@ -510,11 +517,14 @@ ivde_status ivde_optimize(const ivde_energy *energy, int32_t n_threads, int32_t 
 
 /* ---------------------------------------------------------------- tuning */
 
-/* Times every (labels_per_lane, waves_per_group) launch shape on the given
- * problem (which must already be valid for ivde_cost_volume) and writes the
- * fastest into *opt_out.  Each candidate runs `reps` times; times in
- * microseconds go to times_us[i] for candidate i if not NULL (capacity
- * max_times).  Synchronises `stream`. */
+/* Times every (labels_per_lane, waves_per_group, pixels_per_step) launch
+ * shape on the given problem (which must already be valid for
+ * ivde_cost_volume) and writes the fastest into *opt_out.  The 15
+ * candidates, in order: labels per lane 1, 2, 4, 8 x waves per group 1, 2, 4
+ * with one pixel per step, then one label per lane x waves per group 1, 2, 4
+ * with pixel pairs (skipped, time -1, where that sweep does not exist).
+ * Each candidate runs `reps` times; times in microseconds go to times_us[i]
+ * for candidate i if not NULL (capacity max_times).  Synchronises `stream`. */
 ivde_status ivde_autotune(int32_t n_views, const ivde_camera *cams, const ivde_image *views,
                           const ivde_segmentation *segs, const ivde_label_range *labels,
                           const ivde_options *opt, void *workspace, size_t workspace_bytes,

@@ -52,12 +52,12 @@ def _batch_case(wls, args):
     shapes, table = {}, {}
     for key, members in classes.items():
         o, t = ivde.autotune_cached(dvs[members[0]], lrs[members[0]], base, args.tune_cache, reps=1)
-        shapes[key] = (o.labels_per_lane, o.waves_per_group)
+        shapes[key] = (o.labels_per_lane, o.waves_per_group, o.pixels_per_step)
         table[key] = t
     weight = {k: sum(_evals(wls[i]) for i in m) for k, m in classes.items()}
     main_class = max(weight, key=weight.get)
     tuned = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=shapes[main_class][0],
-                         waves_per_group=shapes[main_class][1])
+                         waves_per_group=shapes[main_class][1], pixels_per_step=shapes[main_class][2])
     _log(f"shape classes {shapes}; batch shape {shapes[main_class]} from {main_class}")
     opt = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=tuned.labels_per_lane,
                        waves_per_group=tuned.waves_per_group)
@@ -137,7 +137,7 @@ def _batch_case(wls, args):
                    "launch_shape": {"labels_per_lane": tuned.labels_per_lane,
                                     "waves_per_group": tuned.waves_per_group, "from_class": main_class},
                    "shape_classes": {k: {"frames": len(classes[k]), "shape": shapes[k],
-                                         "autotune_us": ({f"{a[0]}x{a[1]}": v for a, v in table[k].items()}
+                                         "autotune_us": ({"x".join(map(str, a)): v for a, v in table[k].items()}
                                                          if table[k] else "cached")} for k in classes}},
         "per_frame_sweep": per_frame,
         "sweep_rate_by_labels": groups,
@@ -349,14 +349,20 @@ def bench_served(args):
                                                    "p99_ms": _pct(tied, 99)}
         return out
 
-    _log("temporal run, cut full sweeps")
-    tmp = run(True, args.chunk_evals)
+    chunks = [int(float(c)) for c in str(args.chunk_evals).split(",")]
+    _log(f"temporal run, cut full sweeps ({chunks[0] or 'default'} evaluations per launch)")
+    tmp = run(True, chunks[0])
+    by_chunk = {}
+    for c in chunks[1:]:
+        _log(f"temporal run, {c} evaluations per launch")
+        r = run(True, c)
+        by_chunk[str(c)] = {k: r[k] for k in ("latency_ms", "p_frames", "i_frames", "frames_per_s") if k in r}
     uncut = None
     if args.gop > 0 and not args.no_uncut:
         _log("temporal run, full sweeps in one launch")
         uncut = run(True, -1)
     _log("full-recompute run")
-    full = run(False, args.chunk_evals)
+    full = run(False, chunks[0])
     demand_full = sum(_evals(wl) for _, wl, _ in rigs) / len(rigs) * rate
     return {
         "metric": "pixel·label·view cost evals/s + %HBM roofline; p50/p99 frame latency",
@@ -367,7 +373,7 @@ def bench_served(args):
                                "C (10x2048x1088, 256); YUV420 10-bit, bilinear, FP16 costs, 80 GB arena",
                    "seconds": duration, "slots": args.slots, "gop": args.gop,
                    "distinct_frames_per_rig": n_cycle,
-                   "chunk_evals": args.chunk_evals or "library default (4e9)",
+                   "chunk_evals": chunks[0] or "library default (4e9)",
                    "mask": "temporal rule on the GPU (T_P = 3, T_I = 1)" if rule else "changed-segment mask input",
                    "protocol": "each rig's first (I) frame is computed before the arrival clock; " +
                                ("frames in pinned host memory, uploaded by the server on the request's stream; "
@@ -377,6 +383,7 @@ def bench_served(args):
         "latency_ms": tmp["latency_ms"],
         "temporal": tmp,
         "temporal_uncut_sweeps": uncut,
+        "temporal_other_chunk_sizes": by_chunk,
         "full_recompute": full,
         "load_factor_full": demand_full / max(full["swept_evals_per_s"], 1.0),
     }
@@ -394,21 +401,32 @@ def bench_shapes(args):
     rows = []
     cache = args.tune_cache
     stream = torch.cuda.current_stream()
-    for S in (5000, 10000, 20000, 40000):
+    seg_list = [int(x) for x in args.shape_segments.split(",")]
+    lab_list = [int(x) for x in args.shape_labels.split(",")]
+    for S in seg_list:
         t0 = time.perf_counter()
         wl = synth.make_arc_workload(f"shapes-S{S}", synth.SEED_BATCH + 5, n_segments=S, num_labels=256)
         dv = ivde.DeviceViews.from_workload(wl)
         _log(f"S={S}: generated in {time.perf_counter() - t0:.1f} s, {dv.rows} rows")
-        for L in (128, 256):
+        for L in lab_list:
             lr = ivde.label_range(wl.z_near, wl.z_far, L)
             base = ivde.options(ivde.BILINEAR, ivde.F32)
-            tuned, table = ivde.autotune_cached(dv, lr, base, cache, reps=2)
+            if args.no_tune:
+                tuned, table = base, None
+            else:
+                tuned, table = ivde.autotune_cached(dv, lr, base, cache, reps=2)
             res = {}
-            for name, o in (("j1", base), ("tuned", tuned)):
+            variants = [("j1", base)]
+            if not args.no_tune:
+                variants.append(("tuned", tuned))
+            if args.compare_px:
+                variants.append(("pairs", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=2)))
+            for name, o in variants:
                 ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                       for _ in range(args.steps)]
                 opts = [ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=o.labels_per_lane,
-                                     waves_per_group=o.waves_per_group, sweep_events=e) for e in ev]
+                                     waves_per_group=o.waves_per_group, sweep_events=e,
+                                     pixels_per_step=o.pixels_per_step) for e in ev]
                 C, ws = ivde.cost_volume(dv, lr, opts[0])
                 torch.cuda.synchronize()
                 for op in opts:
@@ -417,13 +435,17 @@ def bench_shapes(args):
                 ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
                 evals = sum(c.width * c.height for c in wl.cams) * L * (wl.n_views - 1)
                 res[name] = {"sweep_ms": ms, "evals_per_s": evals / (ms / 1e3),
-                             "labels_per_lane": o.labels_per_lane or 1, "waves_per_group": o.waves_per_group}
+                             "labels_per_lane": o.labels_per_lane or 1, "waves_per_group": o.waves_per_group,
+                             "pixels_per_step": o.pixels_per_step}
             row = {"segments_per_view": S, "labels": L, "pixels_per_segment": 1920 * 1080 / S,
                    "class": ivde.shape_class(dv, lr, base), **res,
-                   "autotune_us": {f"{k[0]}x{k[1]}": v for k, v in table.items()} if table else None}
-            _log(f"S={S} L={L}: {res['j1']['sweep_ms']:.2f} ms, {res['j1']['evals_per_s']:.3g} evals/s "
-                 f"(tuned {res['tuned']['labels_per_lane']}x{res['tuned']['waves_per_group']}: "
-                 f"{res['tuned']['sweep_ms']:.2f} ms)")
+                   "autotune_us": {"x".join(map(str, k)): v for k, v in table.items()} if table else None}
+            if "pairs" in res:
+                _log(f"S={S} L={L}: pixel pairs {res['pairs']['sweep_ms']:.2f} ms, "
+                     f"{res['pairs']['evals_per_s']:.3g} evals/s")
+            _log(f"S={S} L={L}: {res['j1']['sweep_ms']:.2f} ms, {res['j1']['evals_per_s']:.3g} evals/s" +
+                 ("" if args.no_tune else f" (tuned {res['tuned']['labels_per_lane']}x"
+                                          f"{res['tuned']['waves_per_group']}: {res['tuned']['sweep_ms']:.2f} ms)"))
             rows.append(row)
         del dv
     return {"mode": "shapes", "workload": "8-view 1920x1080 YUV420 10-bit arc rig, bilinear, FP32 costs",

@@ -1,6 +1,9 @@
-// Launch-shape autotuner: times every (labels per lane, waves per group)
-// shape of the sweep on a given problem and returns the fastest.  The shapes
-// change how labels map to lanes and waves to workgroups, never a result.
+// Launch-shape autotuner: times every (labels per lane, waves per group,
+// pixels per step) shape of the sweep on a given problem and returns the
+// fastest.  Labels per lane and waves per group change how labels map to
+// lanes and waves to workgroups, never a result; the pixel-pair sweep adds a
+// segment's pixels in another order (bitwise equal results only where the
+// sums are integers).
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -14,11 +17,12 @@ using namespace ivde;
 namespace {
 
 struct Shape {
-    int J, wpg;
+    int J, wpg, px;
 };
 
-constexpr Shape kShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
-                             {4, 1}, {4, 2}, {4, 4}, {8, 1}, {8, 2}, {8, 4}};
+constexpr Shape kShapes[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {2, 1, 1}, {2, 2, 1}, {2, 4, 1},
+                             {4, 1, 1}, {4, 2, 1}, {4, 4, 1}, {8, 1, 1}, {8, 2, 1}, {8, 4, 1},
+                             {1, 1, 2}, {1, 2, 2}, {1, 4, 2}};
 
 }  // namespace
 
@@ -49,12 +53,15 @@ extern "C" ivde_status ivde_autotune(int32_t n_views, const ivde_camera *cams, c
         ivde_options o = *opt;
         o.labels_per_lane = sh.J;
         o.waves_per_group = sh.wpg;
+        o.pixels_per_step = sh.px;
         o.sweep_events[0] = ev[0];
         o.sweep_events[1] = ev[1];
         const Layout ly = plan_layout(n_views, cams, segs, labels, &o, views[0].bit_depth);
         float us = -1.f;
-        // a shape whose work list does not fit the given workspace is skipped
-        if (ly.workspace_bytes <= workspace_bytes && 64 * sh.J <= 2 * ((labels->num_labels + 63) / 64) * 64) {
+        // a shape whose work list does not fit the given workspace is skipped,
+        // and so is a pixel-pair shape where that sweep does not exist
+        if (ly.workspace_bytes <= workspace_bytes && 64 * sh.J <= 2 * ((labels->num_labels + 63) / 64) * 64 &&
+            ly.px == sh.px) {
             st = ivde_cost_volume(n_views, cams, views, segs, labels, &o, workspace, workspace_bytes, cost_out,
                                   stream);   // warm-up
             float total = 0.f;
@@ -80,6 +87,7 @@ extern "C" ivde_status ivde_autotune(int32_t n_views, const ivde_camera *cams, c
                 chosen = *opt;
                 chosen.labels_per_lane = sh.J;
                 chosen.waves_per_group = sh.wpg;
+                chosen.pixels_per_step = sh.px;
             }
         }
         if (times_us && i < max_times) times_us[i] = us;

@@ -6,7 +6,10 @@
 // that the concatenation is one queue.  Frames are ordered by decreasing
 // work so the queue drains large tasks first.  The sweep kernel runs the
 // same per-task code as ivde_cost_volume, so each frame's cost volume is
-// bitwise equal to what ivde_cost_volume returns for it.
+// bitwise equal to what ivde_cost_volume returns for it.  Frames whose
+// levels lie far apart take the pixel-pair sweep (as ivde_cost_volume would
+// choose for them): their tasks form the back of the queue, drained by a
+// second persistent launch right after the first.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,13 +32,14 @@ struct ivde_batch {
     std::vector<Layout> layouts;
     std::vector<size_t> frame_off;     // byte offset of each frame's region
     std::vector<int64_t> task_off;     // first task of each frame in the queue
-    std::vector<int> order;            // frames by decreasing work
+    std::vector<int> order;            // one-pixel frames, then pixel-pair frames, each by decreasing work
     ivde_options opt{};
     char *ws = nullptr;
     size_t off_probs = 0, off_tasks = 0, off_counters = 0, total_bytes = 0;
     int64_t n_tasks = 0;
+    int64_t n_tasks1 = 0;              // tasks of the one-pixel frames (the front of the queue)
     int J = 4, wpg = 4, tex_f32 = 0, f16 = 0, bilinear = 1;
-    int n_groups = 0;
+    int n_groups = 0, n_groups2 = 0;   // resident groups of the one-pixel and the pixel-pair sweep
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -106,11 +110,15 @@ ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_op
     }
     b.order.resize(n_frames);
     std::iota(b.order.begin(), b.order.end(), 0);
-    std::stable_sort(b.order.begin(), b.order.end(), [&](int a, int c) { return work[a] > work[c]; });
+    std::stable_sort(b.order.begin(), b.order.end(), [&](int a, int c) {
+        const int pa = b.layouts[a].px, pc = b.layouts[c].px;
+        return pa != pc ? pa < pc : work[a] > work[c];
+    });
     int64_t t = 0;
     for (int f : b.order) {
         b.task_off[f] = t;
         t += b.layouts[f].n_tasks;
+        if (b.layouts[f].px == 1) b.n_tasks1 = t;
     }
     b.n_tasks = t;
     b.off_probs = off;
@@ -118,7 +126,7 @@ ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_op
     b.off_tasks = off;
     off = align_up(off + sizeof(Task) * (size_t)b.n_tasks, 256);
     b.off_counters = off;
-    off = align_up(off + (kXcds + 1) * sizeof(int32_t), 256);   // cursors, then the task count
+    off = align_up(off + 2 * (kXcds + 1) * sizeof(int32_t), 256);   // per sweep: cursors, then the task count
     // keep host copies of the frame descriptions: the plan outlives the caller's arrays
     b.cams.resize(n_frames);
     b.views.resize(n_frames);
@@ -163,19 +171,29 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
     if ((e = launch_upload(b.ws + b.off_probs, probs.data(), sizeof(Problem) * probs.size(), s)) != hipSuccess)
         return hip_fail(e, "batch problem table");
     int32_t *counters = reinterpret_cast<int32_t *>(b.ws + b.off_counters);
-    if ((e = launch_fill_i32(counters, 0, kXcds, s)) != hipSuccess) return hip_fail(e, "batch cursors");
-    if ((e = launch_fill_i32(counters + kXcds, (int32_t)b.n_tasks, 1, s)) != hipSuccess)
-        return hip_fail(e, "batch count");
+    int32_t *counters2 = counters + kXcds + 1;
+    const int64_t n2 = b.n_tasks - b.n_tasks1;
+    if ((e = launch_fill_i32(counters, 0, kXcds, s)) != hipSuccess ||
+        (e = launch_fill_i32(counters + kXcds, (int32_t)b.n_tasks1, 1, s)) != hipSuccess ||
+        (e = launch_fill_i32(counters2, 0, kXcds, s)) != hipSuccess ||
+        (e = launch_fill_i32(counters2 + kXcds, (int32_t)n2, 1, s)) != hipSuccess)
+        return hip_fail(e, "batch cursors");
     // timing events only in eager runs: a captured graph replays without them
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "capture status");
     const bool timed = b.opt.sweep_events[0] && b.opt.sweep_events[1] && cap == hipStreamCaptureStatusNone;
     if (timed && (e = hipEventRecord(static_cast<hipEvent_t>(b.opt.sweep_events[0]), s)) != hipSuccess)
         return hip_fail(e, "event record");
-    e = launch_sweep_persistent(reinterpret_cast<const Problem *>(b.ws + b.off_probs),
-                                reinterpret_cast<const Task *>(b.ws + b.off_tasks), counters + kXcds, counters,
-                                b.n_tasks, b.J, b.bilinear, b.tex_f32, b.f16, b.wpg, b.n_groups, s);
-    if (e != hipSuccess) return hip_fail(e, "batch sweep");
+    const Problem *dprobs = reinterpret_cast<const Problem *>(b.ws + b.off_probs);
+    const Task *tasks = reinterpret_cast<const Task *>(b.ws + b.off_tasks);
+    if (b.n_tasks1 > 0 &&
+        (e = launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, b.n_tasks1, b.J, 1, b.bilinear,
+                                     b.tex_f32, b.f16, b.wpg, b.n_groups, s)) != hipSuccess)
+        return hip_fail(e, "batch sweep");
+    if (n2 > 0 &&
+        (e = launch_sweep_persistent(dprobs, tasks + b.n_tasks1, counters2 + kXcds, counters2, n2, b.J, 2, b.bilinear,
+                                     b.tex_f32, b.f16, b.wpg, b.n_groups2, s)) != hipSuccess)
+        return hip_fail(e, "batch pixel-pair sweep");
     if (timed && (e = hipEventRecord(static_cast<hipEvent_t>(b.opt.sweep_events[1]), s)) != hipSuccess)
         return hip_fail(e, "event record");
     for (int f = 0; f < b.n_frames; ++f) {
@@ -188,13 +206,13 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
     return IVDE_OK;
 }
 
-int persistent_groups(int J, int bilinear, int tex_f32, int f16, int wpg)
+int persistent_groups(int J, int px, int bilinear, int tex_f32, int f16, int wpg)
 {
     // enough resident groups to fill every CU at the kernel's occupancy
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (sweep_persistent_occupancy(J, bilinear, tex_f32, f16, wpg, &per_cu) != hipSuccess) return 0;
+    if (sweep_persistent_occupancy(J, px, bilinear, tex_f32, f16, wpg, &per_cu) != hipSuccess) return 0;
     return cus * std::max(1, per_cu);
 }
 
@@ -232,8 +250,9 @@ ivde_status ivde_batch_create(int32_t n_frames, const ivde_frame *frames, const 
         return st;
     }
     b->ws = static_cast<char *>(workspace);
-    b->n_groups = persistent_groups(b->J, b->bilinear, b->tex_f32, b->f16, b->wpg);
-    if (b->n_groups <= 0) {
+    b->n_groups = persistent_groups(b->J, 1, b->bilinear, b->tex_f32, b->f16, b->wpg);
+    b->n_groups2 = b->n_tasks1 < b->n_tasks ? persistent_groups(b->J, 2, b->bilinear, b->tex_f32, b->f16, b->wpg) : 1;
+    if (b->n_groups <= 0 || b->n_groups2 <= 0) {
         delete b;
         set_error("batch: occupancy query failed");
         return IVDE_EHIP;

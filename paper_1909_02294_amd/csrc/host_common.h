@@ -23,6 +23,7 @@ struct ViewLayout {
 // Byte offsets of everything one problem keeps in its workspace.
 struct Layout {
     int n, L, J, wpg, n_lblocks, tex_f32, f16;
+    int px;                            // pixels per wave step of the sweep (1 or 2)
     int max_w, max_h, max_s, max_bands;
     int64_t total_rows, n_tasks;
     size_t off_problem, off_views, off_pairs, off_sigma, off_flag, off_tasks;

@@ -97,15 +97,17 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
 // The sweep over tasks[0, n_tasks): enough resident groups to fill every CU
 // take tasks from per-XCD cursors.  counters: kXcds + 1 device ints of
 // scratch (the cursors, then the task count), set by this call.
-hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J,
+// px: pixels per wave step (2: the pixel-pair sweep, which exists for one
+// label per lane and half texels; 1: the one-pixel sweep).
+hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int px,
                         int bilinear, int tex_f32, int f16out, int waves_per_group, int32_t *counters,
                         hipStream_t s);
 // cursors: kXcds zeroed counters, one per contiguous range of the task list
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
-                                   int32_t *cursors, int64_t max_tasks, int J, int bilinear, int tex_f32,
+                                   int32_t *cursors, int64_t max_tasks, int J, int px, int bilinear, int tex_f32,
                                    int f16out, int waves_per_group, int n_groups, hipStream_t s);
 // Resident groups per CU of the persistent sweep for this launch shape.
-hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16out, int waves_per_group,
+hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_f32, int f16out, int waves_per_group,
                                       int *groups_per_cu);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s);

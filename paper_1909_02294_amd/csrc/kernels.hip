@@ -855,6 +855,303 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 #endif
 }
 
+// ------------------------------------------------------------------ pixel-pair sweep
+// The same (view, segment, 64-level block) tasks, with each wave step
+// covering two pixels of the segment at 32 levels instead of one pixel at
+// 64: lanes 0-31 take the even records of the segment, lanes 32-63 the odd
+// ones, and lane k of either half the levels 64 b + k (first pass) and
+// 64 b + 32 + k (second pass).  The 64 gathers of one instruction then span
+// the epipolar stretch of 32 levels at two neighbouring pixels, which touch
+// almost the same texels, instead of the stretch of 64 levels: half the
+// cache lines per gather.  The segment's pixel records are staged in the
+// wave's slice of LDS as {x, y, Y | Cb, Cr} (FP16 colours, exact for samples
+// up to 11 bits), read back by each lane for its own pixel; g . p~ is
+// recomputed from (x, y) as the index build computes it.  The two halves'
+// sums and counts meet through one cross-lane exchange per (target, pass).
+constexpr int kPairStage = 256;   // records one wave stages at a time (16 B each)
+
+__device__ __forceinline__ uint32_t pack_h2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+
+// Records [i0, i0 + n) of the view into the stage (n <= kPairStage).
+__device__ __forceinline__ void stage_records(const float *__restrict__ pix, int i0, int n, uint4 *st)
+{
+    const int lane = lane_id();
+    __builtin_amdgcn_wave_barrier();   // earlier reads of the stage come first
+    for (int t0 = 0; t0 < n; t0 += kWave) {
+        const int t = t0 + lane;
+        if (t < n) {
+            const float *r = pix + 8 * (int64_t)(i0 + t);
+            const float4 r0 = ldg(reinterpret_cast<const float4 *>(r));
+            const float2 r1 = ldg(reinterpret_cast<const float2 *>(r + 4));
+            st[t] = make_uint4(__float_as_uint(r0.x), __float_as_uint(r0.y), pack_h2(r0.w, r1.x),
+                               pack_h2(r1.y, 0.f));
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Projection and gathers of one (pixel, label) for the pixel-pair sweep: as
+// project_issue with half texels, but the bilinear fractions are returned
+// instead of the four weights, which consume_pair forms (the same
+// operations, later), so fewer registers stay live across the gathers.
+template <bool BIL, int FRONT>
+__device__ __forceinline__ void project_pair(const Target &T, float qx, float qy, float qz, float w,
+                                             Sample<BIL, false> &smp, float &ax, float &ay, bool &valid)
+{
+    const float hx = fmaf(w, T.e0, qx);
+    const float hy = fmaf(w, T.e1, qy);
+    const float hz = fmaf(w, T.e2, qz);
+    const float r = __builtin_amdgcn_rcpf(hz);
+    const float u = hx * r, v = hy * r;
+    valid = FRONT == 2 ? true : FRONT == 1 ? (hz > 0.f) : ((w > 0.f) & (hz > 0.f));
+    if constexpr (BIL) {
+        const float uc = __builtin_amdgcn_fmed3f(u, T.lo, T.hi_x);
+        const float vc = __builtin_amdgcn_fmed3f(v, T.lo, T.hi_y);
+        valid &= (uc == u) & (vc == v);
+        const uint32_t x0 = (uint32_t)(int)uc, y0 = (uint32_t)(int)vc;
+        ax = __builtin_amdgcn_fractf(uc);
+        ay = __builtin_amdgcn_fractf(vc);
+        const int off = (int)(mad_u24(y0, T.tp, x0) * 8u);
+        smp.a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
+        smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
+    } else {
+        const float fx = floorf(u + 0.5f), fy = floorf(v + 0.5f);
+        valid &= (fx >= 1.f) & (fx <= T.hi_x - kEdge) & (fy >= 1.f) & (fy <= T.hi_y - kEdge);
+        const uint32_t xi = (uint32_t)(int)fx, yi = (uint32_t)(int)fy;
+        const int off = valid ? (int)(mad_u24(yi, T.tp, xi) * 8u) : 0;
+        smp.a = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(T.rs, off, 0, 0));
+        ax = ay = 0.f;
+    }
+}
+
+// |dY| + |dCb| + |dCr| of one evaluation against reference colours held
+// as FP16 (rz = Y | Cb, rw = Cr), with the weights formed from the
+// bilinear fractions as project_issue forms them.
+template <bool BIL>
+__device__ __forceinline__ float consume_pair(const Sample<BIL, false> &smp, float ax, float ay, uint32_t rz,
+                                              uint32_t rw)
+{
+    float tY, tU, tV;
+    if constexpr (BIL) {
+        Weights wt;
+        wt.w11 = ax * ay;
+        wt.w01 = ax - wt.w11;
+        wt.w10 = ay - wt.w11;
+        wt.w00 = (1.f - ax) - wt.w10;
+        tY = fmaf(h_lo(smp.a.x), wt.w00, -h_lo(rz));
+        tU = fmaf(h_hi(smp.a.x), wt.w00, -h_hi(rz));
+        tV = fmaf(h_lo(smp.a.y), wt.w00, -h_lo(rw));
+        tY = fmaf(h_lo(smp.a.z), wt.w01, tY);
+        tU = fmaf(h_hi(smp.a.z), wt.w01, tU);
+        tV = fmaf(h_lo(smp.a.w), wt.w01, tV);
+        tY = fmaf(h_lo(smp.b.x), wt.w10, tY);
+        tU = fmaf(h_hi(smp.b.x), wt.w10, tU);
+        tV = fmaf(h_lo(smp.b.y), wt.w10, tV);
+        tY = fmaf(h_lo(smp.b.z), wt.w11, tY);
+        tU = fmaf(h_hi(smp.b.z), wt.w11, tU);
+        tV = fmaf(h_lo(smp.b.w), wt.w11, tV);
+    } else {
+        tY = h_lo(smp.a.x) - h_lo(rz);
+        tU = h_hi(smp.a.x) - h_hi(rz);
+        tV = h_lo(smp.a.y) - h_lo(rw);
+    }
+    return fabsf(tY) + fabsf(tU) + fabsf(tV);
+}
+
+// Pairs of staged records [0, m) towards one target at one pass (lane k of
+// either half at level sig): PU pairs per step with every gather issued
+// before the first is consumed, then the remaining pairs one at a time (the
+// last possibly with one pixel).
+template <int PU, bool BIL, int FRONT>
+__device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h, const float (&H)[9],
+                                                   const float (&g)[3], const Target &T, float sig, float &acc,
+                                                   uint64_t &acci, int &cnt)
+{
+    int i = 0;
+    for (; i + 2 * PU <= m; i += 2 * PU) {
+        Sample<BIL, false> smp[PU];
+        float ax[PU], ay[PU];
+        bool val[PU];
+        uint32_t rz[PU], rw[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const uint4 r = st[i + 2 * u + h];
+            const float x = __uint_as_float(r.x), y = __uint_as_float(r.y);
+            rz[u] = r.z;
+            rw[u] = r.w;
+            const float qx = fmaf(H[0], x, fmaf(H[1], y, H[2]));
+            const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5]));
+            const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8]));
+            const float gp = fmaf(g[0], x, fmaf(g[1], y, g[2]));
+            project_pair<BIL, FRONT>(T, qx, qy, qz, sig * gp, smp[u], ax[u], ay[u], val[u]);
+        }
+        if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const float d = consume_pair<BIL>(smp[u], ax[u], ay[u], rz[u], rw[u]);
+            if constexpr (BIL)
+                acc += val[u] ? d : 0.f;
+            else
+                acci += val[u] ? (uint32_t)d : 0u;
+            cnt += val[u] ? 1 : 0;
+        }
+    }
+    for (; i < m; i += 2) {
+        const int j = i + h;
+        const bool here = j < m;
+        const uint4 r = st[here ? j : m - 1];
+        const float x = __uint_as_float(r.x), y = __uint_as_float(r.y);
+        const float qx = fmaf(H[0], x, fmaf(H[1], y, H[2]));
+        const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5]));
+        const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8]));
+        const float gp = fmaf(g[0], x, fmaf(g[1], y, g[2]));
+        Sample<BIL, false> smp;
+        float ax, ay;
+        bool val;
+        project_pair<BIL, FRONT>(T, qx, qy, qz, sig * gp, smp, ax, ay, val);
+        val &= here;
+        const float d = consume_pair<BIL>(smp, ax, ay, r.z, r.w);
+        if constexpr (BIL)
+            acc += val ? d : 0.f;
+        else
+            acci += val ? (uint32_t)d : 0u;
+        cnt += val ? 1 : 0;
+    }
+}
+
+// Pairs each wave keeps in flight in the pixel-pair sweep.  Three fit 64
+// VGPRs; evaluating both of a lane's levels per pixel (the projection base
+// formed once for both) fits only one pixel in flight and was slower at 128
+// levels (20.7 against 19.3 ms on the 8-view 1080p arc rig).
+#ifndef IVDE_PAIR_INFLIGHT
+#define IVDE_PAIR_INFLIGHT 3
+#endif
+
+template <bool BIL, bool F16OUT>
+__device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st)
+{
+    constexpr int PU = IVDE_PAIR_INFLIGHT;
+    const int lane = lane_id();
+    const int h = lane >> 5, k = lane & 31;
+    const int c = task.view, s = task.seg;
+    const int L = ldu(&P->L), n = ldu(&P->n_views);
+    const ViewDesc *views = ldu(&P->views);
+    const PairConst *pairs = ldu(&P->pairs);
+    const float *sigma = ldu(&P->sigma);
+    const float norm = ldu(&P->norm);
+    void *cost = ldu(&P->cost);
+    const ViewDesc *vc = views + c;
+    const int32_t *offsets = ldu(&vc->offsets);
+    const int p0 = ldu(offsets + s), p1 = ldu(offsets + s + 1);
+    const float *pix = ldu(&vc->pixrec);
+    const int nt = ldu(&vc->n_targets);
+    const int64_t row0 = ldu(&vc->row0);
+    const int front_all = ldu(&vc->front_all);
+    const uint32_t front_targets = ldu(&vc->front_targets);
+    const float g[3] = {ldu(&vc->g[0]), ldu(&vc->g[1]), ldu(&vc->g[2])};
+
+    const int lbase = task.lblock * kWave;
+    const int passes = lbase + kWave / 2 < L ? 2 : 1;
+    int lab[2];
+    float sig[2], best[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        lab[q] = lbase + q * (kWave / 2) + k;
+        sig[q] = lab[q] < L ? sigma[c * L + lab[q]] : 0.f;
+        best[q] = __builtin_inff();
+    }
+    const int np = p1 - p0;
+    const bool resident = np <= kPairStage;   // staged once for every target
+    if (resident && np > 0) stage_records(pix, p0, np, st);
+
+    for (int ti = 0; ti < nt; ++ti) {
+        const int c2 = ldu(&vc->targets[ti]);
+        const ViewDesc *vt = views + c2;
+        Target T;
+        T.rs = make_rsrc(ldu(&vt->tex), ldu(&vt->tex_bytes));
+        T.lo = 1.f - kEdge;
+        T.hi_x = (float)ldu(&vt->W) + kEdge;
+        T.hi_y = (float)ldu(&vt->H) + kEdge;
+        T.tp = (uint32_t)ldu(&vt->tex_pitch);
+        T.rowB = (int)T.tp * 8;
+        const float *pc = reinterpret_cast<const float *>(pairs + c * n + c2);
+        const f32x4 ha = ldu4(pc), hb = ldu4(pc + 4), hc = ldu4(pc + 8);
+        const float H[9] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w, hc.x};
+        T.e0 = hc.y;
+        T.e1 = hc.z;
+        T.e2 = hc.w;
+        const int front = front_all ? (((front_targets >> c2) & 1u) ? 2 : 1) : 0;
+        for (int q = 0; q < passes; ++q) {
+            float acc = 0.f;
+            uint64_t acci = 0;
+            int cnt = 0;
+            for (int b0 = 0; b0 < np; b0 += kPairStage) {
+                const int m = min(kPairStage, np - b0);
+                if (!resident) stage_records(pix, p0 + b0, m, st);
+                if (front == 2)
+                    sweep_pair_records<PU, BIL, 2>(st, m, h, H, g, T, sig[q], acc, acci, cnt);
+                else if (front == 1)
+                    sweep_pair_records<PU, BIL, 1>(st, m, h, H, g, T, sig[q], acc, acci, cnt);
+                else
+                    sweep_pair_records<PU, BIL, 0>(st, m, h, H, g, T, sig[q], acc, acci, cnt);
+            }
+            // the two halves' sums and counts: one exchange across the halves
+            cnt += __shfl_xor(cnt, kWave / 2);
+            float sum;
+            if constexpr (BIL) {
+                sum = acc + __shfl_xor(acc, kWave / 2);
+            } else {
+                const uint32_t lo = (uint32_t)acci, hi = (uint32_t)(acci >> 32);
+                const uint64_t other = ((uint64_t)(uint32_t)__shfl_xor((int)hi, kWave / 2) << 32) |
+                                       (uint32_t)__shfl_xor((int)lo, kWave / 2);
+                sum = (float)(acci + other);
+            }
+            if (cnt > 0) best[q] = fminf(best[q], sum / ((float)cnt * norm));
+        }
+    }
+
+    const int64_t row = row0 + s;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (h == 0 && lab[q] < L) {
+            const float o = best[q] == __builtin_inff() ? 1.0f : best[q];
+            if constexpr (F16OUT)
+                static_cast<__half *>(cost)[row * L + lab[q]] = __float2half_rn(o);
+            else
+                static_cast<float *>(cost)[row * L + lab[q]] = o;
+        }
+    }
+}
+
+template <bool BIL, bool F16OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_pairs(
+    const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
+    int32_t *__restrict__ cursors, int64_t max_tasks)
+{
+    extern __shared__ uint4 pair_stage[];
+    uint4 *st = pair_stage + (threadIdx.x / kWave) * kPairStage;
+    const int lane = lane_id();
+    const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
+    // per-XCD ranges and work stealing as in sweep_persistent_body
+    const int home = (int)(blockIdx.x % kXcds);
+    for (int k = 0; k < kXcds; ++k) {
+        const int x = (home + k) % kXcds;
+        const int64_t lo = limit * x / kXcds, n = limit * (x + 1) / kXcds - lo;
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(&cursors[x], 1);
+            t = uniform(__shfl(t, 0));
+            if (t >= n) break;
+            const Task task = ldu_task(tasks + lo + t);
+            sweep_task_pairs<BIL, F16OUT>(probs + task.problem, task, st);
+        }
+    }
+}
+
 // Cursors of the sweep to zero, then the task count.
 __global__ void k_sweep_counters(int32_t *__restrict__ counters, int32_t n_tasks)
 {
@@ -1063,14 +1360,21 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
     return hipGetLastError();
 }
 
+// Dynamic LDS of the pixel-pair sweep: one record stage per wave.
+static size_t pair_stage_bytes(int wpg) { return (size_t)wpg * kPairStage * sizeof(uint4); }
+
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
 static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursors,
-                             int64_t max_tasks, int wpg, int n_groups, hipStream_t s)
+                             int64_t max_tasks, int px, int wpg, int n_groups, hipStream_t s)
 {
-    if constexpr (J == 1 && !TEXF32)
-        hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
-                           dprobs, tasks, n_tasks, cursors, max_tasks);
-    else
+    if constexpr (J == 1 && !TEXF32) {
+        if (px == 2)
+            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg),
+                               pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
+        else
+            hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
+                               dprobs, tasks, n_tasks, cursors, max_tasks);
+    } else
         hipLaunchKernelGGL((k_sweep_persistent<J, BIL, TEXF32, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0,
                            s, dprobs, tasks, n_tasks, cursors, max_tasks);
     return hipGetLastError();
@@ -1091,26 +1395,29 @@ static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int
     } while (0)
 
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
-static hipError_t occ(int wpg, int *per_cu)
+static hipError_t occ(int px, int wpg, int *per_cu)
 {
-    if constexpr (J == 1 && !TEXF32)
+    if constexpr (J == 1 && !TEXF32) {
+        if (px == 2)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT>, 64 * wpg,
+                                                                pair_stage_bytes(wpg));
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent_j1<BIL, F16OUT>, 64 * wpg, 0);
-    else
+    } else
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<J, BIL, TEXF32, F16OUT>,
                                                             64 * wpg, 0);
 }
 
-hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16out, int wpg, int *per_cu)
+hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_f32, int f16out, int wpg, int *per_cu)
 {
     const int f16 = f16out;
 #define IVDE_OCC(JJ)                                                                                   \
     do {                                                                                              \
         if (bilinear) {                                                                               \
-            if (tex_f32) return f16 ? occ<JJ, true, true, true>(wpg, per_cu) : occ<JJ, true, true, false>(wpg, per_cu); \
-            return f16 ? occ<JJ, true, false, true>(wpg, per_cu) : occ<JJ, true, false, false>(wpg, per_cu); \
+            if (tex_f32) return f16 ? occ<JJ, true, true, true>(px, wpg, per_cu) : occ<JJ, true, true, false>(px, wpg, per_cu); \
+            return f16 ? occ<JJ, true, false, true>(px, wpg, per_cu) : occ<JJ, true, false, false>(px, wpg, per_cu); \
         }                                                                                             \
-        if (tex_f32) return f16 ? occ<JJ, false, true, true>(wpg, per_cu) : occ<JJ, false, true, false>(wpg, per_cu); \
-        return f16 ? occ<JJ, false, false, true>(wpg, per_cu) : occ<JJ, false, false, false>(wpg, per_cu); \
+        if (tex_f32) return f16 ? occ<JJ, false, true, true>(px, wpg, per_cu) : occ<JJ, false, true, false>(px, wpg, per_cu); \
+        return f16 ? occ<JJ, false, false, true>(px, wpg, per_cu) : occ<JJ, false, false, false>(px, wpg, per_cu); \
     } while (0)
     switch (J) {
     case 1: IVDE_OCC(1);
@@ -1123,19 +1430,19 @@ hipError_t sweep_persistent_occupancy(int J, int bilinear, int tex_f32, int f16o
 }
 
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
-                                   int32_t *cursors, int64_t max_tasks, int J, int bilinear, int tex_f32,
+                                   int32_t *cursors, int64_t max_tasks, int J, int px, int bilinear, int tex_f32,
                                    int f16out, int wpg, int n_groups, hipStream_t s)
 {
     switch (J) {
-    case 1: IVDE_DISPATCH_FLAGS(sweep_pers, 1, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
-    case 2: IVDE_DISPATCH_FLAGS(sweep_pers, 2, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
-    case 4: IVDE_DISPATCH_FLAGS(sweep_pers, 4, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
-    case 8: IVDE_DISPATCH_FLAGS(sweep_pers, 8, dprobs, tasks, n_tasks_dev, cursors, max_tasks, wpg, n_groups, s);
+    case 1: IVDE_DISPATCH_FLAGS(sweep_pers, 1, dprobs, tasks, n_tasks_dev, cursors, max_tasks, px, wpg, n_groups, s);
+    case 2: IVDE_DISPATCH_FLAGS(sweep_pers, 2, dprobs, tasks, n_tasks_dev, cursors, max_tasks, px, wpg, n_groups, s);
+    case 4: IVDE_DISPATCH_FLAGS(sweep_pers, 4, dprobs, tasks, n_tasks_dev, cursors, max_tasks, px, wpg, n_groups, s);
+    case 8: IVDE_DISPATCH_FLAGS(sweep_pers, 8, dprobs, tasks, n_tasks_dev, cursors, max_tasks, px, wpg, n_groups, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int bilinear,
+hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int px, int bilinear,
                         int tex_f32, int f16out, int wpg, int32_t *counters, hipStream_t s)
 {
     if (n_tasks <= 0) return hipSuccess;
@@ -1144,12 +1451,12 @@ hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_task
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = sweep_persistent_occupancy(J, bilinear, tex_f32, f16out, wpg, &per_cu)) != hipSuccess) return e;
+    if ((e = sweep_persistent_occupancy(J, px, bilinear, tex_f32, f16out, wpg, &per_cu)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sweep_counters, dim3(1), dim3(64), 0, s, counters, (int32_t)n_tasks);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int n_groups = std::max(1, cus) * std::max(1, per_cu);
-    return launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, n_tasks, J, bilinear, tex_f32, f16out,
-                                   wpg, n_groups, s);
+    return launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, n_tasks, J, px, bilinear, tex_f32,
+                                   f16out, wpg, n_groups, s);
 }
 
 hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s)

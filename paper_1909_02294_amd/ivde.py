@@ -54,7 +54,8 @@ class LabelRange(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("sampling", ctypes.c_int32), ("cost_dtype", ctypes.c_int32), ("targets", ctypes.c_int32),
                 ("target_mask", ctypes.c_void_p), ("labels_per_lane", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32), ("sweep_events", ctypes.c_void_p * 2)]
+                ("waves_per_group", ctypes.c_int32), ("sweep_events", ctypes.c_void_p * 2),
+                ("pixels_per_step", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -263,10 +264,12 @@ def label_range(z_near, z_far, num_labels, depth_ref=REF_RIG_CENTER):
 
 
 def options(sampling=BILINEAR, cost_dtype=F32, targets=TARGETS_ALL, target_mask=None,
-            labels_per_lane=0, waves_per_group=0, sweep_events=None):
+            labels_per_lane=0, waves_per_group=0, sweep_events=None, pixels_per_step=0):
     """sweep_events: optional pair of torch.cuda.Event(enable_timing=True),
-    recorded by the library around its sweep kernel."""
+    recorded by the library around its sweep kernel; pixels_per_step: 2 for
+    the pixel-pair sweep, 1 for the one-pixel sweep, 0 the default."""
     o = Options(int(sampling), int(cost_dtype), int(targets), None, int(labels_per_lane), int(waves_per_group))
+    o.pixels_per_step = int(pixels_per_step)
     if sweep_events is not None:
         torch = _torch()
         for ev in sweep_events:           # make torch create the underlying events
@@ -564,11 +567,13 @@ class Server:
 
 
 # ---------------------------------------------------------------- tuning
-AUTOTUNE_SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4)]
+# (labels per lane, waves per group, pixels per step), in the library's order
+AUTOTUNE_SHAPES = [(1, 1, 1), (1, 2, 1), (1, 4, 1), (2, 1, 1), (2, 2, 1), (2, 4, 1), (4, 1, 1), (4, 2, 1), (4, 4, 1),
+                   (8, 1, 1), (8, 2, 1), (8, 4, 1), (1, 1, 2), (1, 2, 2), (1, 4, 2)]
 
 
 def autotune(dv: DeviceViews, lr: LabelRange, opt: Options, reps=2, stream=None):
-    """ivde_autotune: returns (best Options, {(J, wpg): microseconds or None})."""
+    """ivde_autotune: returns (best Options, {(J, wpg, px): microseconds or None})."""
     torch = _torch()
     lib = load()
     probe = Options(opt.sampling, opt.cost_dtype, opt.targets, opt.target_mask, 1, 1)
@@ -623,10 +628,12 @@ def autotune_cached(dv: DeviceViews, lr: LabelRange, opt: Options, cache_path=No
     hit = cache.get(key)
     if hit is not None:
         return options(opt.sampling, opt.cost_dtype, opt.targets, getattr(opt, "_mask", None),
-                       labels_per_lane=hit["labels_per_lane"], waves_per_group=hit["waves_per_group"]), None
+                       labels_per_lane=hit["labels_per_lane"], waves_per_group=hit["waves_per_group"],
+                       pixels_per_step=hit.get("pixels_per_step", 1)), None
     best, table = autotune(dv, lr, opt, reps=reps, stream=stream)
     cache[key] = {"labels_per_lane": best.labels_per_lane, "waves_per_group": best.waves_per_group,
-                  "us": {f"{k[0]}x{k[1]}": v for k, v in table.items()}}
+                  "pixels_per_step": best.pixels_per_step,
+                  "us": {"x".join(map(str, k)): v for k, v in table.items()}}
     if cache_path is not None:
         tmp = f"{cache_path}.tmp{os.getpid()}"
         with open(tmp, "w") as fh:

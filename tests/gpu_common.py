@@ -28,12 +28,13 @@ TIE_F64 = 1.2e-12
 
 
 def run_gpu(ns, sampling=None, cost_dtype=ivde.F32, targets=ivde.TARGETS_ALL, target_mask=None,
-            depth_ref=ivde.REF_RIG_CENTER, labels_per_lane=0, waves_per_group=0):
+            depth_ref=ivde.REF_RIG_CENTER, labels_per_lane=0, waves_per_group=0, pixels_per_step=0):
     dv = ivde.DeviceViews(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift)
     if sampling is None:
         sampling = ivde.BILINEAR if ns.bilinear else ivde.NEAREST
     lr = ivde.label_range(ns.z_near, ns.z_far, ns.num_labels, depth_ref)
-    opt = ivde.options(sampling, cost_dtype, targets, target_mask, labels_per_lane, waves_per_group)
+    opt = ivde.options(sampling, cost_dtype, targets, target_mask, labels_per_lane, waves_per_group,
+                       pixels_per_step=pixels_per_step)
     C, ws = ivde.cost_volume(dv, lr, opt)
     lab = ivde.argmin(C)
     import torch

@@ -40,7 +40,7 @@ def test_cached_class_is_not_timed_again(tmp_path, monkeypatch):
 
     def fake_autotune(dv, lr_, opt, reps=2, stream=None):
         calls.append(ivde.shape_class(dv, lr_, opt))
-        best = ivde.options(opt.sampling, opt.cost_dtype, labels_per_lane=2, waves_per_group=4)
+        best = ivde.options(opt.sampling, opt.cost_dtype, labels_per_lane=2, waves_per_group=4, pixels_per_step=1)
         return best, {s: 100.0 + i for i, s in enumerate(ivde.AUTOTUNE_SHAPES)}
 
     monkeypatch.setattr(ivde, "autotune", fake_autotune)
@@ -48,6 +48,8 @@ def test_cached_class_is_not_timed_again(tmp_path, monkeypatch):
     assert (best.labels_per_lane, best.waves_per_group) == (2, 4) and table is not None
     stored = json.loads(path.read_text())
     assert stored["bil-f32-tex16-L256-px128-t7"]["labels_per_lane"] == 2
+    assert stored["bil-f32-tex16-L256-px128-t7"]["pixels_per_step"] == 1
+    assert "1x4x2" in stored["bil-f32-tex16-L256-px128-t7"]["us"]
     # same class (another segment count that rounds alike, 250 levels): from the file
     best2, table2 = ivde.autotune_cached(_dv(S=21000), ivde.label_range(1.5, 10.0, 250), o, str(path))
     assert table2 is None and (best2.labels_per_lane, best2.waves_per_group) == (2, 4)

@@ -1,0 +1,149 @@
+"""GPU parity of the pixel-pair sweep (pixels_per_step = 2): each wave step
+covers two pixels of a segment at 32 levels, the segment's pixel records
+are staged in LDS, and the two halves of the wave meet in one cross-lane
+exchange per (target, pass).  It must match the FP64 oracle at the same
+bars as the one-pixel sweep, give bitwise the one-pixel sweep's result
+wherever the sums are integers (nearest sampling), and cover segments
+larger than one LDS stage (256 records), odd pixel counts, points behind a
+camera, FP16 storage and the batched and served forms."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import _problems as P
+from tests.gpu_common import compare, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1909_02294_amd import ivde, synth  # noqa: E402
+
+
+def _case(name):
+    print(f"[case] {name}", flush=True)
+
+
+@pytest.mark.parametrize("seed,S,L", [(1, 150, 70), (2, 150, 64), (3, 40, 33), (4, 9, 130)])
+def test_pairs_small_arc_bilinear_420(seed, S, L):
+    """Arc rigs, 4:2:0 10-bit, bilinear; with 9 or 40 segments on 160x96
+    most segments exceed one stage of 256 records."""
+    _case(f"pairs arc seed {seed} S {S} L {L}")
+    wl = synth.make_small_arc(seed=seed, n_views=4, width=160, height=96, n_segments=S, num_labels=L)
+    sizes = np.concatenate([np.bincount(s.ravel(), minlength=n) for s, n in zip(wl.seg, wl.S)])
+    if S <= 40:
+        assert sizes.max() > 256
+    assert (sizes % 2 == 1).any()
+    G, lab = run_gpu(wl, pixels_per_step=2)
+    O = run_oracle(wl)
+    r = compare(G, O, label=f"pairs arc{seed}")
+    assert r["max_err"] <= 1e-4, r
+    assert np.array_equal(lab, np.argmin(G, 1))
+    # the same quantity as the one-pixel sweep, up to FP32 summation order
+    G1, _ = run_gpu(wl, pixels_per_step=1)
+    assert np.abs(G - G1).max() <= 1e-5
+
+
+def test_pairs_nearest_rectified_equals_one_pixel_sweep():
+    """Nearest sampling sums integer code-value differences: the order of
+    the additions does not matter, so both sweeps agree bit for bit."""
+    _case("pairs rectified nearest")
+    wl = synth.make_rectified_320x240()
+    G2, _ = run_gpu(wl, pixels_per_step=2)
+    G1, _ = run_gpu(wl, pixels_per_step=1)
+    assert np.array_equal(G2, G1)
+    r = compare(G2, run_oracle(wl), label="rectified pairs")
+    assert r["max_err"] <= 1e-6 and r["argmin_agree"] == 1.0, r
+
+
+@pytest.mark.parametrize("case", [
+    dict(n_views=2, width=13, height=9, n_seg=5, L=1),
+    dict(n_views=3, width=12, height=8, n_seg=6, L=5, chroma_shift=1, bilinear=True, rotated=True, bit_depth=10),
+    dict(n_views=4, width=31, height=17, n_seg=12, L=65, bilinear=True, rotated=True, bit_depth=10),
+    dict(n_views=5, width=24, height=16, n_seg=9, L=300, rotated=True, bilinear=True),
+    dict(n_views=3, width=40, height=23, n_seg=2, L=40, rotated=True, bilinear=True, bit_depth=11),
+])
+def test_pairs_tiny_cases(case):
+    _case(f"pairs tiny {case}")
+    ns = P.tiny_problem(22, **case)
+    G, _ = run_gpu(ns, pixels_per_step=2)
+    compare(G, run_oracle(ns), label=str(case))
+
+
+@pytest.mark.parametrize("ref", ["rig", 0])
+def test_pairs_facing_rig(ref):
+    """Points behind the source and the target cameras (the general
+    validity test of the sweep)."""
+    _case(f"pairs facing rig {ref}")
+    ns = P.facing_problem(60, width=96, height=64, n_seg=60, L=48, bit_depth=10, chroma_shift=1, bilinear=True)
+    geo = P.behind_geometry(ns, ref)
+    assert geo["behind_share"] >= 0.01
+    gref = ivde.REF_RIG_CENTER if ref == "rig" else ref
+    oref = oracle.REF_RIG_CENTER if ref == "rig" else ref
+    G, _ = run_gpu(ns, depth_ref=gref, pixels_per_step=2)
+    compare(G, run_oracle(ns, depth_ref=oref), label=f"pairs facing {ref}")
+    G1, _ = run_gpu(ns, depth_ref=gref, pixels_per_step=1)
+    assert np.array_equal(G == 1.0, G1 == 1.0)
+
+
+def test_pairs_fp16_storage_and_repeat():
+    _case("pairs fp16 and repeat")
+    wl = synth.make_small_arc(seed=7, n_views=3, width=128, height=80, n_segments=139, num_labels=47)
+    G, _ = run_gpu(wl, cost_dtype=ivde.F16, pixels_per_step=2)
+    compare(G, run_oracle(wl), f16=True, label="pairs fp16")
+    G2, _ = run_gpu(wl, cost_dtype=ivde.F16, pixels_per_step=2)
+    assert np.array_equal(G, G2)
+
+
+def test_pairs_batched_and_served_equal_plain():
+    """The batched form (one persistent launch, graph replays) and the
+    served form run the same kernel: bitwise the plain pixel-pair result."""
+    _case("pairs batched and served")
+    wls = [synth.make_small_arc(seed=30 + i, n_views=3 + i % 2, width=120, height=72, n_segments=60 + 30 * i,
+                                num_labels=[40, 64, 96][i % 3]) for i in range(4)]
+    opt = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=2)
+    ref, frames = [], []
+    for wl in wls:
+        dv = ivde.DeviceViews.from_workload(wl)
+        lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
+        C, _ = ivde.cost_volume(dv, lr, opt)
+        ref.append(C.clone())
+        out = torch.full_like(C, -3.0)
+        lab = torch.full((C.shape[0],), -1, dtype=torch.int32, device="cuda")
+        frames.append((dv, lr, out, lab))
+    stream = torch.cuda.Stream()
+    batch = ivde.Batch(frames, opt)
+    for use_graph in (False, True, True):
+        for _, _, out, _ in frames:
+            out.fill_(-3.0)
+        batch.run(stream, use_graph=use_graph)
+        stream.synchronize()
+        for (dv, lr, out, lab), r in zip(frames, ref):
+            assert torch.equal(out, r)
+            assert torch.equal(lab, ivde.argmin(r))
+    batch.close()
+    # served: an I frame then a P frame of one rig, FP32 storage
+    wl = wls[1]
+    fr = synth.make_sequence(wl, 2, seed=77)
+    srv = ivde.Server(1 << 30, max_slots=2)
+    dv = ivde.DeviceViews.from_workload(wl)
+    lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
+    rid = srv.register(dv, lr, opt)
+    outs = []
+    for i, f in enumerate(fr):
+        img = ivde.DeviceViews(wl.cams, f["Y"], f["U"], f["V"], wl.seg, wl.S, wl.bit_depth, wl.chroma_shift)
+        out = torch.empty((dv.rows, wl.num_labels), dtype=torch.float32, device="cuda")
+        mask = None if f["mask"] is None else torch.from_numpy(np.concatenate(f["mask"]).astype(np.uint8)).cuda()
+        st = srv.wait(srv.submit(rid, img.c_images, mask, out))
+        assert st["status"] == 0
+        plain, _ = ivde.cost_volume(img, lr, opt)
+        torch.cuda.synchronize()
+        if mask is None:
+            assert torch.equal(out, plain)
+        else:
+            m = mask.bool()
+            assert torch.equal(out[m], plain[m]) and torch.equal(out[~m], outs[-1][~m])
+        outs.append(out)
+    srv.close()
