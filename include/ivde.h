@@ -255,8 +255,9 @@ typedef struct {
     int64_t chunk_evals;      /* a full-frame sweep runs as launches of about this many
                                  pixel-label-target evaluations, and the next launch is
                                  enqueued only while no other rig's uncut frame is in
-                                 flight, so short frames wait at most one launch behind a
-                                 full one; 0: 4e9 (about 4 ms on MI355X); < 0: one launch */
+                                 flight (or once its own rig's next frame is admitted), so
+                                 short frames wait at most one launch behind a full one;
+                                 0: 8e9 (about 8 ms on MI355X); < 0: one launch */
 } ivde_server_config;
 
 typedef struct {

@@ -373,7 +373,7 @@ def bench_served(args):
                                "C (10x2048x1088, 256); YUV420 10-bit, bilinear, FP16 costs, 80 GB arena",
                    "seconds": duration, "slots": args.slots, "gop": args.gop,
                    "distinct_frames_per_rig": n_cycle,
-                   "chunk_evals": chunks[0] or "library default (4e9)",
+                   "chunk_evals": chunks[0] or "library default (8e9)",
                    "mask": "temporal rule on the GPU (T_P = 3, T_I = 1)" if rule else "changed-segment mask input",
                    "protocol": "each rig's first (I) frame is computed before the arrival clock; " +
                                ("frames in pinned host memory, uploaded by the server on the request's stream; "

@@ -25,7 +25,9 @@
 // other rigs that arrive meanwhile wait for all of it.  The scheduler
 // enqueues the next launch of a cut sweep only after the previous one has
 // completed and while no uncut request is in flight, so a P frame admitted
-// during an I frame waits at most for the launch that is running.
+// during an I frame waits at most for the launch that is running.  Once the
+// I frame's own rig has its next frame admitted, the I frame no longer gives
+// way: that frame starts from the I frame's volume and waits for it anyway.
 //
 // Frames may also be handed over in host memory (ivde_stream_submit_host):
 // the planes and the mask are copied into the request's working set on its
@@ -202,7 +204,7 @@ int64_t frame_evals(int n, const ivde_camera *cams, const ivde_label_range &labe
     return e;
 }
 
-constexpr int64_t kDefaultChunkEvals = 4000000000LL;
+constexpr int64_t kDefaultChunkEvals = 8000000000LL;
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -357,6 +359,10 @@ bool ivde_server::uncut_in_flight(uint64_t except) const
 void ivde_server::progress()
 {
     std::vector<int> pending_rigs;   // rigs with an earlier request not all enqueued
+    // A cut sweep whose rig already has its next frame admitted stops giving
+    // way: that frame waits for it by construction.
+    std::vector<int> admitted(rigs.size(), 0);
+    for (uint64_t t : active) admitted[reqs[t].rig]++;
     for (size_t i = 0; i < active.size();) {
         Request &r = reqs[active[i]];
         Slot &sl = slots[r.slot];
@@ -367,7 +373,7 @@ void ivde_server::progress()
             const ivde_status st = start(r, sl, rig);
             if (st != IVDE_OK) abort(r, sl, st);
         } else if (!r.enqueued && r.started && hipEventQuery(sl.chunk) != hipErrorNotReady &&
-                   !uncut_in_flight(r.ticket)) {
+                   (admitted[r.rig] > 1 || !uncut_in_flight(r.ticket))) {
             const ivde_status st = pump(r, sl, rig);
             if (st != IVDE_OK) abort(r, sl, st);
         }

@@ -99,6 +99,7 @@ def test_size_query(lib):
 @pytest.mark.parametrize("field,value", [
     ("n_views", 0), ("n_views", 33), ("z_near", -1.0), ("z_far", float("nan")), ("num_labels", 0),
     ("depth_ref", 7), ("sampling", 5), ("cost_dtype", 9), ("labels_per_lane", 3), ("waves_per_group", 8),
+    ("pixels_per_step", 3), ("pixels_per_step", -1),
     ("bit_depth", 7), ("bit_depth", 17), ("width", 0), ("segments", 0),
 ])
 def test_invalid_arguments_are_rejected(lib, field, value):
@@ -111,7 +112,7 @@ def test_invalid_arguments_are_rejected(lib, field, value):
         n = value
     elif field in ("z_near", "z_far", "num_labels", "depth_ref"):
         setattr(lr, field, value)
-    elif field in ("sampling", "cost_dtype", "labels_per_lane", "waves_per_group"):
+    elif field in ("sampling", "cost_dtype", "labels_per_lane", "waves_per_group", "pixels_per_step"):
         setattr(opt, field, value)
     elif field == "bit_depth":
         bd = value

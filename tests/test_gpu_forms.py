@@ -169,11 +169,39 @@ def test_autotune():
 _tie_aware = tie_aware
 
 
+def entry_error_bound(ns):
+    """Bound on the FP32 error of one cost entry away from the validity
+    band: every sample's position is off by at most position_error_bound
+    pixels, bilinear sampling changes by at most the largest difference of
+    neighbouring samples per pixel of offset (per channel, summed over the
+    three channels, in units of the cost), the FP32 interpolation and
+    differences of one pixel's cost (16 roundings of values below the
+    normalising 3 (2^b - 1)) add at most 16 2^-24, and the FP32 sum of n
+    costs in [0, 1] and its division at most (n + 2) 2^-24."""
+    from tests.gpu_common import position_error_bound
+    grad = 0.0
+    for planes in (ns.Y, ns.U, ns.V):
+        g = 0.0
+        for a in planes:
+            a = np.asarray(a, np.float64)
+            g = max(g, np.abs(np.diff(a, axis=0)).max(), np.abs(np.diff(a, axis=1)).max())
+        grad += g
+    n_max = max(int(np.bincount(s.ravel()).max()) for s in ns.seg)
+    return position_error_bound(ns) * 2.0 * grad / (3.0 * ((1 << ns.bit_depth) - 1)) + (n_max + 18) * 2.0 ** -24
+
+
 def test_precision_small_512_labels():
     """512 labels on a 256 px wide image: label steps are a few hundredths
-    of a pixel, so near-equal neighbouring labels are common; strict argmin
-    agreement is only asked at 99% (95% after FP16 rounding), tie-aware
-    agreement at 99.9%."""
+    of a pixel, so neighbouring labels often cost almost the same.  Two
+    labels whose oracle costs differ by less than twice the entry error
+    bound (derived above) may legitimately swap; every other row must pick
+    the oracle's label.  The bound holds away from the bilinear validity
+    band; entries beyond it must each hold a sample within the FP32 position
+    error of that band (a sample counted on one side and not the other), and
+    their rows are judged by the tie-aware bar only.  Both bars at 99.9%:
+    strict agreement on the rows whose oracle margin exceeds twice the bound,
+    and agreement within twice the bound on all rows (plus the FP16 rounding,
+    2^-12, for FP16 storage).  Strict agreement over all rows is reported."""
     _case("precision small")
     wl = synth.make_small_arc(seed=8, n_views=4, width=256, height=136, n_segments=160, num_labels=512)
     dv = ivde.DeviceViews.from_workload(wl)
@@ -182,10 +210,23 @@ def test_precision_small_512_labels():
     c16, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F16))
     O = run_oracle(wl)
     G32, G16 = c32.double().cpu().numpy(), c16.double().cpu().numpy()
-    compare(G32, O, argmin_min=0.99, label="f32")
-    # FP16 rounding (2^-12 near 0.25) makes neighbouring labels tie exactly
-    compare(G16, O, f16=True, argmin_min=0.95, label="f16")
-    assert _tie_aware(G32, O) >= 0.999 and _tie_aware(G16, O, 2.0 ** -11) >= 0.999
+    eps = entry_error_bound(wl)
+    srt = np.sort(O, 1)
+    n_band, _ = assert_large_errors_explained(wl, G32, O, thresh=eps, label="f32 beyond the entry bound")
+    in_band = (np.abs(G32 - O) > eps).any(1)
+    clear = (srt[:, 1] - srt[:, 0] > 2 * eps) & ~in_band
+    res = {}
+    for name, G, slack in (("f32", G32, 0.0), ("f16", G16, 2.0 ** -12)):
+        r = compare(G, O, f16=slack > 0, argmin_min=0.0, label=name)
+        ga = np.argmin(G, 1)
+        strict_clear = float((ga[clear] == np.argmin(O, 1)[clear]).mean())
+        within = _tie_aware(G, O, 2 * eps + slack)
+        assert within >= 0.999, (name, within, eps)
+        if slack == 0.0:
+            assert strict_clear >= 0.999, (name, strict_clear, eps)
+        res[name] = dict(strict_all=r["argmin_agree"], strict_clear_rows=strict_clear, within_2eps=within)
+    print(f"precision small: entry bound {eps:.3g}, {n_band} entries beyond it (validity band), "
+          f"rows with a clear margin {clear.mean():.3f}, {res}", flush=True)
     assert np.abs(G16 - G32).max() <= 2.0 ** -12
 
 
