@@ -100,7 +100,7 @@ def measured_counters(name: str, wl_sha: str):
 _CLASS_OF = [("v_fma_f32", 0), ("v_fmac_f32", 1), ("v_mul_f32", 2), ("v_add_f32_e64", 6), ("v_add_f32", 3),
              ("v_sub_f32", 4), ("v_mov_b32", 5), ("v_fma_mix_f32", 7), ("v_med3_f32", 8), ("v_fract_f32", 9),
              ("v_cvt_", 10), ("v_cmp_", 11), ("v_cndmask_b32", 12), ("v_rcp_f32", 13), ("v_mad_u32_u24", 14),
-             ("v_lshlrev_b32", 15), ("v_addc_co_u32", 16)]
+             ("v_lshlrev_b32", 15), ("v_addc_co_u32", 16), ("v_add_u32", 17)]
 _HALF_RATE_DEFAULT = 7
 
 
@@ -127,12 +127,19 @@ def calibrate():
     return {"valu": classes, "gather": {"cycles_per_load_per_cu": cyc.value, "clock_ghz": ghz.value}}
 
 
-def sweep_roofline(evals, sweep_s, calib, counters):
-    """The sweep's rooflines from the loop's instruction mix (recorded by
-    the build from the kernel's assembly) and the calibrated costs."""
+SWEEP_FORMS = {1: ("one_pixel", "k_sweep_persistent_j1 (bilinear, half texels, FP32 store; one pixel at 64 levels "
+                                "per wave step)"),
+               2: ("pairs", "k_sweep_pairs (bilinear, half texels, FP32 store; two pixels at 32 levels per wave "
+                            "step, projected records in LDS)")}
+
+
+def sweep_roofline(evals, sweep_s, calib, counters, px):
+    """The sweep's rooflines from the instruction mix of the loop of the
+    form that ran (px pixels per wave step; recorded by the build from the
+    kernel's assembly) and the calibrated costs."""
     from paper_1909_02294_amd import build as _b
     with open(_b.MIX_JSON) as fh:
-        mix = json.load(fh)
+        mix = json.load(fh)["forms"][SWEEP_FORMS[px][0]]
     names = list(calib["valu"])
     fma = calib["valu"]["v_fma_f32"]["cycles"]
     per_iter_cycles = 0.0
@@ -143,13 +150,13 @@ def sweep_roofline(evals, sweep_s, calib, counters):
         k = next((k for prefix, k in _CLASS_OF if op.startswith(prefix)), _HALF_RATE_DEFAULT)
         c = calib["valu"][names[k]]["cycles"]
         per_iter_cycles += n * c
-        classes[op] = {"count_per_4_pixels": n, "class": names[k], "cycles": round(c, 3)}
-    px = mix["pixels_per_iteration"]
+        classes[op] = {"count_per_iteration": n, "class": names[k], "cycles": round(c, 3)}
+    steps = mix["wave_steps_per_iteration"]
     wave_steps = evals / 64.0
-    cycles_per_step = per_iter_cycles / px                       # SIMD cycles per wave step
+    cycles_per_step = per_iter_cycles / steps                    # SIMD cycles per wave step
     slots_per_step = cycles_per_step / fma                       # full-rate lane-op slots per lane
     achieved = wave_steps * slots_per_step * 64 / sweep_s
-    loads_per_step = mix["gathers"] / px
+    loads_per_step = mix["gathers"] / steps
     gcyc = calib["gather"]["cycles_per_load_per_cu"]
     gather_rate = wave_steps * loads_per_step / sweep_s
     gather_peak = 256 * CLOCK_GHZ * 1e9 / gcyc
@@ -157,11 +164,12 @@ def sweep_roofline(evals, sweep_s, calib, counters):
         "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12, "unit": "TOP/s",
         "frac": achieved / VALU_PEAK_SLOTS,
         "traffic": counters["hbm_bytes_per_launch"] if counters else None,
-        "kernel": "k_sweep_persistent_j1 (bilinear, half texels, FP32 store)",
+        "kernel": SWEEP_FORMS[px][1],
         "what": "VALU issue slots in full-rate FP32 lane-operations (157.3 TFLOP/s / 2 per FMA = 78.6 T/s); "
                 "each instruction of the sweep's inner loop weighted by its calibrated issue cost",
         "evals_per_launch": evals, "algorithmic_ops_per_eval": OPS_PER_BILINEAR_EVAL,
-        "valu_instructions_per_wave_step": mix["valu_instructions"] / px,
+        "valu_instructions_per_wave_step": mix["valu_instructions"] / steps,
+        "wave_steps_per_loop_iteration": steps,
         "issue_slots_per_eval": slots_per_step, "calib_fma_cycles": fma,
         "gather": {"loads_per_wave_step": loads_per_step, "cycles_per_load_per_cu_l1_hit": gcyc,
                    "achieved": gather_rate / 1e9, "peak": gather_peak / 1e9, "unit": "G wave-loads/s",
@@ -269,7 +277,12 @@ def bench_plain(args):
     counters = measured_counters("sweep_arc1080p_hbm.json", wl_sha)
     print("[bench] calibrating issue and gather costs", file=sys.stderr, flush=True)
     calib = calibrate()
-    roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters)
+    J, wpg, px = ivde.sweep_shape(dv, lr, base)
+    if J == 1:
+        roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters, px)
+    else:
+        roofline, classes = {"note": f"no instruction model for {J} labels per lane"}, {}
+    roofline["launch_shape"] = {"labels_per_lane": J, "waves_per_group": wpg, "pixels_per_step": px}
     out = {
         "metric": METRIC,
         "value": value,

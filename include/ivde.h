@@ -130,10 +130,14 @@ typedef struct {
  * result.  pixels_per_step 2 runs the pixel-pair sweep (each wave step two
  * pixels at 32 levels instead of one pixel at 64: half the epipolar span
  * per gather); it exists for one label per lane and images of up to 11
- * bits, elsewhere the one-pixel sweep runs; 0 picks the default, 1 the
- * one-pixel sweep.  Both sweeps compute the same quantity but add a
- * segment's pixels in a different order, so their FP32 results may differ
- * in the last bits.  sweep_events, if both non-NULL, are hipEvent_t handles
+ * bits, elsewhere the one-pixel sweep runs; 0 picks the default (the
+ * pixel-pair sweep wherever it exists), 1 the one-pixel sweep.  Both
+ * sweeps compute the same quantity but add a segment's pixels in a
+ * different order and, towards targets proven in front of every level
+ * point, the pixel-pair sweep forms a sample's projection from H p~ divided
+ * by g . p~: their FP32 results may differ in the last bits, and a sample
+ * within FP32 rounding of the bilinear validity band's edge may count in
+ * one and not the other.  sweep_events, if both non-NULL, are hipEvent_t handles
  * the call records on its stream immediately before and after the sweep
  * kernel (for timing that kernel alone). */
 typedef struct {
@@ -159,6 +163,15 @@ ivde_status ivde_cost_volume_size(int32_t n_views, const ivde_camera *cams,
                                   const ivde_label_range *labels,
                                   const ivde_options *opt, int32_t bit_depth,
                                   size_t *cost_bytes, size_t *workspace_bytes);
+
+/* The launch shape ivde_cost_volume takes for these arguments: labels per
+ * lane, waves per workgroup and pixels per wave step (1: the one-pixel
+ * sweep, 2: the pixel-pair sweep), from the options where they are set and
+ * the defaults where they are 0.  Any output pointer may be NULL; arguments
+ * are checked as for ivde_cost_volume_size.  Nothing is enqueued. */
+ivde_status ivde_sweep_shape(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
+                             const ivde_label_range *labels, const ivde_options *opt, int32_t bit_depth,
+                             int32_t *labels_per_lane, int32_t *waves_per_group, int32_t *pixels_per_step);
 
 /* The cost volume C[view][segment][label] (Sec. III-C Eq. (4) over every
  * pixel of the segment, minimum over the target views).

@@ -420,6 +420,7 @@ def bench_shapes(args):
             if not args.no_tune:
                 variants.append(("tuned", tuned))
             if args.compare_px:
+                variants.append(("one", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=1)))
                 variants.append(("pairs", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=2)))
             for name, o in variants:
                 ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -441,8 +442,8 @@ def bench_shapes(args):
                    "class": ivde.shape_class(dv, lr, base), **res,
                    "autotune_us": {"x".join(map(str, k)): v for k, v in table.items()} if table else None}
             if "pairs" in res:
-                _log(f"S={S} L={L}: pixel pairs {res['pairs']['sweep_ms']:.2f} ms, "
-                     f"{res['pairs']['evals_per_s']:.3g} evals/s")
+                _log(f"S={S} L={L}: one pixel {res['one']['sweep_ms']:.2f} ms, pixel pairs "
+                     f"{res['pairs']['sweep_ms']:.2f} ms, {res['pairs']['evals_per_s']:.3g} evals/s")
             _log(f"S={S} L={L}: {res['j1']['sweep_ms']:.2f} ms, {res['j1']['evals_per_s']:.3g} evals/s" +
                  ("" if args.no_tune else f" (tuned {res['tuned']['labels_per_lane']}x"
                                           f"{res['tuned']['waves_per_group']}: {res['tuned']['sweep_ms']:.2f} ms)"))
@@ -472,15 +473,17 @@ def bench_precision(args):
     stream = torch.cuda.current_stream()
     out, vols, labs = {}, {}, {}
     for name, dt in (("f16", ivde.F16), ("f32", ivde.F32)):
-        C, ws = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, dt))
+        C, ws = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, dt, pixels_per_step=args.pixels_per_step))
         lab = torch.empty(dv.rows, dtype=torch.int32, device="cuda")
         for _ in range(args.warmup):
-            ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, dt), workspace=ws, out=C, stream=stream)
+            ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, dt, pixels_per_step=args.pixels_per_step),
+                             workspace=ws, out=C, stream=stream)
         torch.cuda.synchronize()
         K = args.steps
         step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         sweep_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-        opts = [ivde.options(ivde.BILINEAR, dt, sweep_events=e) for e in sweep_ev]
+        opts = [ivde.options(ivde.BILINEAR, dt, sweep_events=e, pixels_per_step=args.pixels_per_step)
+                for e in sweep_ev]
         t = time.perf_counter()
         for (a, b), o in zip(step_ev, opts):
             a.record(stream)

@@ -5,6 +5,7 @@ import concurrent.futures
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -72,27 +73,18 @@ def build(verbose: bool = False, sanitize: bool = False, stage_texels: int = 0) 
 
 
 MIX_JSON = LIB + ".sweep_mix.json"
-SWEEP_SYMBOL = "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil"
+# the bilinear FP32-store instantiations of the two sweep forms
+SWEEP_SYMBOLS = {
+    "one_pixel": "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "pairs": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+}
 
 
-def sweep_mix(verbose: bool = False) -> dict:
-    """Instruction counts of the sweep's hot loop, from the gfx950 assembly
-    of this build: the one-label-per-lane bilinear FP32-store kernel's
-    four-pixel loop (8 buffer gathers) for target views proven in front of
-    every level point (the fewest compares of its three such loops).
-    Written next to the library for the benchmark's issue model."""
-    import json
+def _loops(text: str, symbol: str):
+    """(name, instruction mnemonics) of every block of `symbol` that ends in
+    a branch back to itself."""
     import re
-    import tempfile
-
-    with tempfile.TemporaryDirectory() as td:
-        asm = os.path.join(td, "kernels.s")
-        r = subprocess.run([HIPCC, *COMMON, "--cuda-device-only", "-S", "-o", asm, os.path.join(CSRC, "kernels.hip")],
-                           capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"assembly of kernels.hip failed:\n{r.stderr}")
-        text = open(asm).read()
-    start = text.index(SWEEP_SYMBOL + ":")
+    start = text.index(symbol + ":")
     end = text.index(".Lfunc_end", start)
     blocks, name, body = {}, None, []
     for line in text[start:end].splitlines():
@@ -107,26 +99,56 @@ def sweep_mix(verbose: bool = False) -> dict:
                 body.append(ins)
     if name:
         blocks[name] = body
-    loops = []
-    for name, body in blocks.items():
-        if body and body[-1].split()[0].startswith("s_cbranch") and body[-1].split()[-1] == name:
-            ops = [b.split()[0] for b in body]
-            if sum(o == "buffer_load_dwordx4" for o in ops) == 8:
-                loops.append((sum(o.startswith("v_cmp") for o in ops), name, ops))
-    if not loops:
-        raise RuntimeError("sweep loop not found in the assembly")
-    _, name, ops = min(loops)
-    counts = {}
-    for o in ops:
-        counts[o] = counts.get(o, 0) + 1
-    mix = {"kernel": SWEEP_SYMBOL, "loop": name, "pixels_per_iteration": 4,
-           "valu_instructions": sum(v for k, v in counts.items() if k.startswith("v_")),
-           "gathers": counts.get("buffer_load_dwordx4", 0), "counts": dict(sorted(counts.items()))}
+    return [(n, [b.split()[0] for b in body]) for n, body in blocks.items()
+            if body and body[-1].split()[0].startswith("s_cbranch") and body[-1].split()[-1] == n]
+
+
+def sweep_mix(verbose: bool = False) -> dict:
+    """Instruction counts of the hot loops of both sweep forms, from the
+    gfx950 assembly of this build, for target views proven in front of every
+    level point (the unrolled loops with the fewest compares).  One-pixel sweep: the
+    four-pixel loop of the bilinear FP32-store kernel (8 buffer gathers, one
+    wave step per pixel).  Pixel-pair sweep: the loop over projected records
+    (2 gathers and one LDS record read per wave step of two pixels at 32
+    levels).  Written next to the library for the benchmark's issue model."""
+    import json
+
+    with tempfile.TemporaryDirectory() as td:
+        asm = os.path.join(td, "kernels.s")
+        r = subprocess.run([HIPCC, *COMMON, "--cuda-device-only", "-S", "-o", asm, os.path.join(CSRC, "kernels.hip")],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"assembly of kernels.hip failed:\n{r.stderr}")
+        text = open(asm).read()
+    forms = {}
+    for form, sym in SWEEP_SYMBOLS.items():
+        cands = []
+        for name, ops in _loops(text, sym):
+            gathers = sum(o == "buffer_load_dwordx4" for o in ops)
+            if form == "one_pixel" and gathers == 8:
+                steps = 4
+            elif form == "pairs" and gathers >= 2 and "ds_read_u16" in ops:
+                steps = gathers // 2
+            else:
+                continue
+            cands.append((-steps, sum(o.startswith("v_cmp") for o in ops), name, ops, steps))
+        if not cands:
+            raise RuntimeError(f"{form} sweep loop not found in the assembly")
+        _, _, name, ops, steps = min(cands)     # the unrolled loop, then the fewest compares
+        counts = {}
+        for o in ops:
+            counts[o] = counts.get(o, 0) + 1
+        forms[form] = {"kernel": sym, "loop": name, "wave_steps_per_iteration": steps,
+                       "valu_instructions": sum(v for k, v in counts.items() if k.startswith("v_")),
+                       "gathers": counts.get("buffer_load_dwordx4", 0), "counts": dict(sorted(counts.items()))}
+    mix = {"forms": forms}
     with open(MIX_JSON, "w") as fh:
         json.dump(mix, fh, indent=1)
     if verbose:
-        print(f"sweep loop {name}: {mix['valu_instructions']} VALU instructions, {mix['gathers']} gathers per "
-              f"4 pixels -> {MIX_JSON}")
+        for form, m in forms.items():
+            print(f"{form} sweep loop {m['loop']}: {m['valu_instructions']} VALU instructions, {m['gathers']} "
+                  f"gathers per {m['wave_steps_per_iteration']} wave steps")
+        print(f"-> {MIX_JSON}")
     return mix
 
 

@@ -864,11 +864,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // the epipolar stretch of 32 levels at two neighbouring pixels, which touch
 // almost the same texels, instead of the stretch of 64 levels: half the
 // cache lines per gather.  The segment's pixel records are staged in the
-// wave's slice of LDS as {x, y, Y | Cb, Cr} (FP16 colours, exact for samples
-// up to 11 bits), read back by each lane for its own pixel; g . p~ is
-// recomputed from (x, y) as the index build computes it.  The two halves'
-// sums and counts meet through one cross-lane exchange per (target, pass).
-constexpr int kPairStage = 256;   // records one wave stages at a time (16 B each)
+// wave's slice of LDS per (target, chunk of up to 256 records), read back by
+// each lane for its own pixel, and both 32-level passes run over a chunk
+// while it is staged.  For a target proven in front of every level point
+// the stage holds the projection base already divided by g . p~ (see
+// stage_projected), so a step forms h with three multiply-adds; otherwise
+// it holds {x, y, Y | Cb, Cr} and a step forms q = H p~ and g . p~ as the
+// one-pixel sweep does.  Colours are FP16 (exact for samples up to 11 bits).
+// The two halves' sums and counts meet through one cross-lane exchange per
+// (target, pass).
+constexpr int kPairStage = 256;   // records one wave stages at a time (16 B + 2 B each)
 
 __device__ __forceinline__ uint32_t pack_h2(float a, float b)
 {
@@ -888,6 +893,36 @@ __device__ __forceinline__ void stage_records(const float *__restrict__ pix, int
             const float2 r1 = ldg(reinterpret_cast<const float2 *>(r + 4));
             st[t] = make_uint4(__float_as_uint(r0.x), __float_as_uint(r0.y), pack_h2(r0.w, r1.x),
                                pack_h2(r1.y, 0.f));
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Records [i0, i0 + n) of the view towards a target proven in front of every
+// level point (n <= kPairStage).  The homogeneous target point of a pixel at
+// level sigma is h = q + sigma (g . p~) e with q = H p~; dividing by g . p~
+// (non-zero there, since the level point has finite positive depth) gives
+// q' + sigma e with q' = q / (g . p~), which projects to the same pixel, and
+// the target's validity needs no sign test.  The stage holds {q'x, q'y,
+// q'z, Y | Cb} and the Cr half beside it, in cr.
+__device__ __forceinline__ void stage_projected(const float *__restrict__ pix, int i0, int n, const float (&H)[9],
+                                                uint4 *st, uint16_t *cr)
+{
+    const int lane = lane_id();
+    __builtin_amdgcn_wave_barrier();   // earlier reads of the stage come first
+    for (int t0 = 0; t0 < n; t0 += kWave) {
+        const int t = t0 + lane;
+        if (t < n) {
+            const float *r = pix + 8 * (int64_t)(i0 + t);
+            const float4 r0 = ldg(reinterpret_cast<const float4 *>(r));
+            const float2 r1 = ldg(reinterpret_cast<const float2 *>(r + 4));
+            const float x = r0.x, y = r0.y, rg = 1.0f / r0.z;   // r0.z = g . p~ of the index build
+            const float qx = fmaf(H[0], x, fmaf(H[1], y, H[2])) * rg;
+            const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5])) * rg;
+            const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8])) * rg;
+            st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz), pack_h2(r0.w, r1.x));
+            cr[t] = (uint16_t)pack_h2(r1.y, 0.f);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1023,6 +1058,59 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
     }
 }
 
+// Pairs of projected records [0, m) (stage_projected) towards a target
+// proven in front of every level point, at one pass (lane k of either half
+// at level sig): as sweep_pair_records with h = q' + sig e.
+template <int PU, bool BIL>
+__device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint16_t *cr, int m, int h,
+                                                     const Target &T, float sig, float &acc, uint64_t &acci,
+                                                     int &cnt)
+{
+    int i = 0;
+    for (; i + 2 * PU <= m; i += 2 * PU) {
+        Sample<BIL, false> smp[PU];
+        float ax[PU], ay[PU];
+        bool val[PU];
+        uint32_t rz[PU], rw[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const uint4 r = st[i + 2 * u + h];
+            rz[u] = r.w;
+            rw[u] = cr[i + 2 * u + h];
+            project_pair<BIL, 2>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp[u],
+                                 ax[u], ay[u], val[u]);
+        }
+        if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const float d = consume_pair<BIL>(smp[u], ax[u], ay[u], rz[u], rw[u]);
+            if constexpr (BIL)
+                acc += val[u] ? d : 0.f;
+            else
+                acci += val[u] ? (uint32_t)d : 0u;
+            cnt += val[u] ? 1 : 0;
+        }
+    }
+    for (; i < m; i += 2) {
+        const int j = i + h;
+        const bool here = j < m;
+        const int jj = here ? j : m - 1;
+        const uint4 r = st[jj];
+        Sample<BIL, false> smp;
+        float ax, ay;
+        bool val;
+        project_pair<BIL, 2>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp, ax, ay,
+                             val);
+        val &= here;
+        const float d = consume_pair<BIL>(smp, ax, ay, r.w, cr[jj]);
+        if constexpr (BIL)
+            acc += val ? d : 0.f;
+        else
+            acci += val ? (uint32_t)d : 0u;
+        cnt += val ? 1 : 0;
+    }
+}
+
 // Pairs each wave keeps in flight in the pixel-pair sweep.  Three fit 64
 // VGPRs; evaluating both of a lane's levels per pixel (the projection base
 // formed once for both) fits only one pixel in flight and was slower at 128
@@ -1032,7 +1120,8 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
 #endif
 
 template <bool BIL, bool F16OUT>
-__device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st)
+__device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
+                                                 uint16_t *cr)
 {
     constexpr int PU = IVDE_PAIR_INFLIGHT;
     const int lane = lane_id();
@@ -1065,8 +1154,6 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
         best[q] = __builtin_inff();
     }
     const int np = p1 - p0;
-    const bool resident = np <= kPairStage;   // staged once for every target
-    if (resident && np > 0) stage_records(pix, p0, np, st);
 
     for (int ti = 0; ti < nt; ++ti) {
         const int c2 = ldu(&vc->targets[ti]);
@@ -1085,32 +1172,43 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
         T.e1 = hc.z;
         T.e2 = hc.w;
         const int front = front_all ? (((front_targets >> c2) & 1u) ? 2 : 1) : 0;
-        for (int q = 0; q < passes; ++q) {
-            float acc = 0.f;
-            uint64_t acci = 0;
-            int cnt = 0;
-            for (int b0 = 0; b0 < np; b0 += kPairStage) {
-                const int m = min(kPairStage, np - b0);
-                if (!resident) stage_records(pix, p0 + b0, m, st);
-                if (front == 2)
-                    sweep_pair_records<PU, BIL, 2>(st, m, h, H, g, T, sig[q], acc, acci, cnt);
-                else if (front == 1)
-                    sweep_pair_records<PU, BIL, 1>(st, m, h, H, g, T, sig[q], acc, acci, cnt);
-                else
-                    sweep_pair_records<PU, BIL, 0>(st, m, h, H, g, T, sig[q], acc, acci, cnt);
+        float acc[2] = {0.f, 0.f};
+        uint64_t acci[2] = {0, 0};
+        int cnt[2] = {0, 0};
+        for (int b0 = 0; b0 < np; b0 += kPairStage) {
+            const int m = min(kPairStage, np - b0);
+            if (front == 2) {
+                stage_projected(pix, p0 + b0, m, H, st, cr);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (q < passes) sweep_pair_projected<PU, BIL>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+            } else {
+                stage_records(pix, p0 + b0, m, st);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    if (q >= passes) continue;
+                    if (front == 1)
+                        sweep_pair_records<PU, BIL, 1>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
+                    else
+                        sweep_pair_records<PU, BIL, 0>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
+                }
             }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q >= passes) continue;
             // the two halves' sums and counts: one exchange across the halves
-            cnt += __shfl_xor(cnt, kWave / 2);
+            const int c_all = cnt[q] + __shfl_xor(cnt[q], kWave / 2);
             float sum;
             if constexpr (BIL) {
-                sum = acc + __shfl_xor(acc, kWave / 2);
+                sum = acc[q] + __shfl_xor(acc[q], kWave / 2);
             } else {
-                const uint32_t lo = (uint32_t)acci, hi = (uint32_t)(acci >> 32);
+                const uint32_t lo = (uint32_t)acci[q], hi = (uint32_t)(acci[q] >> 32);
                 const uint64_t other = ((uint64_t)(uint32_t)__shfl_xor((int)hi, kWave / 2) << 32) |
                                        (uint32_t)__shfl_xor((int)lo, kWave / 2);
-                sum = (float)(acci + other);
+                sum = (float)(acci[q] + other);
             }
-            if (cnt > 0) best[q] = fminf(best[q], sum / ((float)cnt * norm));
+            if (c_all > 0) best[q] = fminf(best[q], sum / ((float)c_all * norm));
         }
     }
 
@@ -1133,7 +1231,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     int32_t *__restrict__ cursors, int64_t max_tasks)
 {
     extern __shared__ uint4 pair_stage[];
-    uint4 *st = pair_stage + (threadIdx.x / kWave) * kPairStage;
+    const int wave = (int)(threadIdx.x / kWave), wpg = (int)(blockDim.x / kWave);
+    uint4 *st = pair_stage + wave * kPairStage;
+    uint16_t *cr = reinterpret_cast<uint16_t *>(pair_stage + wpg * kPairStage) + wave * kPairStage;
     const int lane = lane_id();
     const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
     // per-XCD ranges and work stealing as in sweep_persistent_body
@@ -1147,7 +1247,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             t = uniform(__shfl(t, 0));
             if (t >= n) break;
             const Task task = ldu_task(tasks + lo + t);
-            sweep_task_pairs<BIL, F16OUT>(probs + task.problem, task, st);
+            sweep_task_pairs<BIL, F16OUT>(probs + task.problem, task, st, cr);
         }
     }
 }
@@ -1360,8 +1460,9 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
     return hipGetLastError();
 }
 
-// Dynamic LDS of the pixel-pair sweep: one record stage per wave.
-static size_t pair_stage_bytes(int wpg) { return (size_t)wpg * kPairStage * sizeof(uint4); }
+// Dynamic LDS of the pixel-pair sweep: one record stage per wave (16-byte
+// records, then the 2-byte Cr halves of the projected form).
+static size_t pair_stage_bytes(int wpg) { return (size_t)wpg * kPairStage * (sizeof(uint4) + sizeof(uint16_t)); }
 
 template <int J, bool BIL, bool TEXF32, bool F16OUT>
 static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursors,

@@ -91,6 +91,7 @@ _P = ctypes.c_void_p
 _I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 SIGNATURES = {
     "ivde_cost_volume_size": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P]),
+    "ivde_sweep_shape": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _P]),
     "ivde_cost_volume": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P]),
     "ivde_cost_volume_noalloc": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
     "ivde_argmin": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
@@ -290,6 +291,16 @@ def sizes(dv: DeviceViews, lr: LabelRange, opt: Options):
     check(lib.ivde_cost_volume_size(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt),
                                     dv.bit_depth, ctypes.byref(cb), ctypes.byref(wb)))
     return cb.value, wb.value
+
+
+def sweep_shape(dv: DeviceViews, lr: LabelRange, opt: Options):
+    """(labels_per_lane, waves_per_group, pixels_per_step) of the sweep
+    ivde_cost_volume runs for these arguments."""
+    lib = load()
+    j, w, p = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib.ivde_sweep_shape(dv.n, dv.c_cams, dv.c_segs, ctypes.byref(lr), ctypes.byref(opt), dv.bit_depth,
+                               ctypes.byref(j), ctypes.byref(w), ctypes.byref(p)))
+    return j.value, w.value, p.value
 
 
 def alloc_bytes(nbytes, device="cuda"):

@@ -27,9 +27,16 @@ TIE_AWARE_MIN = 0.999
 TIE_F64 = 1.2e-12
 
 
+# pixels per wave step run_gpu asks for when a test does not say (0: the
+# library's default); a test module may set it to run its cases again with
+# the other sweep form
+SWEEP_PX = 0
+
+
 def run_gpu(ns, sampling=None, cost_dtype=ivde.F32, targets=ivde.TARGETS_ALL, target_mask=None,
             depth_ref=ivde.REF_RIG_CENTER, labels_per_lane=0, waves_per_group=0, pixels_per_step=0):
     dv = ivde.DeviceViews(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift)
+    pixels_per_step = pixels_per_step or SWEEP_PX
     if sampling is None:
         sampling = ivde.BILINEAR if ns.bilinear else ivde.NEAREST
     lr = ivde.label_range(ns.z_near, ns.z_far, ns.num_labels, depth_ref)

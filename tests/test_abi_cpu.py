@@ -96,6 +96,36 @@ def test_size_query(lib):
     assert cb.value == n * S * L * 2
 
 
+def test_sweep_shape_query(lib):
+    """The launch shape the plain call takes: the pixel-pair sweep by default
+    (one label per lane, half texels), the one-pixel sweep where asked for,
+    with more labels per lane, or with FP32 texels (12 bits and more)."""
+    n, w, h, S = 3, 40, 30, 17
+    lr = ivde.label_range(1.0, 5.0, 256)
+
+    def shape(opt, bits=10):
+        j, wpg, px = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        st = lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr), ctypes.byref(opt), bits,
+                                  ctypes.byref(j), ctypes.byref(wpg), ctypes.byref(px))
+        assert st == ivde.IVDE_OK, st
+        return j.value, wpg.value, px.value
+
+    assert shape(ivde.options(ivde.BILINEAR, ivde.F32)) == (1, 4, 2)
+    assert shape(ivde.options(ivde.NEAREST, ivde.F16)) == (1, 4, 2)
+    assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=8) == (1, 4, 2)
+    assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=12) == (1, 4, 1)
+    assert shape(ivde.options(pixels_per_step=1)) == (1, 4, 1)
+    assert shape(ivde.options(labels_per_lane=2, waves_per_group=2)) == (2, 2, 1)
+    assert shape(ivde.options(labels_per_lane=2, pixels_per_step=2)) == (2, 4, 1)
+    # outputs may be NULL; argument errors as for the size query
+    assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
+                                ctypes.byref(ivde.options()), 10, None, None, None) == ivde.IVDE_OK
+    assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
+                                ctypes.byref(ivde.options()), 7, None, None, None) == ivde.IVDE_EINVAL
+    assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
+                                ctypes.byref(ivde.options(pixels_per_step=3)), 10, None, None, None) == ivde.IVDE_EINVAL
+
+
 @pytest.mark.parametrize("field,value", [
     ("n_views", 0), ("n_views", 33), ("z_near", -1.0), ("z_far", float("nan")), ("num_labels", 0),
     ("depth_ref", 7), ("sampling", 5), ("cost_dtype", 9), ("labels_per_lane", 3), ("waves_per_group", 8),

@@ -48,12 +48,16 @@ def test_small_arc_bilinear_420(seed):
     assert r["max_err"] <= 1e-4, r
 
 
-@pytest.mark.parametrize("labels_per_lane,waves", [(1, 1), (2, 2), (4, 4), (8, 1)])
-def test_launch_shapes_give_identical_results(labels_per_lane, waves):
-    _print_case(f"launch shape J={labels_per_lane} wpg={waves}")
+@pytest.mark.parametrize("labels_per_lane,waves,px", [(1, 1, 2), (1, 2, 2), (1, 1, 1), (2, 2, 1), (4, 4, 1),
+                                                      (8, 1, 1)])
+def test_launch_shapes_give_identical_results(labels_per_lane, waves, px):
+    """Within one sweep form (pixels per wave step) the launch shape never
+    changes a result: each shape against one label per lane at 4 waves per
+    group (more labels per lane run the one-pixel form)."""
+    _print_case(f"launch shape J={labels_per_lane} wpg={waves} px={px}")
     wl = P.synth.make_small_arc(seed=9, n_views=3, width=97, height=61, n_segments=60, num_labels=130)
-    G0, _ = run_gpu(wl)
-    G1, _ = run_gpu(wl, labels_per_lane=labels_per_lane, waves_per_group=waves)
+    G0, _ = run_gpu(wl, labels_per_lane=1, waves_per_group=4, pixels_per_step=px)
+    G1, _ = run_gpu(wl, labels_per_lane=labels_per_lane, waves_per_group=waves, pixels_per_step=px)
     assert np.array_equal(G0, G1)
 
 

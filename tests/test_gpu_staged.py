@@ -35,7 +35,7 @@ def _workload(case):
 def _cost(wl):
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
-    C, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1))
+    C, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=1))
     torch.cuda.synchronize()
     return C.cpu().numpy()
 
@@ -103,7 +103,7 @@ for i, case in enumerate(json.loads(sys.argv[2])):
     wl = synth.make_small_arc(seed=seed, n_views=n, width=w, height=h, n_segments=S, num_labels=L)
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
-    C, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1))
+    C, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=1))
     torch.cuda.synchronize()
     np.save(f"{sys.argv[3]}/staged{i}.npy", C.cpu().numpy())
 print("loaded", ivde.LIB_PATH)
