@@ -410,7 +410,7 @@ def bench_shapes(args):
         _log(f"S={S}: generated in {time.perf_counter() - t0:.1f} s, {dv.rows} rows")
         for L in lab_list:
             lr = ivde.label_range(wl.z_near, wl.z_far, L)
-            base = ivde.options(ivde.BILINEAR, ivde.F32)
+            base = ivde.options(ivde.BILINEAR, ivde.F32, pixels_per_step=args.pixels_per_step)
             if args.no_tune:
                 tuned, table = base, None
             else:

@@ -1111,13 +1111,17 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
     }
 }
 
-// Pairs each wave keeps in flight in the pixel-pair sweep.  Three fit 64
-// VGPRs; evaluating both of a lane's levels per pixel (the projection base
-// formed once for both) fits only one pixel in flight and was slower at 128
-// levels (20.7 against 19.3 ms on the 8-view 1080p arc rig).
+// Pairs each wave keeps in flight in the pixel-pair sweep, and the waves per
+// SIMD its kernel is compiled for.  Three pairs at six waves take 76 VGPRs
+// with nothing spilled; on the 8-view 1080p arc rig they beat eight waves
+// (64 VGPRs, spills outside the pixel loop) by 3-6% at 128, 256 and 512
+// levels, and two or four pairs at four to six waves by up to 2%.
+// Evaluating both of a lane's levels per pixel (the projection base formed
+// once for both) fits only one pixel in flight and was slower.
 #ifndef IVDE_PAIR_INFLIGHT
 #define IVDE_PAIR_INFLIGHT 3
 #endif
+#define IVDE_PAIR_WAVES_PER_SIMD 6
 
 template <bool BIL, bool F16OUT>
 __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
@@ -1226,7 +1230,7 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
 }
 
 template <bool BIL, bool F16OUT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_pairs(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(IVDE_PAIR_WAVES_PER_SIMD, IVDE_PAIR_WAVES_PER_SIMD))) void k_sweep_pairs(
     const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
     int32_t *__restrict__ cursors, int64_t max_tasks)
 {
