@@ -127,53 +127,80 @@ def calibrate():
     return {"valu": classes, "gather": {"cycles_per_load_per_cu": cyc.value, "clock_ghz": ghz.value}}
 
 
-SWEEP_FORMS = {1: ("one_pixel", "k_sweep_persistent_j1 (bilinear, half texels, FP32 store; one pixel at 64 levels "
-                                "per wave step)"),
-               2: ("pairs", "k_sweep_pairs (bilinear, half texels, FP32 store; two pixels at 32 levels per wave "
-                            "step, projected records in LDS)")}
+SWEEP_FORMS = {1: "k_sweep_persistent_j1 (bilinear, half texels, FP32 store; one pixel at 64 levels per wave step)",
+               2: "k_sweep_pairs (bilinear, half texels, FP32 store; two pixels at 32 levels per wave step, records "
+                  "staged in LDS)"}
 
 
-def sweep_roofline(evals, sweep_s, calib, counters, px):
-    """The sweep's rooflines from the instruction mix of the loop of the
-    form that ran (px pixels per wave step; recorded by the build from the
-    kernel's assembly) and the calibrated costs."""
+def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None):
+    """The sweep's rooflines: VALU issue and texture gathers.  Each loop's
+    instruction mix is recorded by the build from the kernel's assembly and
+    priced with the calibrated issue costs; for the pixel-pair sweep the
+    loops are weighted by the wave steps the kernel counted in each (steps =
+    (all, on projected records, inside the validity band), from
+    ivde_workspace_sweep_steps).  The binding unit is the one nearer its
+    ceiling."""
     from paper_1909_02294_amd import build as _b
     with open(_b.MIX_JSON) as fh:
-        mix = json.load(fh)["forms"][SWEEP_FORMS[px][0]]
+        forms = json.load(fh)["forms"]
     names = list(calib["valu"])
     fma = calib["valu"]["v_fma_f32"]["cycles"]
-    per_iter_cycles = 0.0
-    classes = {}
-    for op, n in mix["counts"].items():
-        if not op.startswith("v_"):
-            continue
-        k = next((k for prefix, k in _CLASS_OF if op.startswith(prefix)), _HALF_RATE_DEFAULT)
-        c = calib["valu"][names[k]]["cycles"]
-        per_iter_cycles += n * c
-        classes[op] = {"count_per_iteration": n, "class": names[k], "cycles": round(c, 3)}
-    steps = mix["wave_steps_per_iteration"]
-    wave_steps = evals / 64.0
-    cycles_per_step = per_iter_cycles / steps                    # SIMD cycles per wave step
-    slots_per_step = cycles_per_step / fma                       # full-rate lane-op slots per lane
-    achieved = wave_steps * slots_per_step * 64 / sweep_s
-    loads_per_step = mix["gathers"] / steps
+
+    def loop_cycles(mix):
+        cyc, classes = 0.0, {}
+        for op, n in mix["counts"].items():
+            if not op.startswith("v_"):
+                continue
+            k = next((k for prefix, k in _CLASS_OF if op.startswith(prefix)), _HALF_RATE_DEFAULT)
+            c = calib["valu"][names[k]]["cycles"]
+            cyc += n * c
+            classes[op] = {"count_per_iteration": n, "class": names[k], "cycles": round(c, 3)}
+        return cyc / mix["wave_steps_per_iteration"], mix["valu_instructions"] / mix["wave_steps_per_iteration"], classes
+
+    if px == 1:
+        cyc, ins, classes = loop_cycles(forms["one_pixel"])
+        by_loop = {"one_pixel": evals / 64.0}
+        loops = {"one_pixel": classes}
+        simd_cycles = by_loop["one_pixel"] * cyc
+        instructions = by_loop["one_pixel"] * ins
+    else:
+        all_, proj, inside = steps
+        by_loop = {"pairs_inside": inside, "pairs_tested": proj - inside, "pairs_records": all_ - proj}
+        simd_cycles = instructions = 0.0
+        loops = {}
+        for name, n in by_loop.items():
+            cyc, ins, classes = loop_cycles(forms[name])
+            simd_cycles += n * cyc
+            instructions += n * ins
+            loops[name] = classes
+    issued_steps = sum(by_loop.values())
+    slots = simd_cycles / fma                                     # full-rate issue slots per lane, all wave steps
+    valu_achieved = slots * 64 / sweep_s
+    valu = {"achieved": valu_achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12, "unit": "TOP/s",
+            "frac": valu_achieved / VALU_PEAK_SLOTS,
+            "what": "VALU issue slots in full-rate FP32 lane-operations (157.3 TFLOP/s / 2 per FMA = 78.6 T/s); "
+                    "each instruction of the sweep's inner loops weighted by its calibrated issue cost",
+            "valu_instructions_per_wave_step": instructions / issued_steps,
+            "issue_slots_per_eval": slots * 64 / evals, "calib_fma_cycles": fma,
+            "algorithmic_ops_per_eval": OPS_PER_BILINEAR_EVAL}
     gcyc = calib["gather"]["cycles_per_load_per_cu"]
-    gather_rate = wave_steps * loads_per_step / sweep_s
+    gather_algo = evals / 64.0 * 2                               # two 16-byte row gathers per 64 evaluations
+    gather_rate = gather_algo / sweep_s
     gather_peak = 256 * CLOCK_GHZ * 1e9 / gcyc
+    gather = {"achieved": gather_rate / 1e9, "peak": gather_peak / 1e9, "unit": "G wave-loads/s",
+              "frac": gather_rate / gather_peak, "loads_per_wave_step": 2.0, "cycles_per_load_per_cu_l1_hit": gcyc,
+              "what": "wave-level 16-byte buffer gathers (two per 64 evaluations) against the texture path's "
+                      "calibrated rate for L1 hits, 256 CUs x 2.4 GHz / cycles per gather"}
+    primary, other = (gather, "valu") if gather["frac"] >= valu["frac"] else (valu, "gather")
     out = {
-        "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12, "unit": "TOP/s",
-        "frac": achieved / VALU_PEAK_SLOTS,
+        "bound": "gather" if primary is gather else "alu",
+        "achieved": primary["achieved"], "peak": primary["peak"], "unit": primary["unit"], "frac": primary["frac"],
         "traffic": counters["hbm_bytes_per_launch"] if counters else None,
-        "kernel": SWEEP_FORMS[px][1],
-        "what": "VALU issue slots in full-rate FP32 lane-operations (157.3 TFLOP/s / 2 per FMA = 78.6 T/s); "
-                "each instruction of the sweep's inner loop weighted by its calibrated issue cost",
-        "evals_per_launch": evals, "algorithmic_ops_per_eval": OPS_PER_BILINEAR_EVAL,
-        "valu_instructions_per_wave_step": mix["valu_instructions"] / steps,
-        "wave_steps_per_loop_iteration": steps,
-        "issue_slots_per_eval": slots_per_step, "calib_fma_cycles": fma,
-        "gather": {"loads_per_wave_step": loads_per_step, "cycles_per_load_per_cu_l1_hit": gcyc,
-                   "achieved": gather_rate / 1e9, "peak": gather_peak / 1e9, "unit": "G wave-loads/s",
-                   "frac": gather_rate / gather_peak},
+        "kernel": SWEEP_FORMS[px],
+        "what": primary["what"],
+        "evals_per_launch": evals,
+        "wave_steps": {k: int(v) for k, v in by_loop.items()},
+        "valu": valu, "gather": gather,
         "l2_hit_rate": counters["l2_hit_rate"] if counters else None,
     }
     if counters:
@@ -181,7 +208,7 @@ def sweep_roofline(evals, sweep_s, calib, counters, px):
                                "frac": counters["hbm_bytes_per_launch"] / sweep_s / 1e9 / HBM_PEAK_GBS,
                                "note": "HBM bytes from FETCH_SIZE and WRITE_SIZE (scaled by a copy of known "
                                        "size) over the sweep time: not the binding unit"}
-    return out, classes
+    return out, loops
 
 
 def cpu_baseline(wl, target_seconds=15.0, seed=7):
@@ -279,7 +306,8 @@ def bench_plain(args):
     calib = calibrate()
     J, wpg, px = ivde.sweep_shape(dv, lr, base)
     if J == 1:
-        roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters, px)
+        steps = ivde.sweep_steps(ws, stream) if px == 2 else None
+        roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters, px, steps)
     else:
         roofline, classes = {"note": f"no instruction model for {J} labels per lane"}, {}
     roofline["launch_shape"] = {"labels_per_lane": J, "waves_per_group": wpg, "pixels_per_step": px}

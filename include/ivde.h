@@ -223,6 +223,17 @@ ivde_status ivde_cost_volume_noalloc(int32_t n_views, const ivde_camera *cams, c
  * Synchronises `stream`. */
 ivde_status ivde_workspace_status(const void *workspace, ivde_stream stream);
 
+/* After the stream that ran ivde_cost_volume with this workspace has
+ * completed: the wave steps its pixel-pair sweep took (one step = two
+ * pixels of a segment towards one target at 32 levels), in total, on
+ * records whose projection base was staged already divided by g . p~
+ * (targets proven in front of every level point), and on chunks of records
+ * whose every sample was shown to lie inside the bilinear validity band,
+ * which run without per-sample validity tests.  All three are 0 after a
+ * one-pixel sweep.  For performance accounting; synchronises `stream`. */
+ivde_status ivde_workspace_sweep_steps(const void *workspace, ivde_stream stream, int64_t *steps_total,
+                                       int64_t *steps_projected, int64_t *steps_inside);
+
 /* ---------------------------------------------------------------- batched form */
 
 /* One frame of a batch: the same fields as one ivde_cost_volume call. */

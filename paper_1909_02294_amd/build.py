@@ -104,13 +104,17 @@ def _loops(text: str, symbol: str):
 
 
 def sweep_mix(verbose: bool = False) -> dict:
-    """Instruction counts of the hot loops of both sweep forms, from the
-    gfx950 assembly of this build, for target views proven in front of every
-    level point (the unrolled loops with the fewest compares).  One-pixel sweep: the
-    four-pixel loop of the bilinear FP32-store kernel (8 buffer gathers, one
-    wave step per pixel).  Pixel-pair sweep: the loop over projected records
-    (2 gathers and one LDS record read per wave step of two pixels at 32
-    levels).  Written next to the library for the benchmark's issue model."""
+    """Instruction counts of the sweep's hot loops, from the gfx950 assembly
+    of this build (the bilinear FP32-store kernels; each loop's unrolled
+    copy, the one with the fewest compares where the kernel has several):
+    one_pixel, the one-pixel sweep's four-pixel loop for targets proven in
+    front of every level point (8 gathers, one wave step per pixel); and the
+    pixel-pair sweep's loops over three pairs (6 gathers, one LDS record read
+    per wave step of two pixels at 32 levels): pairs_inside on projected
+    records of chunks inside the validity band (no per-sample tests),
+    pairs_tested on projected records with the band test, pairs_records on
+    {x, y} records with the sign tests.  Written next to the library for the
+    benchmark's issue model."""
     import json
 
     with tempfile.TemporaryDirectory() as td:
@@ -120,21 +124,23 @@ def sweep_mix(verbose: bool = False) -> dict:
         if r.returncode != 0:
             raise RuntimeError(f"assembly of kernels.hip failed:\n{r.stderr}")
         text = open(asm).read()
+    wanted = {
+        "one_pixel": (SWEEP_SYMBOLS["one_pixel"], lambda ops, g: g == 8, 4),
+        "pairs_inside": (SWEEP_SYMBOLS["pairs"],
+                         lambda ops, g: g == 6 and "ds_read_u16" in ops and "v_med3_f32" not in ops, 3),
+        "pairs_tested": (SWEEP_SYMBOLS["pairs"],
+                         lambda ops, g: g == 6 and "ds_read_u16" in ops and "v_med3_f32" in ops, 3),
+        "pairs_records": (SWEEP_SYMBOLS["pairs"], lambda ops, g: g == 6 and "ds_read_u16" not in ops, 3),
+    }
     forms = {}
-    for form, sym in SWEEP_SYMBOLS.items():
+    for form, (sym, pick, steps) in wanted.items():
         cands = []
         for name, ops in _loops(text, sym):
-            gathers = sum(o == "buffer_load_dwordx4" for o in ops)
-            if form == "one_pixel" and gathers == 8:
-                steps = 4
-            elif form == "pairs" and gathers >= 2 and "ds_read_u16" in ops:
-                steps = gathers // 2
-            else:
-                continue
-            cands.append((-steps, sum(o.startswith("v_cmp") for o in ops), name, ops, steps))
+            if pick(ops, sum(o == "buffer_load_dwordx4" for o in ops)):
+                cands.append((sum(o.startswith("v_cmp") for o in ops), name, ops))
         if not cands:
             raise RuntimeError(f"{form} sweep loop not found in the assembly")
-        _, _, name, ops, steps = min(cands)     # the unrolled loop, then the fewest compares
+        _, name, ops = min(cands)
         counts = {}
         for o in ops:
             counts[o] = counts.get(o, 0) + 1

@@ -161,7 +161,7 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
         if (st != IVDE_OK) return st;
         probs[f] = hc.problem;
         if ((e = upload_constants(hc, ly, fws, s)) != hipSuccess) return hip_fail(e, "batch constants");
-        if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(fws + ly.off_flag), 0, 1, s)) != hipSuccess)
+        if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(fws + ly.off_flag), 0, kFlagWords, s)) != hipSuccess)
             return hip_fail(e, "batch flag");
         const Problem *dp = reinterpret_cast<const Problem *>(fws + ly.off_problem);
         if ((e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s)) != hipSuccess) return hip_fail(e, "batch index");

@@ -234,7 +234,7 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
     ly.off_views = take(sizeof(ViewDesc) * n);
     ly.off_pairs = take(sizeof(PairConst) * n * n);
     ly.off_sigma = take(sizeof(float) * n * ly.L);
-    ly.off_flag = take(sizeof(int32_t) * 4);
+    ly.off_flag = take(kFlagWords * sizeof(int32_t));   // error flag, then 3 x 64-bit sweep step counts
     ly.total_rows = 0;
     ly.max_w = ly.max_h = ly.max_s = ly.max_bands = 0;
     for (int v = 0; v < n; ++v) {
@@ -470,6 +470,7 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
     P.sigma = reinterpret_cast<float *>(ws_base + ly.off_sigma);
     P.cost = cost_out;
     P.flag = reinterpret_cast<int32_t *>(ws_base + ly.off_flag);
+    P.steps = reinterpret_cast<unsigned long long *>(ws_base + ly.off_flag + 8);
     return IVDE_OK;
 }
 
@@ -509,6 +510,8 @@ ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *
     hipError_t e = upload_constants(hc, ly, ws, s);
     if (e != hipSuccess) return hip_fail(e, "constant upload");
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
+    e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag) + 2, 0, kFlagWords - 2, s);
+    if (e != hipSuccess) return hip_fail(e, "step count reset");
     if (index_ready) {
         // the segment-id flag of the index build stays as it was
         e = launch_refresh(dp, extents_of(ly), ly.tex_f32, s);
@@ -686,6 +689,28 @@ ivde_status ivde_workspace_status(const void *workspace, ivde_stream stream)
         set_error("a segment id was outside [0, num_segments)");
         return IVDE_EINVAL;
     }
+    return IVDE_OK;
+}
+
+ivde_status ivde_workspace_sweep_steps(const void *workspace, ivde_stream stream, int64_t *steps_total,
+                                       int64_t *steps_projected, int64_t *steps_inside)
+{
+    if (!workspace) {
+        set_error("null workspace");
+        return IVDE_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    Problem p;
+    e = hipMemcpy(&p, workspace, sizeof(p), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read problem header");
+    unsigned long long c[3] = {0, 0, 0};
+    e = hipMemcpy(c, p.steps, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read step counts");
+    if (steps_total) *steps_total = (int64_t)c[0];
+    if (steps_projected) *steps_projected = (int64_t)c[1];
+    if (steps_inside) *steps_inside = (int64_t)c[2];
     return IVDE_OK;
 }
 

@@ -26,7 +26,7 @@ struct Layout {
     int px;                            // pixels per wave step of the sweep (1 or 2)
     int max_w, max_h, max_s, max_bands;
     int64_t total_rows, n_tasks;
-    size_t off_problem, off_views, off_pairs, off_sigma, off_flag, off_tasks;
+    size_t off_problem, off_views, off_pairs, off_sigma, off_flag, off_tasks;   // off_flag: kFlagWords words
     size_t off_centre, off_mean;       // [rows][2] int32 and [rows][4] float over all views
     size_t off_sums;                   // [rows][6] uint64 pixel sums (statistics without the index)
     size_t off_cursors;                // kXcds + 1 int32: sweep cursors and task count

@@ -9,6 +9,7 @@ namespace ivde {
 constexpr int kMaxViews = 32;          // views per problem (pair table is n x n)
 constexpr int kBand = 32;              // rows per spatial band of the work list
 constexpr int kXcds = 8;               // XCDs of the MI355X; consecutive blocks go to consecutive XCDs
+constexpr int kFlagWords = 8;          // workspace flag area: error flag, padding, 3 x 64-bit step counts
 constexpr float kEdge = 1.0f / 64.0f;  // bilinear margin outside the outer pixel centres
 
 // Per-view device descriptor.  Everything a kernel needs about one view:
@@ -66,6 +67,9 @@ struct Problem {
     float *sigma;              // [n_views * L], 1 / (z_l - delta_c) or 0 when undefined
     void *cost;                // [total_rows * L] float or half
     int32_t *flag;             // device error flag (segment id out of range)
+    // wave steps of the pixel-pair sweep: [0] all, [1] on projected records,
+    // [2] on chunks whose every sample lies inside the validity band
+    unsigned long long *steps;
 };
 
 // A unit of sweep work: one wave computes labels [64 J b, 64 J (b + 1)) of

@@ -906,10 +906,21 @@ __device__ __forceinline__ void stage_records(const float *__restrict__ pix, int
 // q' + sigma e with q' = q / (g . p~), which projects to the same pixel, and
 // the target's validity needs no sign test.  The stage holds {q'x, q'y,
 // q'z, Y | Cb} and the Cr half beside it, in cr.
-__device__ __forceinline__ void stage_projected(const float *__restrict__ pix, int i0, int n, const float (&H)[9],
-                                                uint4 *st, uint16_t *cr)
+//
+// Returns true (wave-uniform) when every staged record's samples at levels
+// sig_a .. sig_b lie inside the validity band.  The level points of one
+// pixel between two levels form a segment of its viewing ray in front of
+// the target, so their projections form the segment between the two end
+// projections, and the band is convex: both ends inside it, with a margin
+// of kInside pixels far above the FP32 error of any projected coordinate,
+// put every level's sample inside, as the sweep computes it.
+constexpr float kInside = 1.0f / 16.0f;
+
+__device__ __forceinline__ bool stage_projected(const float *__restrict__ pix, int i0, int n, const float (&H)[9],
+                                                const Target &T, float sig_a, float sig_b, uint4 *st, uint16_t *cr)
 {
     const int lane = lane_id();
+    bool outside = false;
     __builtin_amdgcn_wave_barrier();   // earlier reads of the stage come first
     for (int t0 = 0; t0 < n; t0 += kWave) {
         const int t = t0 + lane;
@@ -923,16 +934,27 @@ __device__ __forceinline__ void stage_projected(const float *__restrict__ pix, i
             const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8])) * rg;
             st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz), pack_h2(r0.w, r1.x));
             cr[t] = (uint16_t)pack_h2(r1.y, 0.f);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const float w = k ? sig_b : sig_a;
+                const float rz = __builtin_amdgcn_rcpf(fmaf(w, T.e2, qz));
+                const float u = fmaf(w, T.e0, qx) * rz, v = fmaf(w, T.e1, qy) * rz;
+                outside |= !((u >= T.lo + kInside) & (u <= T.hi_x - kInside) & (v >= T.lo + kInside) &
+                             (v <= T.hi_y - kInside));
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    return __ballot(outside) == 0;
 }
 
 // Projection and gathers of one (pixel, label) for the pixel-pair sweep: as
 // project_issue with half texels, but the bilinear fractions are returned
 // instead of the four weights, which consume_pair forms (the same
 // operations, later), so fewer registers stay live across the gathers.
+// FRONT 3: as 2, and the sample is known to lie inside the validity band
+// (stage_projected), so it is neither clamped nor tested.
 template <bool BIL, int FRONT>
 __device__ __forceinline__ void project_pair(const Target &T, float qx, float qy, float qz, float w,
                                              Sample<BIL, false> &smp, float &ax, float &ay, bool &valid)
@@ -942,11 +964,14 @@ __device__ __forceinline__ void project_pair(const Target &T, float qx, float qy
     const float hz = fmaf(w, T.e2, qz);
     const float r = __builtin_amdgcn_rcpf(hz);
     const float u = hx * r, v = hy * r;
-    valid = FRONT == 2 ? true : FRONT == 1 ? (hz > 0.f) : ((w > 0.f) & (hz > 0.f));
+    valid = FRONT >= 2 ? true : FRONT == 1 ? (hz > 0.f) : ((w > 0.f) & (hz > 0.f));
     if constexpr (BIL) {
-        const float uc = __builtin_amdgcn_fmed3f(u, T.lo, T.hi_x);
-        const float vc = __builtin_amdgcn_fmed3f(v, T.lo, T.hi_y);
-        valid &= (uc == u) & (vc == v);
+        float uc = u, vc = v;
+        if constexpr (FRONT != 3) {
+            uc = __builtin_amdgcn_fmed3f(u, T.lo, T.hi_x);
+            vc = __builtin_amdgcn_fmed3f(v, T.lo, T.hi_y);
+            valid &= (uc == u) & (vc == v);
+        }
         const uint32_t x0 = (uint32_t)(int)uc, y0 = (uint32_t)(int)vc;
         ax = __builtin_amdgcn_fractf(uc);
         ay = __builtin_amdgcn_fractf(vc);
@@ -955,9 +980,10 @@ __device__ __forceinline__ void project_pair(const Target &T, float qx, float qy
         smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
     } else {
         const float fx = floorf(u + 0.5f), fy = floorf(v + 0.5f);
-        valid &= (fx >= 1.f) & (fx <= T.hi_x - kEdge) & (fy >= 1.f) & (fy <= T.hi_y - kEdge);
+        if constexpr (FRONT != 3)
+            valid &= (fx >= 1.f) & (fx <= T.hi_x - kEdge) & (fy >= 1.f) & (fy <= T.hi_y - kEdge);
         const uint32_t xi = (uint32_t)(int)fx, yi = (uint32_t)(int)fy;
-        const int off = valid ? (int)(mad_u24(yi, T.tp, xi) * 8u) : 0;
+        const int off = (FRONT == 3 || valid) ? (int)(mad_u24(yi, T.tp, xi) * 8u) : 0;
         smp.a = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(T.rs, off, 0, 0));
         ax = ay = 0.f;
     }
@@ -1060,8 +1086,9 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
 
 // Pairs of projected records [0, m) (stage_projected) towards a target
 // proven in front of every level point, at one pass (lane k of either half
-// at level sig): as sweep_pair_records with h = q' + sig e.
-template <int PU, bool BIL>
+// at level sig): as sweep_pair_records with h = q' + sig e; FRONT 3 when
+// every sample of the chunk lies inside the validity band.
+template <int PU, bool BIL, int FRONT>
 __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint16_t *cr, int m, int h,
                                                      const Target &T, float sig, float &acc, uint64_t &acci,
                                                      int &cnt)
@@ -1077,8 +1104,8 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
             const uint4 r = st[i + 2 * u + h];
             rz[u] = r.w;
             rw[u] = cr[i + 2 * u + h];
-            project_pair<BIL, 2>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp[u],
-                                 ax[u], ay[u], val[u]);
+            project_pair<BIL, FRONT>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig,
+                                     smp[u], ax[u], ay[u], val[u]);
         }
         if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1088,7 +1115,7 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
                 acc += val[u] ? d : 0.f;
             else
                 acci += val[u] ? (uint32_t)d : 0u;
-            cnt += val[u] ? 1 : 0;
+            if constexpr (FRONT != 3) cnt += val[u] ? 1 : 0;
         }
     }
     for (; i < m; i += 2) {
@@ -1099,16 +1126,17 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
         Sample<BIL, false> smp;
         float ax, ay;
         bool val;
-        project_pair<BIL, 2>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp, ax, ay,
-                             val);
+        project_pair<BIL, FRONT>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp, ax,
+                                 ay, val);
         val &= here;
         const float d = consume_pair<BIL>(smp, ax, ay, r.w, cr[jj]);
         if constexpr (BIL)
             acc += val ? d : 0.f;
         else
             acci += val ? (uint32_t)d : 0u;
-        cnt += val ? 1 : 0;
+        if constexpr (FRONT != 3) cnt += val ? 1 : 0;
     }
+    if constexpr (FRONT == 3) cnt += (m + 1 - h) / 2;   // every record of this half, every sample valid
 }
 
 // Pairs each wave keeps in flight in the pixel-pair sweep, and the waves per
@@ -1123,9 +1151,15 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
 #endif
 #define IVDE_PAIR_WAVES_PER_SIMD 6
 
+// Wave steps of the pixel-pair sweep a wave has taken since its last flush
+// (wave-uniform): all, on projected records, on chunks inside the band.
+struct PairSteps {
+    uint32_t all = 0, projected = 0, inside = 0;
+};
+
 template <bool BIL, bool F16OUT>
 __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
-                                                 uint16_t *cr)
+                                                 uint16_t *cr, PairSteps &ns)
 {
     constexpr int PU = IVDE_PAIR_INFLIGHT;
     const int lane = lane_id();
@@ -1154,10 +1188,13 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         lab[q] = lbase + q * (kWave / 2) + k;
-        sig[q] = lab[q] < L ? sigma[c * L + lab[q]] : 0.f;
+        // lanes past the last level repeat it (their sums are never stored)
+        sig[q] = sigma[c * L + min(lab[q], L - 1)];
         best[q] = __builtin_inff();
     }
     const int np = p1 - p0;
+    // the task's first and last levels
+    const float sig_a = ldu(sigma + c * L + lbase), sig_b = ldu(sigma + c * L + min(lbase + kWave, L) - 1);
 
     for (int ti = 0; ti < nt; ++ti) {
         const int c2 = ldu(&vc->targets[ti]);
@@ -1181,11 +1218,22 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
         int cnt[2] = {0, 0};
         for (int b0 = 0; b0 < np; b0 += kPairStage) {
             const int m = min(kPairStage, np - b0);
+            const uint32_t steps = (uint32_t)(passes * ((m + 1) / 2));
+            ns.all += steps;
             if (front == 2) {
-                stage_projected(pix, p0 + b0, m, H, st, cr);
+                ns.projected += steps;
+                if (stage_projected(pix, p0 + b0, m, H, T, sig_a, sig_b, st, cr)) {
+                    ns.inside += steps;
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    if (q < passes) sweep_pair_projected<PU, BIL>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                    for (int q = 0; q < 2; ++q)
+                        if (q < passes)
+                            sweep_pair_projected<PU, BIL, 3>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (q < passes)
+                            sweep_pair_projected<PU, BIL, 2>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                }
             } else {
                 stage_records(pix, p0 + b0, m, st);
 #pragma unroll
@@ -1242,6 +1290,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(IVDE_PAIR_W
     const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
     // per-XCD ranges and work stealing as in sweep_persistent_body
     const int home = (int)(blockIdx.x % kXcds);
+    // step counts go to the problem of the tasks they came from, one flush
+    // per change of problem and one at the end
+    PairSteps ns;
+    int cur = -1;
+    auto flush = [&]() {
+        if (cur >= 0 && lane == 0 && ns.all) {
+            unsigned long long *d = ldu(&probs[cur].steps);
+            atomicAdd(d, (unsigned long long)ns.all);
+            atomicAdd(d + 1, (unsigned long long)ns.projected);
+            atomicAdd(d + 2, (unsigned long long)ns.inside);
+        }
+        ns = PairSteps{};
+    };
     for (int k = 0; k < kXcds; ++k) {
         const int x = (home + k) % kXcds;
         const int64_t lo = limit * x / kXcds, n = limit * (x + 1) / kXcds - lo;
@@ -1251,9 +1312,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(IVDE_PAIR_W
             t = uniform(__shfl(t, 0));
             if (t >= n) break;
             const Task task = ldu_task(tasks + lo + t);
-            sweep_task_pairs<BIL, F16OUT>(probs + task.problem, task, st, cr);
+            if (task.problem != cur) {
+                flush();
+                cur = task.problem;
+            }
+            sweep_task_pairs<BIL, F16OUT>(probs + task.problem, task, st, cr, ns);
         }
     }
+    flush();
 }
 
 // Cursors of the sweep to zero, then the task count.

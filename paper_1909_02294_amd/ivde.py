@@ -92,6 +92,7 @@ _I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 SIGNATURES = {
     "ivde_cost_volume_size": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P]),
     "ivde_sweep_shape": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _P]),
+    "ivde_workspace_sweep_steps": (_I32, [_P, _P, _P, _P, _P]),
     "ivde_cost_volume": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _SZ, _P, _P]),
     "ivde_cost_volume_noalloc": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
     "ivde_argmin": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
@@ -361,6 +362,16 @@ def argmin(cost, stream=None, out=None):
 def workspace_status(workspace, stream=None):
     lib = load()
     return lib.ivde_workspace_status(ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream))
+
+
+def sweep_steps(workspace, stream=None):
+    """(all, on projected records, inside the validity band): the wave steps
+    of the pixel-pair sweep of the last cost_volume call on `workspace`."""
+    lib = load()
+    a, p, i = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    check(lib.ivde_workspace_sweep_steps(ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream), ctypes.byref(a),
+                                         ctypes.byref(p), ctypes.byref(i)))
+    return a.value, p.value, i.value
 
 
 def last_error() -> str:

@@ -96,6 +96,12 @@ def test_size_query(lib):
     assert cb.value == n * S * L * 2
 
 
+def test_sweep_steps_needs_a_workspace(lib):
+    a = ctypes.c_int64(-1)
+    assert lib.ivde_workspace_sweep_steps(None, None, ctypes.byref(a), None, None) == ivde.IVDE_EINVAL
+    assert a.value == -1
+
+
 def test_sweep_shape_query(lib):
     """The launch shape the plain call takes: the pixel-pair sweep by default
     (one label per lane, half texels), the one-pixel sweep where asked for,

@@ -147,3 +147,46 @@ def test_pairs_batched_and_served_equal_plain():
             assert torch.equal(out[m], plain[m]) and torch.equal(out[~m], outs[-1][~m])
         outs.append(out)
     srv.close()
+
+
+def _expected_pair_steps(ns):
+    """Wave steps of the pixel-pair sweep over every task and target, from
+    the segment sizes alone: per (view, segment, 64-level block, target),
+    the block's passes (two of 32 levels, one for a last block of at most 32)
+    times, per chunk of at most 256 records, half the chunk rounded up."""
+    n, L = len(ns.cams), ns.num_labels
+    passes = sum(2 if b * 64 + 32 < L else 1 for b in range((L + 63) // 64))
+    total = 0
+    for c in range(n):
+        m = np.bincount(np.asarray(ns.seg[c]).ravel(), minlength=ns.S[c]).astype(np.int64)
+        per_seg = (m // 256) * 128 + ((m % 256) + 1) // 2
+        total += (n - 1) * passes * int(per_seg.sum())
+    return total
+
+
+def _steps(ns, px, depth_ref=ivde.REF_RIG_CENTER):
+    dv = ivde.DeviceViews(ns.cams, ns.Y, ns.U, ns.V, ns.seg, ns.S, ns.bit_depth, ns.chroma_shift)
+    lr = ivde.label_range(ns.z_near, ns.z_far, ns.num_labels, depth_ref)
+    C, ws = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F32, pixels_per_step=px))
+    return ivde.sweep_steps(ws)
+
+
+def test_pairs_step_accounting():
+    """The kernel's own count of its wave steps: every step of every task
+    and target counted once, the projected-record steps those of targets
+    proven in front of every level point, and the steps without per-sample
+    validity tests a subset of those; a one-pixel sweep counts nothing."""
+    _case("pairs step accounting")
+    wl = synth.make_small_arc(seed=3, n_views=4, width=160, height=96, n_segments=40, num_labels=130)
+    total, projected, inside = _steps(wl, 2)
+    assert total == _expected_pair_steps(wl)
+    assert 0 < inside <= projected <= total
+    # a repeated call counts afresh
+    assert _steps(wl, 2) == (total, projected, inside)
+    assert _steps(wl, 1) == (0, 0, 0)
+    # cameras facing each other: some targets are not proven in front of
+    # every level point, so their steps form q and g . p~ per sample
+    ns = P.facing_problem(60, width=96, height=64, n_seg=60, L=48, bit_depth=10, chroma_shift=1, bilinear=True)
+    t2, p2, i2 = _steps(ns, 2)
+    assert t2 == _expected_pair_steps(ns)
+    assert i2 <= p2 < t2
