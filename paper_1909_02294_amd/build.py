@@ -36,10 +36,15 @@ STAGE_LIB = os.path.join(HERE, "libivde_stage.so")
 STAGE_TEXELS = 624
 
 
-def _compile(src: str, sanitize: bool = False, stage_texels: int = 0) -> str:
-    tag = ".san" if sanitize else f".stage{stage_texels}" if stage_texels else ""
+# Measurement build (libivde_tested.so): the pixel-pair sweep tests every
+# sample against the validity band, also on chunks shown to lie inside it.
+TESTED_LIB = os.path.join(HERE, "libivde_tested.so")
+
+
+def _compile(src: str, sanitize: bool = False, stage_texels: int = 0, tested: bool = False) -> str:
+    tag = ".san" if sanitize else f".stage{stage_texels}" if stage_texels else ".tested" if tested else ""
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + tag + ".o")
-    extra = [f"-DIVDE_STAGE_TEXELS={stage_texels}"] if stage_texels else []
+    extra = [f"-DIVDE_STAGE_TEXELS={stage_texels}"] if stage_texels else ["-DIVDE_PAIR_INSIDE=0"] if tested else []
     cmd = [HIPCC, *COMMON, *(SAN_HOST if sanitize else []), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -50,15 +55,24 @@ def _compile(src: str, sanitize: bool = False, stage_texels: int = 0) -> str:
     return obj
 
 
-def build(verbose: bool = False, sanitize: bool = False, stage_texels: int = 0) -> str:
+def build(verbose: bool = False, sanitize: bool = False, stage_texels: int = 0, tested: bool = False) -> str:
     """Compile every source and link libivde.so next to this file; with
     sanitize, the host-sanitizer build libivde_san.so; with stage_texels,
-    the LDS-staging measurement build libivde_stage.so."""
+    the LDS-staging measurement build libivde_stage.so; with tested, the
+    measurement build libivde_tested.so (only kernels.hip differs: the
+    objects of the other sources are the default build's)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+
+    def one(src):
+        if tested and src != "kernels.hip":
+            obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+            return obj if os.path.exists(obj) else _compile(src)
+        return _compile(src, sanitize, stage_texels, tested)
+
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, sanitize, stage_texels), srcs))
-    lib = SAN_LIB if sanitize else STAGE_LIB if stage_texels else LIB
+        objs = list(ex.map(one, srcs))
+    lib = SAN_LIB if sanitize else STAGE_LIB if stage_texels else TESTED_LIB if tested else LIB
     tmp = lib + ".tmp"
     link_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"] \
         if sanitize else []

@@ -1150,6 +1150,11 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
 #define IVDE_PAIR_INFLIGHT 3
 #endif
 #define IVDE_PAIR_WAVES_PER_SIMD 6
+// 0 (a measurement build): chunks inside the validity band run the tested
+// loop as well, which must give bitwise the same volume.
+#ifndef IVDE_PAIR_INSIDE
+#define IVDE_PAIR_INSIDE 1
+#endif
 
 // Wave steps of the pixel-pair sweep a wave has taken since its last flush
 // (wave-uniform): all, on projected records, on chunks inside the band.
@@ -1222,7 +1227,8 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
             ns.all += steps;
             if (front == 2) {
                 ns.projected += steps;
-                if (stage_projected(pix, p0 + b0, m, H, T, sig_a, sig_b, st, cr)) {
+                const bool inside = stage_projected(pix, p0 + b0, m, H, T, sig_a, sig_b, st, cr);
+                if (IVDE_PAIR_INSIDE && inside) {
                     ns.inside += steps;
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
