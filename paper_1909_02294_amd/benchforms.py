@@ -437,7 +437,8 @@ def bench_shapes(args):
                 evals = sum(c.width * c.height for c in wl.cams) * L * (wl.n_views - 1)
                 res[name] = {"sweep_ms": ms, "evals_per_s": evals / (ms / 1e3),
                              "labels_per_lane": o.labels_per_lane or 1, "waves_per_group": o.waves_per_group,
-                             "pixels_per_step": o.pixels_per_step}
+                             "pixels_per_step": o.pixels_per_step,
+                             "pair_wave_steps": dict(zip(("all", "projected", "inside"), ivde.sweep_steps(ws)))}
             row = {"segments_per_view": S, "labels": L, "pixels_per_segment": 1920 * 1080 / S,
                    "class": ivde.shape_class(dv, lr, base), **res,
                    "autotune_us": {"x".join(map(str, k)): v for k, v in table.items()} if table else None}
