@@ -129,6 +129,8 @@ def calibrate():
 
 SWEEP_FORMS = {1: "k_sweep_persistent_j1 (bilinear, half texels, FP32 store; one pixel at 64 levels per wave step)",
                2: "k_sweep_pairs (bilinear, half texels, FP32 store; two pixels at 32 levels per wave step, records "
+                  "staged in LDS)",
+               4: "k_sweep_pairs (bilinear, half texels, FP32 store; four pixels at 16 levels per wave step, records "
                   "staged in LDS)"}
 
 
@@ -138,7 +140,7 @@ def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None):
     priced with the calibrated issue costs; for the pixel-pair sweep the
     loops are weighted by the wave steps the kernel counted in each (steps =
     (all, on projected records, inside the validity band), from
-    ivde_workspace_sweep_steps).  The binding unit is the one nearer its
+    ivde_workspace_sweep_steps; two or four pixels per step).  The binding unit is the one nearer its
     ceiling."""
     from paper_1909_02294_amd import build as _b
     with open(_b.MIX_JSON) as fh:
@@ -165,7 +167,8 @@ def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None):
         instructions = by_loop["one_pixel"] * ins
     else:
         all_, proj, inside = steps
-        by_loop = {"pairs_inside": inside, "pairs_tested": proj - inside, "pairs_records": all_ - proj}
+        pre = "pairs_" if px == 2 else "quads_"
+        by_loop = {pre + "inside": inside, pre + "tested": proj - inside, pre + "records": all_ - proj}
         simd_cycles = instructions = 0.0
         loops = {}
         for name, n in by_loop.items():
@@ -306,7 +309,7 @@ def bench_plain(args):
     calib = calibrate()
     J, wpg, px = ivde.sweep_shape(dv, lr, base)
     if J == 1:
-        steps = ivde.sweep_steps(ws, stream) if px == 2 else None
+        steps = ivde.sweep_steps(ws, stream) if px in (2, 4) else None
         roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters, px, steps)
     else:
         roofline, classes = {"note": f"no instruction model for {J} labels per lane"}, {}
@@ -525,7 +528,8 @@ def main():
     ap.add_argument("--shape-labels", default="128,256", help="shapes: level counts")
     ap.add_argument("--no-tune", action="store_true", help="shapes: the default launch shape only")
     ap.add_argument("--compare-px", action="store_true", help="shapes: also time the pixel-pair sweep")
-    ap.add_argument("--pixels-per-step", type=int, default=0, help="plain: 1 one-pixel sweep, 2 pixel pairs")
+    ap.add_argument("--pixels-per-step", type=int, default=0,
+                    help="1 one-pixel sweep, 2 or 4 pixels per wave step; 0 the library's choice")
     ap.add_argument("--tune-cache", default=None,
                     help="batched, shapes: JSON file caching tuned launch shapes per shape class "
                          "(default: kept in memory for this run)")

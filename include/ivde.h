@@ -129,15 +129,17 @@ typedef struct {
  * are launch-shape knobs; 0 picks the tuned default.  They never change a
  * result.  pixels_per_step 2 runs the pixel-pair sweep (each wave step two
  * pixels at 32 levels instead of one pixel at 64: half the epipolar span
- * per gather); it exists for one label per lane and images of up to 11
- * bits, elsewhere the one-pixel sweep runs; 0 picks the default (the
- * pixel-pair sweep wherever it exists), 1 the one-pixel sweep.  Both
- * sweeps compute the same quantity but add a segment's pixels in a
- * different order and, towards targets proven in front of every level
- * point, the pixel-pair sweep forms a sample's projection from H p~ divided
- * by g . p~: their FP32 results may differ in the last bits, and a sample
- * within FP32 rounding of the bilinear validity band's edge may count in
- * one and not the other.  sweep_events, if both non-NULL, are hipEvent_t handles
+ * per gather), 4 its four-pixel form (four pixels at 16 levels); they exist
+ * for one label per lane and images of up to 11 bits, elsewhere the
+ * one-pixel sweep runs; 1 asks for the one-pixel sweep, 0 picks the
+ * default: four pixels where neighbouring levels land at least 3 px apart
+ * (FP64 mean over each view's image centre projected into its targets),
+ * else two.  The sweeps compute the same quantity but add a segment's
+ * pixels in different orders and, towards targets proven in front of every
+ * level point, the multi-pixel sweeps form a sample's projection from H p~
+ * divided by g . p~: their FP32 results may differ in the last bits, and a
+ * sample within FP32 rounding of the bilinear validity band's edge may
+ * count in one and not the other.  sweep_events, if both non-NULL, are hipEvent_t handles
  * the call records on its stream immediately before and after the sweep
  * kernel (for timing that kernel alone). */
 typedef struct {
@@ -148,7 +150,7 @@ typedef struct {
     int32_t labels_per_lane;
     int32_t waves_per_group;
     void *sweep_events[2];
-    int32_t pixels_per_step;  /* 0, 1 or 2 */
+    int32_t pixels_per_step;  /* 0, 1, 2 or 4 */
 } ivde_options;
 
 /* ---------------------------------------------------------------- plain form */
@@ -166,7 +168,7 @@ ivde_status ivde_cost_volume_size(int32_t n_views, const ivde_camera *cams,
 
 /* The launch shape ivde_cost_volume takes for these arguments: labels per
  * lane, waves per workgroup and pixels per wave step (1: the one-pixel
- * sweep, 2: the pixel-pair sweep), from the options where they are set and
+ * sweep, 2 or 4: the multi-pixel sweep), from the options where they are set and
  * the defaults where they are 0.  Any output pointer may be NULL; arguments
  * are checked as for ivde_cost_volume_size.  Nothing is enqueued. */
 ivde_status ivde_sweep_shape(int32_t n_views, const ivde_camera *cams, const ivde_segmentation *segs,
@@ -224,8 +226,8 @@ ivde_status ivde_cost_volume_noalloc(int32_t n_views, const ivde_camera *cams, c
 ivde_status ivde_workspace_status(const void *workspace, ivde_stream stream);
 
 /* After the stream that ran ivde_cost_volume with this workspace has
- * completed: the wave steps its pixel-pair sweep took (one step = two
- * pixels of a segment towards one target at 32 levels), in total, on
+ * completed: the wave steps its multi-pixel sweep took (one step = two
+ * pixels of a segment towards one target at 32 levels, or four at 16), in total, on
  * records whose projection base was staged already divided by g . p~
  * (targets proven in front of every level point), and on chunks of records
  * whose every sample was shown to lie inside the bilinear validity band,
@@ -544,10 +546,11 @@ ivde_status ivde_optimize(const ivde_energy *energy, int32_t n_threads, int32_t 
 
 /* Times every (labels_per_lane, waves_per_group, pixels_per_step) launch
  * shape on the given problem (which must already be valid for
- * ivde_cost_volume) and writes the fastest into *opt_out.  The 15
+ * ivde_cost_volume) and writes the fastest into *opt_out.  The 18
  * candidates, in order: labels per lane 1, 2, 4, 8 x waves per group 1, 2, 4
  * with one pixel per step, then one label per lane x waves per group 1, 2, 4
- * with pixel pairs (skipped, time -1, where that sweep does not exist).
+ * with two and then four pixels per step (skipped, time -1, where those
+ * sweeps do not exist).
  * Each candidate runs `reps` times; times in microseconds go to times_us[i]
  * for candidate i if not NULL (capacity max_times).  Synchronises `stream`. */
 ivde_status ivde_autotune(int32_t n_views, const ivde_camera *cams, const ivde_image *views,

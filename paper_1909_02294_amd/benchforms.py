@@ -422,6 +422,7 @@ def bench_shapes(args):
             if args.compare_px:
                 variants.append(("one", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=1)))
                 variants.append(("pairs", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=2)))
+                variants.append(("quads", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=4)))
             for name, o in variants:
                 ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                       for _ in range(args.steps)]
@@ -444,7 +445,7 @@ def bench_shapes(args):
                    "autotune_us": {"x".join(map(str, k)): v for k, v in table.items()} if table else None}
             if "pairs" in res:
                 _log(f"S={S} L={L}: one pixel {res['one']['sweep_ms']:.2f} ms, pixel pairs "
-                     f"{res['pairs']['sweep_ms']:.2f} ms, {res['pairs']['evals_per_s']:.3g} evals/s")
+                     f"{res['pairs']['sweep_ms']:.2f} ms, four pixels {res['quads']['sweep_ms']:.2f} ms")
             _log(f"S={S} L={L}: {res['j1']['sweep_ms']:.2f} ms, {res['j1']['evals_per_s']:.3g} evals/s" +
                  ("" if args.no_tune else f" (tuned {res['tuned']['labels_per_lane']}x"
                                           f"{res['tuned']['waves_per_group']}: {res['tuned']['sweep_ms']:.2f} ms)"))

@@ -90,7 +90,8 @@ MIX_JSON = LIB + ".sweep_mix.json"
 # the bilinear FP32-store instantiations of the two sweep forms
 SWEEP_SYMBOLS = {
     "one_pixel": "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
-    "pairs": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "pairs": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi2EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "quads": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi4EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
 }
 
 
@@ -146,6 +147,9 @@ def sweep_mix(verbose: bool = False) -> dict:
                          lambda ops, g: g == 6 and "ds_read_u16" in ops and "v_med3_f32" in ops, 3),
         "pairs_records": (SWEEP_SYMBOLS["pairs"], lambda ops, g: g == 6 and "ds_read_u16" not in ops, 3),
     }
+    for form in ("inside", "tested", "records"):   # four pixels per step: the same loops
+        sym, pick, steps = wanted["pairs_" + form]
+        wanted["quads_" + form] = (SWEEP_SYMBOLS["quads"], pick, steps)
     forms = {}
     for form, (sym, pick, steps) in wanted.items():
         cands = []

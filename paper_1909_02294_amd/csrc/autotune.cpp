@@ -22,7 +22,7 @@ struct Shape {
 
 constexpr Shape kShapes[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {2, 1, 1}, {2, 2, 1}, {2, 4, 1},
                              {4, 1, 1}, {4, 2, 1}, {4, 4, 1}, {8, 1, 1}, {8, 2, 1}, {8, 4, 1},
-                             {1, 1, 2}, {1, 2, 2}, {1, 4, 2}};
+                             {1, 1, 2}, {1, 2, 2}, {1, 4, 2}, {1, 1, 4}, {1, 2, 4}, {1, 4, 4}};
 
 }  // namespace
 

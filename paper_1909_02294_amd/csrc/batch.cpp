@@ -23,6 +23,11 @@
 
 using namespace ivde;
 
+// Sweep forms a batch can hold, by pixels per wave step, in queue order.
+constexpr int kBatchForms = 3;
+constexpr int kBatchFormPx[kBatchForms] = {1, 2, 4};
+inline int form_index(int px) { return px == 1 ? 0 : px == 2 ? 1 : 2; }
+
 struct ivde_batch {
     int n_frames = 0;
     std::vector<ivde_frame> frames;
@@ -32,14 +37,14 @@ struct ivde_batch {
     std::vector<Layout> layouts;
     std::vector<size_t> frame_off;     // byte offset of each frame's region
     std::vector<int64_t> task_off;     // first task of each frame in the queue
-    std::vector<int> order;            // one-pixel frames, then pixel-pair frames, each by decreasing work
+    std::vector<int> order;            // frames by sweep form (1, 2, then 4 pixels per step), each by decreasing work
     ivde_options opt{};
     char *ws = nullptr;
     size_t off_probs = 0, off_tasks = 0, off_counters = 0, total_bytes = 0;
     int64_t n_tasks = 0;
-    int64_t n_tasks1 = 0;              // tasks of the one-pixel frames (the front of the queue)
+    int64_t form_end[kBatchForms] = {0, 0, 0};   // end of each sweep form's range of the queue
     int J = 4, wpg = 4, tex_f32 = 0, f16 = 0, bilinear = 1;
-    int n_groups = 0, n_groups2 = 0;   // resident groups of the one-pixel and the pixel-pair sweep
+    int n_groups[kBatchForms] = {0, 0, 0};       // resident groups of each form's persistent sweep
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -118,7 +123,7 @@ ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_op
     for (int f : b.order) {
         b.task_off[f] = t;
         t += b.layouts[f].n_tasks;
-        if (b.layouts[f].px == 1) b.n_tasks1 = t;
+        for (int k = form_index(b.layouts[f].px); k < kBatchForms; ++k) b.form_end[k] = t;
     }
     b.n_tasks = t;
     b.off_probs = off;
@@ -126,7 +131,7 @@ ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_op
     b.off_tasks = off;
     off = align_up(off + sizeof(Task) * (size_t)b.n_tasks, 256);
     b.off_counters = off;
-    off = align_up(off + 2 * (kXcds + 1) * sizeof(int32_t), 256);   // per sweep: cursors, then the task count
+    off = align_up(off + kBatchForms * (kXcds + 1) * sizeof(int32_t), 256);   // per sweep: cursors, then the task count
     // keep host copies of the frame descriptions: the plan outlives the caller's arrays
     b.cams.resize(n_frames);
     b.views.resize(n_frames);
@@ -171,13 +176,13 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
     if ((e = launch_upload(b.ws + b.off_probs, probs.data(), sizeof(Problem) * probs.size(), s)) != hipSuccess)
         return hip_fail(e, "batch problem table");
     int32_t *counters = reinterpret_cast<int32_t *>(b.ws + b.off_counters);
-    int32_t *counters2 = counters + kXcds + 1;
-    const int64_t n2 = b.n_tasks - b.n_tasks1;
-    if ((e = launch_fill_i32(counters, 0, kXcds, s)) != hipSuccess ||
-        (e = launch_fill_i32(counters + kXcds, (int32_t)b.n_tasks1, 1, s)) != hipSuccess ||
-        (e = launch_fill_i32(counters2, 0, kXcds, s)) != hipSuccess ||
-        (e = launch_fill_i32(counters2 + kXcds, (int32_t)n2, 1, s)) != hipSuccess)
-        return hip_fail(e, "batch cursors");
+    for (int k = 0; k < kBatchForms; ++k) {
+        const int64_t n = b.form_end[k] - (k ? b.form_end[k - 1] : 0);
+        int32_t *ck = counters + k * (kXcds + 1);
+        if ((e = launch_fill_i32(ck, 0, kXcds, s)) != hipSuccess ||
+            (e = launch_fill_i32(ck + kXcds, (int32_t)n, 1, s)) != hipSuccess)
+            return hip_fail(e, "batch cursors");
+    }
     // timing events only in eager runs: a captured graph replays without them
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "capture status");
@@ -186,14 +191,13 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
         return hip_fail(e, "event record");
     const Problem *dprobs = reinterpret_cast<const Problem *>(b.ws + b.off_probs);
     const Task *tasks = reinterpret_cast<const Task *>(b.ws + b.off_tasks);
-    if (b.n_tasks1 > 0 &&
-        (e = launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, b.n_tasks1, b.J, 1, b.bilinear,
-                                     b.tex_f32, b.f16, b.wpg, b.n_groups, s)) != hipSuccess)
-        return hip_fail(e, "batch sweep");
-    if (n2 > 0 &&
-        (e = launch_sweep_persistent(dprobs, tasks + b.n_tasks1, counters2 + kXcds, counters2, n2, b.J, 2, b.bilinear,
-                                     b.tex_f32, b.f16, b.wpg, b.n_groups2, s)) != hipSuccess)
-        return hip_fail(e, "batch pixel-pair sweep");
+    for (int k = 0; k < kBatchForms; ++k) {
+        const int64_t t0 = k ? b.form_end[k - 1] : 0, n = b.form_end[k] - t0;
+        int32_t *ck = counters + k * (kXcds + 1);
+        if (n > 0 && (e = launch_sweep_persistent(dprobs, tasks + t0, ck + kXcds, ck, n, b.J, kBatchFormPx[k],
+                                                  b.bilinear, b.tex_f32, b.f16, b.wpg, b.n_groups[k], s)) != hipSuccess)
+            return hip_fail(e, "batch sweep");
+    }
     if (timed && (e = hipEventRecord(static_cast<hipEvent_t>(b.opt.sweep_events[1]), s)) != hipSuccess)
         return hip_fail(e, "event record");
     for (int f = 0; f < b.n_frames; ++f) {
@@ -250,9 +254,13 @@ ivde_status ivde_batch_create(int32_t n_frames, const ivde_frame *frames, const 
         return st;
     }
     b->ws = static_cast<char *>(workspace);
-    b->n_groups = persistent_groups(b->J, 1, b->bilinear, b->tex_f32, b->f16, b->wpg);
-    b->n_groups2 = b->n_tasks1 < b->n_tasks ? persistent_groups(b->J, 2, b->bilinear, b->tex_f32, b->f16, b->wpg) : 1;
-    if (b->n_groups <= 0 || b->n_groups2 <= 0) {
+    bool ok = true;
+    for (int k = 0; k < kBatchForms; ++k) {
+        const bool used = b->form_end[k] > (k ? b->form_end[k - 1] : 0);
+        b->n_groups[k] = used ? persistent_groups(b->J, kBatchFormPx[k], b->bilinear, b->tex_f32, b->f16, b->wpg) : 1;
+        ok &= b->n_groups[k] > 0;
+    }
+    if (!ok) {
         delete b;
         set_error("batch: occupancy query failed");
         return IVDE_EHIP;

@@ -178,8 +178,8 @@ ivde_status validate_problem(int32_t n, const ivde_camera *cams, const ivde_imag
         set_error("waves_per_group must be 0, 1, 2 or 4");
         return IVDE_EINVAL;
     }
-    if (opt->pixels_per_step < 0 || opt->pixels_per_step > 2) {
-        set_error("pixels_per_step must be 0, 1 or 2");
+    if (opt->pixels_per_step < 0 || opt->pixels_per_step > 4 || opt->pixels_per_step == 3) {
+        set_error("pixels_per_step must be 0, 1, 2 or 4");
         return IVDE_EINVAL;
     }
     return IVDE_OK;
@@ -196,20 +196,99 @@ int default_labels_per_lane(int L)
 
 // ---------------------------------------------------------------- layout
 
-// Pixels per wave step of the sweep.  The pixel-pair sweep (one label per
-// lane, half texels) halves the epipolar span of every gather and, for
-// targets proven in front of every level point, forms each sample's
-// projection from staged records in three multiply-adds instead of twelve
-// instructions.  On the 8-view 1080p arc rig (5,000 to 40,000 segments per
-// view) it was as fast or faster at every level count measured: 64 levels
-// 15.6-16.7 ms against 23.8-30.1 ms, 256 levels 30.1-31.1 against
-// 31.2-32.8 ms, 512 levels 55.3-57.9 against 58.1-59.0 ms; so it is the
-// default wherever it exists.
-static int choose_px(const ivde_options *opt, int J, int tex_f32)
+// Mean distance in pixels between neighbouring levels, at each view's image
+// centre projected into each of its targets (FP64; pairs where either end
+// lies behind a camera are left out).
+static double level_step_px(int32_t n, const ivde_camera *cams, const ivde_label_range *labels,
+                            const ivde_options *opt)
+{
+    const int L = labels->num_labels;
+    if (L < 2 || n < 2) return 0.0;
+    std::vector<double> M(9 * n), C(3 * n), axis(3 * n);
+    for (int v = 0; v < n; ++v) {
+        double Kinv[9], Rt[9], c[3];
+        inv3(cams[v].K, Kinv);
+        transpose3(cams[v].R, Rt);
+        mul3(Rt, Kinv, &M[9 * v]);
+        mv3(Rt, cams[v].t, c);
+        for (int i = 0; i < 3; ++i) {
+            C[3 * v + i] = -c[i];
+            axis[3 * v + i] = cams[v].R[6 + i];
+        }
+    }
+    double cm[3] = {0, 0, 0}, am[3] = {0, 0, 0};
+    for (int u = 0; u < n; ++u)
+        for (int i = 0; i < 3; ++i) {
+            cm[i] += C[3 * u + i] / n;
+            am[i] += axis[3 * u + i] / n;
+        }
+    const double alen = std::sqrt(am[0] * am[0] + am[1] * am[1] + am[2] * am[2]);
+    double sum = 0.0;
+    int cnt = 0;
+    for (int v = 0; v < n; ++v) {
+        double Cr[3], nr[3];
+        const int rv = labels->depth_ref == IVDE_REF_RIG_CENTER ? -1
+                       : labels->depth_ref == IVDE_REF_OWN  ? v
+                                                             : labels->depth_ref;
+        for (int i = 0; i < 3; ++i) {
+            Cr[i] = rv < 0 ? cm[i] : C[3 * rv + i];
+            nr[i] = rv < 0 ? (alen > 0.0 ? am[i] / alen : 0.0) : axis[3 * rv + i];
+        }
+        const double p[3] = {0.5 * (cams[v].width - 1), 0.5 * (cams[v].height - 1), 1.0};
+        double d[3];
+        mv3(&M[9 * v], p, d);
+        const double nd = nr[0] * d[0] + nr[1] * d[1] + nr[2] * d[2];
+        const double delta = nr[0] * (C[3 * v] - Cr[0]) + nr[1] * (C[3 * v + 1] - Cr[1]) + nr[2] * (C[3 * v + 2] - Cr[2]);
+        if (!(std::fabs(nd) > 0.0)) continue;
+        double X[2][3];
+        const double z[2] = {labels->z_far, labels->z_near};
+        for (int k = 0; k < 2; ++k) {
+            const double tau = (z[k] - delta) / nd;
+            for (int i = 0; i < 3; ++i) X[k][i] = C[3 * v + i] + tau * d[i];
+        }
+        for (int c2 = 0; c2 < n; ++c2) {
+            if (c2 == v) continue;
+            if (opt->targets == IVDE_TARGETS_NEAREST_LR && c2 != v - 1 && c2 != v + 1) continue;
+            if (opt->targets == IVDE_TARGETS_EXPLICIT && !opt->target_mask[v * n + c2]) continue;
+            double uv[2][2];
+            bool ok = true;
+            for (int k = 0; k < 2; ++k) {
+                double xc[3], h[3];
+                mv3(cams[c2].R, X[k], xc);
+                for (int i = 0; i < 3; ++i) xc[i] += cams[c2].t[i];
+                mv3(cams[c2].K, xc, h);
+                ok &= h[2] > 0.0;
+                uv[k][0] = h[0] / h[2];
+                uv[k][1] = h[1] / h[2];
+            }
+            if (!ok) continue;
+            sum += std::hypot(uv[1][0] - uv[0][0], uv[1][1] - uv[0][1]);
+            cnt += 1;
+        }
+    }
+    return cnt ? sum / cnt / (L - 1) : 0.0;
+}
+
+// Pixels per wave step of the sweep (one label per lane, half texels; the
+// one-pixel sweep elsewhere).  Two pixels at 32 levels per step (pairs) or
+// four at 16 (quads) shorten the epipolar stretch every gather spans; towards
+// targets proven in front of every level point each sample's projection is
+// three multiply-adds on a staged record.  On the 8-view 1080p arc rig
+// (5,000 to 40,000 segments per view) pairs beat the one-pixel sweep at
+// every level count (64: 14.7-15.8 against 23.7-30.1 ms; 256: 28.2-28.6
+// against 31.1-32.8 ms), and quads beat pairs where neighbouring levels
+// land far apart (64 levels, 8 px: 11.7-11.9 against 14.7-15.8 ms; 128
+// levels, 4 px: 16.7-17.7 against 17.9-18.7 ms) but lose where they land
+// close (256 levels, 2 px: 28.8-31.2 against 28.2-28.6 ms; 512 levels:
+// 54.4-59.6 against 53.7-54.4 ms): each pass then has four times the
+// groups' ragged tails and a quarter of the levels.  So: quads from 3 px
+// between neighbouring levels at the image centres, pairs below.
+static int choose_px(int32_t n, const ivde_camera *cams, const ivde_label_range *labels, const ivde_options *opt,
+                     int J, int tex_f32)
 {
     if (J != 1 || tex_f32) return 1;
     if (opt->pixels_per_step) return opt->pixels_per_step;
-    return 2;
+    return level_step_px(n, cams, labels, opt) >= 3.0 ? 4 : 2;
 }
 
 Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *segs, const ivde_label_range *labels,
@@ -222,7 +301,7 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
     ly.wpg = opt->waves_per_group ? opt->waves_per_group : 4;
     ly.n_lblocks = (ly.L + 64 * ly.J - 1) / (64 * ly.J);
     ly.tex_f32 = bit_depth > 11;
-    ly.px = choose_px(opt, ly.J, ly.tex_f32);
+    ly.px = choose_px(n, cams, labels, opt, ly.J, ly.tex_f32);
     ly.f16 = opt->cost_dtype == IVDE_F16;
     size_t off = 0;
     auto take = [&](size_t bytes) {

@@ -1027,20 +1027,20 @@ __device__ __forceinline__ float consume_pair(const Sample<BIL, false> &smp, flo
 // either half at level sig): PU pairs per step with every gather issued
 // before the first is consumed, then the remaining pairs one at a time (the
 // last possibly with one pixel).
-template <int PU, bool BIL, int FRONT>
+template <int PU, bool BIL, int FRONT, int G>
 __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h, const float (&H)[9],
                                                    const float (&g)[3], const Target &T, float sig, float &acc,
                                                    uint64_t &acci, int &cnt)
 {
     int i = 0;
-    for (; i + 2 * PU <= m; i += 2 * PU) {
+    for (; i + G * PU <= m; i += G * PU) {
         Sample<BIL, false> smp[PU];
         float ax[PU], ay[PU];
         bool val[PU];
         uint32_t rz[PU], rw[PU];
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
-            const uint4 r = st[i + 2 * u + h];
+            const uint4 r = st[i + G * u + h];
             const float x = __uint_as_float(r.x), y = __uint_as_float(r.y);
             rz[u] = r.z;
             rw[u] = r.w;
@@ -1061,7 +1061,7 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
             cnt += val[u] ? 1 : 0;
         }
     }
-    for (; i < m; i += 2) {
+    for (; i < m; i += G) {
         const int j = i + h;
         const bool here = j < m;
         const uint4 r = st[here ? j : m - 1];
@@ -1088,22 +1088,22 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
 // proven in front of every level point, at one pass (lane k of either half
 // at level sig): as sweep_pair_records with h = q' + sig e; FRONT 3 when
 // every sample of the chunk lies inside the validity band.
-template <int PU, bool BIL, int FRONT>
+template <int PU, bool BIL, int FRONT, int G>
 __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint16_t *cr, int m, int h,
                                                      const Target &T, float sig, float &acc, uint64_t &acci,
                                                      int &cnt)
 {
     int i = 0;
-    for (; i + 2 * PU <= m; i += 2 * PU) {
+    for (; i + G * PU <= m; i += G * PU) {
         Sample<BIL, false> smp[PU];
         float ax[PU], ay[PU];
         bool val[PU];
         uint32_t rz[PU], rw[PU];
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
-            const uint4 r = st[i + 2 * u + h];
+            const uint4 r = st[i + G * u + h];
             rz[u] = r.w;
-            rw[u] = cr[i + 2 * u + h];
+            rw[u] = cr[i + G * u + h];
             project_pair<BIL, FRONT>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig,
                                      smp[u], ax[u], ay[u], val[u]);
         }
@@ -1118,7 +1118,7 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
             if constexpr (FRONT != 3) cnt += val[u] ? 1 : 0;
         }
     }
-    for (; i < m; i += 2) {
+    for (; i < m; i += G) {
         const int j = i + h;
         const bool here = j < m;
         const int jj = here ? j : m - 1;
@@ -1136,7 +1136,7 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
             acci += val ? (uint32_t)d : 0u;
         if constexpr (FRONT != 3) cnt += val ? 1 : 0;
     }
-    if constexpr (FRONT == 3) cnt += (m + 1 - h) / 2;   // every record of this half, every sample valid
+    if constexpr (FRONT == 3) cnt += (m - h + G - 1) / G;   // every record of this group, every sample valid
 }
 
 // Pairs each wave keeps in flight in the pixel-pair sweep, and the waves per
@@ -1162,13 +1162,17 @@ struct PairSteps {
     uint32_t all = 0, projected = 0, inside = 0;
 };
 
-template <bool BIL, bool F16OUT>
+// G pixels per wave step (2: pairs, 4: quads): lane group h = lane / (64 / G)
+// takes records h, h + G, ...; lane k of a group takes level
+// 64 b + (64 / G) q + k in pass q.
+template <bool BIL, bool F16OUT, int G>
 __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
                                                  uint16_t *cr, PairSteps &ns)
 {
     constexpr int PU = IVDE_PAIR_INFLIGHT;
+    constexpr int PW = kWave / G;   // lanes per group = levels per pass
     const int lane = lane_id();
-    const int h = lane >> 5, k = lane & 31;
+    const int h = lane / PW, k = lane % PW;
     const int c = task.view, s = task.seg;
     const int L = ldu(&P->L), n = ldu(&P->n_views);
     const ViewDesc *views = ldu(&P->views);
@@ -1187,12 +1191,12 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
     const float g[3] = {ldu(&vc->g[0]), ldu(&vc->g[1]), ldu(&vc->g[2])};
 
     const int lbase = task.lblock * kWave;
-    const int passes = lbase + kWave / 2 < L ? 2 : 1;
-    int lab[2];
-    float sig[2], best[2];
+    const int passes = min(G, (L - lbase + PW - 1) / PW);
+    int lab[G];
+    float sig[G], best[G];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        lab[q] = lbase + q * (kWave / 2) + k;
+    for (int q = 0; q < G; ++q) {
+        lab[q] = lbase + q * PW + k;
         // lanes past the last level repeat it (their sums are never stored)
         sig[q] = sigma[c * L + min(lab[q], L - 1)];
         best[q] = __builtin_inff();
@@ -1218,12 +1222,18 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
         T.e1 = hc.z;
         T.e2 = hc.w;
         const int front = front_all ? (((front_targets >> c2) & 1u) ? 2 : 1) : 0;
-        float acc[2] = {0.f, 0.f};
-        uint64_t acci[2] = {0, 0};
-        int cnt[2] = {0, 0};
+        float acc[G];
+        uint64_t acci[G];
+        int cnt[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            acc[q] = 0.f;
+            acci[q] = 0;
+            cnt[q] = 0;
+        }
         for (int b0 = 0; b0 < np; b0 += kPairStage) {
             const int m = min(kPairStage, np - b0);
-            const uint32_t steps = (uint32_t)(passes * ((m + 1) / 2));
+            const uint32_t steps = (uint32_t)(passes * ((m + G - 1) / G));
             ns.all += steps;
             if (front == 2) {
                 ns.projected += steps;
@@ -1231,48 +1241,52 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
                 if (IVDE_PAIR_INSIDE && inside) {
                     ns.inside += steps;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < G; ++q)
                         if (q < passes)
-                            sweep_pair_projected<PU, BIL, 3>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                            sweep_pair_projected<PU, BIL, 3, G>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < G; ++q)
                         if (q < passes)
-                            sweep_pair_projected<PU, BIL, 2>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                            sweep_pair_projected<PU, BIL, 2, G>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
                 }
             } else {
                 stage_records(pix, p0 + b0, m, st);
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < G; ++q) {
                     if (q >= passes) continue;
                     if (front == 1)
-                        sweep_pair_records<PU, BIL, 1>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
+                        sweep_pair_records<PU, BIL, 1, G>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
                     else
-                        sweep_pair_records<PU, BIL, 0>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
+                        sweep_pair_records<PU, BIL, 0, G>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
                 }
             }
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < G; ++q) {
             if (q >= passes) continue;
-            // the two halves' sums and counts: one exchange across the halves
-            const int c_all = cnt[q] + __shfl_xor(cnt[q], kWave / 2);
-            float sum;
-            if constexpr (BIL) {
-                sum = acc[q] + __shfl_xor(acc[q], kWave / 2);
-            } else {
-                const uint32_t lo = (uint32_t)acci[q], hi = (uint32_t)(acci[q] >> 32);
-                const uint64_t other = ((uint64_t)(uint32_t)__shfl_xor((int)hi, kWave / 2) << 32) |
-                                       (uint32_t)__shfl_xor((int)lo, kWave / 2);
-                sum = (float)(acci[q] + other);
+            // the groups' sums and counts: log2 G exchanges across the groups
+            int c_all = cnt[q];
+            float sum = acc[q];
+            uint64_t sumi = acci[q];
+#pragma unroll
+            for (int o = PW; o < kWave; o <<= 1) {
+                c_all += __shfl_xor(c_all, o);
+                if constexpr (BIL) {
+                    sum += __shfl_xor(sum, o);
+                } else {
+                    const uint32_t lo = (uint32_t)sumi, hi = (uint32_t)(sumi >> 32);
+                    sumi += ((uint64_t)(uint32_t)__shfl_xor((int)hi, o) << 32) | (uint32_t)__shfl_xor((int)lo, o);
+                }
             }
+            if constexpr (!BIL) sum = (float)sumi;
             if (c_all > 0) best[q] = fminf(best[q], sum / ((float)c_all * norm));
         }
     }
 
     const int64_t row = row0 + s;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < G; ++q) {
         if (h == 0 && lab[q] < L) {
             const float o = best[q] == __builtin_inff() ? 1.0f : best[q];
             if constexpr (F16OUT)
@@ -1283,7 +1297,7 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
     }
 }
 
-template <bool BIL, bool F16OUT>
+template <bool BIL, bool F16OUT, int G>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(IVDE_PAIR_WAVES_PER_SIMD, IVDE_PAIR_WAVES_PER_SIMD))) void k_sweep_pairs(
     const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
     int32_t *__restrict__ cursors, int64_t max_tasks)
@@ -1322,7 +1336,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(IVDE_PAIR_W
                 flush();
                 cur = task.problem;
             }
-            sweep_task_pairs<BIL, F16OUT>(probs + task.problem, task, st, cr, ns);
+            sweep_task_pairs<BIL, F16OUT, G>(probs + task.problem, task, st, cr, ns);
         }
     }
     flush();
@@ -1545,8 +1559,11 @@ static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int
                              int64_t max_tasks, int px, int wpg, int n_groups, hipStream_t s)
 {
     if constexpr (J == 1 && !TEXF32) {
-        if (px == 2)
-            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg),
+        if (px == 4)
+            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 4>), dim3((unsigned)n_groups), dim3(64 * wpg),
+                               pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
+        else if (px == 2)
+            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 2>), dim3((unsigned)n_groups), dim3(64 * wpg),
                                pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
         else
             hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
@@ -1575,8 +1592,11 @@ template <int J, bool BIL, bool TEXF32, bool F16OUT>
 static hipError_t occ(int px, int wpg, int *per_cu)
 {
     if constexpr (J == 1 && !TEXF32) {
+        if (px == 4)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 4>, 64 * wpg,
+                                                                pair_stage_bytes(wpg));
         if (px == 2)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT>, 64 * wpg,
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 2>, 64 * wpg,
                                                                 pair_stage_bytes(wpg));
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent_j1<BIL, F16OUT>, 64 * wpg, 0);
     } else

@@ -591,7 +591,7 @@ class Server:
 # ---------------------------------------------------------------- tuning
 # (labels per lane, waves per group, pixels per step), in the library's order
 AUTOTUNE_SHAPES = [(1, 1, 1), (1, 2, 1), (1, 4, 1), (2, 1, 1), (2, 2, 1), (2, 4, 1), (4, 1, 1), (4, 2, 1), (4, 4, 1),
-                   (8, 1, 1), (8, 2, 1), (8, 4, 1), (1, 1, 2), (1, 2, 2), (1, 4, 2)]
+                   (8, 1, 1), (8, 2, 1), (8, 4, 1), (1, 1, 2), (1, 2, 2), (1, 4, 2), (1, 1, 4), (1, 2, 4), (1, 4, 4)]
 
 
 def autotune(dv: DeviceViews, lr: LabelRange, opt: Options, reps=2, stream=None):

@@ -121,8 +121,17 @@ def test_sweep_shape_query(lib):
     assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=8) == (1, 4, 2)
     assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=12) == (1, 4, 1)
     assert shape(ivde.options(pixels_per_step=1)) == (1, 4, 1)
+    assert shape(ivde.options(pixels_per_step=4)) == (1, 4, 4)
     assert shape(ivde.options(labels_per_lane=2, waves_per_group=2)) == (2, 2, 1)
     assert shape(ivde.options(labels_per_lane=2, pixels_per_step=2)) == (2, 4, 1)
+    assert shape(ivde.options(pixels_per_step=4), bits=12) == (1, 4, 1)
+    # few levels over the same depth range land far apart: four pixels per step
+    lr_far = ivde.label_range(1.0, 5.0, 16)
+    j, wpg, px = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr_far),
+                                ctypes.byref(ivde.options()), 10, ctypes.byref(j), ctypes.byref(wpg),
+                                ctypes.byref(px)) == ivde.IVDE_OK
+    assert px.value == 4
     # outputs may be NULL; argument errors as for the size query
     assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
                                 ctypes.byref(ivde.options()), 10, None, None, None) == ivde.IVDE_OK
@@ -135,7 +144,7 @@ def test_sweep_shape_query(lib):
 @pytest.mark.parametrize("field,value", [
     ("n_views", 0), ("n_views", 33), ("z_near", -1.0), ("z_far", float("nan")), ("num_labels", 0),
     ("depth_ref", 7), ("sampling", 5), ("cost_dtype", 9), ("labels_per_lane", 3), ("waves_per_group", 8),
-    ("pixels_per_step", 3), ("pixels_per_step", -1),
+    ("pixels_per_step", 3), ("pixels_per_step", 5), ("pixels_per_step", -1),
     ("bit_depth", 7), ("bit_depth", 17), ("width", 0), ("segments", 0),
 ])
 def test_invalid_arguments_are_rejected(lib, field, value):

@@ -152,12 +152,12 @@ def test_autotune():
     base = ivde.options(ivde.BILINEAR, ivde.F32)
     best, table = ivde.autotune(dv, lr, base, reps=1)
     assert best.labels_per_lane in (1, 2, 4, 8) and best.waves_per_group in (1, 2, 4)
-    assert best.pixels_per_step in (1, 2)
+    assert best.pixels_per_step in (1, 2, 4)
     timed = {k: v for k, v in table.items() if v is not None}
     # every shape is timed but those whose label block exceeds twice the
-    # levels (8 labels per lane at 96 levels); the pixel-pair shapes exist here
+    # levels (8 labels per lane at 96 levels); the two- and four-pixel shapes exist here
     assert {k for k in table if table[k] is None} == {(8, 1, 1), (8, 2, 1), (8, 4, 1)}
-    assert all(table[(1, w, 2)] is not None for w in (1, 2, 4))
+    assert all(table[(1, w, px)] is not None for w in (1, 2, 4) for px in (2, 4))
     assert timed and min(timed, key=timed.get) == (best.labels_per_lane, best.waves_per_group, best.pixels_per_step)
     # launch shapes never change a result for the same sweep form
     a, _ = ivde.cost_volume(dv, lr, ivde.options(ivde.BILINEAR, ivde.F32, pixels_per_step=best.pixels_per_step))

@@ -1,7 +1,8 @@
-"""GPU parity of the pixel-pair sweep (pixels_per_step = 2): each wave step
-covers two pixels of a segment at 32 levels, the segment's pixel records
-are staged in LDS, and the two halves of the wave meet in one cross-lane
-exchange per (target, pass).  It must match the FP64 oracle at the same
+"""GPU parity of the multi-pixel sweep, with two pixels per wave step
+(pixels_per_step = 2: each wave step covers two pixels of a segment at 32
+levels) and with four (16 levels each): the segment's pixel records are
+staged in LDS, and the lane groups meet in cross-lane exchanges per
+(target, pass).  It must match the FP64 oracle at the same
 bars as the one-pixel sweep, give bitwise the one-pixel sweep's result
 wherever the sums are integers (nearest sampling), and cover segments
 larger than one LDS stage (256 records), odd pixel counts, points behind a
@@ -27,16 +28,17 @@ def _case(name):
 
 
 @pytest.mark.parametrize("seed,S,L", [(1, 150, 70), (2, 150, 64), (3, 40, 33), (4, 9, 130)])
-def test_pairs_small_arc_bilinear_420(seed, S, L):
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_small_arc_bilinear_420(seed, S, L, npx):
     """Arc rigs, 4:2:0 10-bit, bilinear; with 9 or 40 segments on 160x96
     most segments exceed one stage of 256 records."""
-    _case(f"pairs arc seed {seed} S {S} L {L}")
+    _case(f"{npx} px arc seed {seed} S {S} L {L}")
     wl = synth.make_small_arc(seed=seed, n_views=4, width=160, height=96, n_segments=S, num_labels=L)
     sizes = np.concatenate([np.bincount(s.ravel(), minlength=n) for s, n in zip(wl.seg, wl.S)])
     if S <= 40:
         assert sizes.max() > 256
     assert (sizes % 2 == 1).any()
-    G, lab = run_gpu(wl, pixels_per_step=2)
+    G, lab = run_gpu(wl, pixels_per_step=npx)
     O = run_oracle(wl)
     r = compare(G, O, label=f"pairs arc{seed}")
     assert r["max_err"] <= 1e-4, r
@@ -46,12 +48,13 @@ def test_pairs_small_arc_bilinear_420(seed, S, L):
     assert np.abs(G - G1).max() <= 1e-5
 
 
-def test_pairs_nearest_rectified_equals_one_pixel_sweep():
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_nearest_rectified_equals_one_pixel_sweep(npx):
     """Nearest sampling sums integer code-value differences: the order of
     the additions does not matter, so both sweeps agree bit for bit."""
-    _case("pairs rectified nearest")
+    _case(f"{npx} px rectified nearest")
     wl = synth.make_rectified_320x240()
-    G2, _ = run_gpu(wl, pixels_per_step=2)
+    G2, _ = run_gpu(wl, pixels_per_step=npx)
     G1, _ = run_gpu(wl, pixels_per_step=1)
     assert np.array_equal(G2, G1)
     r = compare(G2, run_oracle(wl), label="rectified pairs")
@@ -65,45 +68,49 @@ def test_pairs_nearest_rectified_equals_one_pixel_sweep():
     dict(n_views=5, width=24, height=16, n_seg=9, L=300, rotated=True, bilinear=True),
     dict(n_views=3, width=40, height=23, n_seg=2, L=40, rotated=True, bilinear=True, bit_depth=11),
 ])
-def test_pairs_tiny_cases(case):
-    _case(f"pairs tiny {case}")
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_tiny_cases(case, npx):
+    _case(f"{npx} px tiny {case}")
     ns = P.tiny_problem(22, **case)
-    G, _ = run_gpu(ns, pixels_per_step=2)
+    G, _ = run_gpu(ns, pixels_per_step=npx)
     compare(G, run_oracle(ns), label=str(case))
 
 
 @pytest.mark.parametrize("ref", ["rig", 0])
-def test_pairs_facing_rig(ref):
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_facing_rig(ref, npx):
     """Points behind the source and the target cameras (the general
     validity test of the sweep)."""
-    _case(f"pairs facing rig {ref}")
+    _case(f"{npx} px facing rig {ref}")
     ns = P.facing_problem(60, width=96, height=64, n_seg=60, L=48, bit_depth=10, chroma_shift=1, bilinear=True)
     geo = P.behind_geometry(ns, ref)
     assert geo["behind_share"] >= 0.01
     gref = ivde.REF_RIG_CENTER if ref == "rig" else ref
     oref = oracle.REF_RIG_CENTER if ref == "rig" else ref
-    G, _ = run_gpu(ns, depth_ref=gref, pixels_per_step=2)
+    G, _ = run_gpu(ns, depth_ref=gref, pixels_per_step=npx)
     compare(G, run_oracle(ns, depth_ref=oref), label=f"pairs facing {ref}")
     G1, _ = run_gpu(ns, depth_ref=gref, pixels_per_step=1)
     assert np.array_equal(G == 1.0, G1 == 1.0)
 
 
-def test_pairs_fp16_storage_and_repeat():
-    _case("pairs fp16 and repeat")
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_fp16_storage_and_repeat(npx):
+    _case(f"{npx} px fp16 and repeat")
     wl = synth.make_small_arc(seed=7, n_views=3, width=128, height=80, n_segments=139, num_labels=47)
-    G, _ = run_gpu(wl, cost_dtype=ivde.F16, pixels_per_step=2)
+    G, _ = run_gpu(wl, cost_dtype=ivde.F16, pixels_per_step=npx)
     compare(G, run_oracle(wl), f16=True, label="pairs fp16")
-    G2, _ = run_gpu(wl, cost_dtype=ivde.F16, pixels_per_step=2)
+    G2, _ = run_gpu(wl, cost_dtype=ivde.F16, pixels_per_step=npx)
     assert np.array_equal(G, G2)
 
 
-def test_pairs_batched_and_served_equal_plain():
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_batched_and_served_equal_plain(npx):
     """The batched form (one persistent launch, graph replays) and the
     served form run the same kernel: bitwise the plain pixel-pair result."""
-    _case("pairs batched and served")
+    _case(f"{npx} px batched and served")
     wls = [synth.make_small_arc(seed=30 + i, n_views=3 + i % 2, width=120, height=72, n_segments=60 + 30 * i,
                                 num_labels=[40, 64, 96][i % 3]) for i in range(4)]
-    opt = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=2)
+    opt = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=npx)
     ref, frames = [], []
     for wl in wls:
         dv = ivde.DeviceViews.from_workload(wl)
@@ -149,17 +156,19 @@ def test_pairs_batched_and_served_equal_plain():
     srv.close()
 
 
-def _expected_pair_steps(ns):
-    """Wave steps of the pixel-pair sweep over every task and target, from
-    the segment sizes alone: per (view, segment, 64-level block, target),
-    the block's passes (two of 32 levels, one for a last block of at most 32)
-    times, per chunk of at most 256 records, half the chunk rounded up."""
+def _expected_pair_steps(ns, G):
+    """Wave steps of the G-pixel sweep over every task and target, from the
+    segment sizes alone: per (view, segment, 64-level block, target), the
+    block's passes (G of 64 / G levels, fewer in a last block that holds
+    fewer levels) times, per chunk of at most 256 records, the chunk divided
+    by G rounded up."""
     n, L = len(ns.cams), ns.num_labels
-    passes = sum(2 if b * 64 + 32 < L else 1 for b in range((L + 63) // 64))
+    pw = 64 // G
+    passes = sum(min(G, (L - 64 * b + pw - 1) // pw) for b in range((L + 63) // 64))
     total = 0
     for c in range(n):
         m = np.bincount(np.asarray(ns.seg[c]).ravel(), minlength=ns.S[c]).astype(np.int64)
-        per_seg = (m // 256) * 128 + ((m % 256) + 1) // 2
+        per_seg = (m // 256) * (256 // G) + ((m % 256) + G - 1) // G
         total += (n - 1) * passes * int(per_seg.sum())
     return total
 
@@ -171,22 +180,23 @@ def _steps(ns, px, depth_ref=ivde.REF_RIG_CENTER):
     return ivde.sweep_steps(ws)
 
 
-def test_pairs_step_accounting():
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_step_accounting(npx):
     """The kernel's own count of its wave steps: every step of every task
     and target counted once, the projected-record steps those of targets
     proven in front of every level point, and the steps without per-sample
     validity tests a subset of those; a one-pixel sweep counts nothing."""
-    _case("pairs step accounting")
+    _case(f"{npx} px step accounting")
     wl = synth.make_small_arc(seed=3, n_views=4, width=160, height=96, n_segments=40, num_labels=130)
-    total, projected, inside = _steps(wl, 2)
-    assert total == _expected_pair_steps(wl)
+    total, projected, inside = _steps(wl, npx)
+    assert total == _expected_pair_steps(wl, npx)
     assert 0 < inside <= projected <= total
     # a repeated call counts afresh
-    assert _steps(wl, 2) == (total, projected, inside)
+    assert _steps(wl, npx) == (total, projected, inside)
     assert _steps(wl, 1) == (0, 0, 0)
     # cameras facing each other: some targets are not proven in front of
     # every level point, so their steps form q and g . p~ per sample
     ns = P.facing_problem(60, width=96, height=64, n_seg=60, L=48, bit_depth=10, chroma_shift=1, bilinear=True)
-    t2, p2, i2 = _steps(ns, 2)
-    assert t2 == _expected_pair_steps(ns)
+    t2, p2, i2 = _steps(ns, npx)
+    assert t2 == _expected_pair_steps(ns, npx)
     assert i2 <= p2 < t2
