@@ -268,8 +268,9 @@ def label_range(z_near, z_far, num_labels, depth_ref=REF_RIG_CENTER):
 def options(sampling=BILINEAR, cost_dtype=F32, targets=TARGETS_ALL, target_mask=None,
             labels_per_lane=0, waves_per_group=0, sweep_events=None, pixels_per_step=0):
     """sweep_events: optional pair of torch.cuda.Event(enable_timing=True),
-    recorded by the library around its sweep kernel; pixels_per_step: 2 for
-    the pixel-pair sweep, 1 for the one-pixel sweep, 0 the default."""
+    recorded by the library around its sweep kernel; pixels_per_step: 1 for
+    the one-pixel sweep, 2 or 4 pixels per wave step, 0 the library's
+    choice (4 where neighbouring levels land 3 px or more apart, else 2)."""
     o = Options(int(sampling), int(cost_dtype), int(targets), None, int(labels_per_lane), int(waves_per_group))
     o.pixels_per_step = int(pixels_per_step)
     if sweep_events is not None:
@@ -366,7 +367,7 @@ def workspace_status(workspace, stream=None):
 
 def sweep_steps(workspace, stream=None):
     """(all, on projected records, inside the validity band): the wave steps
-    of the pixel-pair sweep of the last cost_volume call on `workspace`."""
+    of the multi-pixel sweep of the last cost_volume call on `workspace`."""
     lib = load()
     a, p, i = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     check(lib.ivde_workspace_sweep_steps(ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream), ctypes.byref(a),
