@@ -130,8 +130,8 @@ typedef struct {
  * result.  pixels_per_step 2 runs the pixel-pair sweep (each wave step two
  * pixels at 32 levels instead of one pixel at 64: half the epipolar span
  * per gather), 4 its four-pixel form (four pixels at 16 levels); they exist
- * for one label per lane and images of up to 11 bits, elsewhere the
- * one-pixel sweep runs; 1 asks for the one-pixel sweep, 0 picks the
+ * for one label per lane, elsewhere the one-pixel sweep runs; 1 asks for
+ * the one-pixel sweep, 0 picks the
  * default: four pixels where neighbouring levels land at least 3 px apart
  * (FP64 mean over each view's image centre projected into its targets),
  * else two.  The sweeps compute the same quantity but add a segment's

@@ -89,9 +89,9 @@ def build(verbose: bool = False, sanitize: bool = False, stage_texels: int = 0, 
 MIX_JSON = LIB + ".sweep_mix.json"
 # the bilinear FP32-store instantiations of the two sweep forms
 SWEEP_SYMBOLS = {
-    "one_pixel": "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
-    "pairs": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi2EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
-    "quads": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi4EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "one_pixel": "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "pairs": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi2ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "quads": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi4ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
 }
 
 

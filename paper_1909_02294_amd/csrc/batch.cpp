@@ -43,7 +43,7 @@ struct ivde_batch {
     size_t off_probs = 0, off_tasks = 0, off_counters = 0, total_bytes = 0;
     int64_t n_tasks = 0;
     int64_t form_end[kBatchForms] = {0, 0, 0};   // end of each sweep form's range of the queue
-    int J = 4, wpg = 4, tex_f32 = 0, f16 = 0, bilinear = 1;
+    int J = 4, wpg = 4, tex_u16 = 0, f16 = 0, bilinear = 1;
     int n_groups[kBatchForms] = {0, 0, 0};       // resident groups of each form's persistent sweep
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -93,7 +93,7 @@ ivde_status plan_batch(int32_t n_frames, const ivde_frame *frames, const ivde_op
     b.opt = o;
     b.J = o.labels_per_lane;
     b.wpg = o.waves_per_group;
-    b.tex_f32 = bit_depth > 11;
+    b.tex_u16 = bit_depth > 11;
     b.f16 = o.cost_dtype == IVDE_F16;
     b.bilinear = o.sampling == IVDE_BILINEAR;
 
@@ -169,7 +169,7 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
         if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(fws + ly.off_flag), 0, kFlagWords, s)) != hipSuccess)
             return hip_fail(e, "batch flag");
         const Problem *dp = reinterpret_cast<const Problem *>(fws + ly.off_problem);
-        if ((e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s)) != hipSuccess) return hip_fail(e, "batch index");
+        if ((e = launch_prepare(dp, extents_of(ly), ly.tex_u16, s)) != hipSuccess) return hip_fail(e, "batch index");
         Task *tasks = reinterpret_cast<Task *>(b.ws + b.off_tasks) + b.task_off[f];
         if ((e = launch_worklist(dp, extents_of(ly), f, tasks, s)) != hipSuccess) return hip_fail(e, "batch tasks");
     }
@@ -195,7 +195,7 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
         const int64_t t0 = k ? b.form_end[k - 1] : 0, n = b.form_end[k] - t0;
         int32_t *ck = counters + k * (kXcds + 1);
         if (n > 0 && (e = launch_sweep_persistent(dprobs, tasks + t0, ck + kXcds, ck, n, b.J, kBatchFormPx[k],
-                                                  b.bilinear, b.tex_f32, b.f16, b.wpg, b.n_groups[k], s)) != hipSuccess)
+                                                  b.bilinear, b.tex_u16, b.f16, b.wpg, b.n_groups[k], s)) != hipSuccess)
             return hip_fail(e, "batch sweep");
     }
     if (timed && (e = hipEventRecord(static_cast<hipEvent_t>(b.opt.sweep_events[1]), s)) != hipSuccess)
@@ -210,13 +210,13 @@ ivde_status enqueue_batch(ivde_batch &b, hipStream_t s)
     return IVDE_OK;
 }
 
-int persistent_groups(int J, int px, int bilinear, int tex_f32, int f16, int wpg)
+int persistent_groups(int J, int px, int bilinear, int tex_u16, int f16, int wpg)
 {
     // enough resident groups to fill every CU at the kernel's occupancy
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (sweep_persistent_occupancy(J, px, bilinear, tex_f32, f16, wpg, &per_cu) != hipSuccess) return 0;
+    if (sweep_persistent_occupancy(J, px, bilinear, tex_u16, f16, wpg, &per_cu) != hipSuccess) return 0;
     return cus * std::max(1, per_cu);
 }
 
@@ -257,7 +257,7 @@ ivde_status ivde_batch_create(int32_t n_frames, const ivde_frame *frames, const 
     bool ok = true;
     for (int k = 0; k < kBatchForms; ++k) {
         const bool used = b->form_end[k] > (k ? b->form_end[k - 1] : 0);
-        b->n_groups[k] = used ? persistent_groups(b->J, kBatchFormPx[k], b->bilinear, b->tex_f32, b->f16, b->wpg) : 1;
+        b->n_groups[k] = used ? persistent_groups(b->J, kBatchFormPx[k], b->bilinear, b->tex_u16, b->f16, b->wpg) : 1;
         ok &= b->n_groups[k] > 0;
     }
     if (!ok) {

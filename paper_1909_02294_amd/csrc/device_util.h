@@ -54,6 +54,26 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t u)
 __device__ __forceinline__ float h_lo(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
 __device__ __forceinline__ float h_hi(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
 
+// One 16-bit channel of a packed texel or colour word as FP32.  Channels
+// hold halves (code values up to 11 bits, exact) or, with U16, the unsigned
+// 16-bit code values themselves (any bit depth up to 16, exact).
+template <bool U16>
+__device__ __forceinline__ float ch_lo(uint32_t w)
+{
+    if constexpr (U16)
+        return (float)(w & 0xffffu);
+    else
+        return h_lo(w);
+}
+template <bool U16>
+__device__ __forceinline__ float ch_hi(uint32_t w)
+{
+    if constexpr (U16)
+        return (float)(w >> 16);
+    else
+        return h_hi(w);
+}
+
 // Wave-uniform loads through the scalar unit: the address must be uniform
 // and the data must not be written by the running kernel.
 #define IVDE_AS4 __attribute__((address_space(4)))

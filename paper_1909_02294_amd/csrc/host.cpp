@@ -284,9 +284,9 @@ static double level_step_px(int32_t n, const ivde_camera *cams, const ivde_label
 // groups' ragged tails and a quarter of the levels.  So: quads from 3 px
 // between neighbouring levels at the image centres, pairs below.
 static int choose_px(int32_t n, const ivde_camera *cams, const ivde_label_range *labels, const ivde_options *opt,
-                     int J, int tex_f32)
+                     int J)
 {
-    if (J != 1 || tex_f32) return 1;
+    if (J != 1) return 1;
     if (opt->pixels_per_step) return opt->pixels_per_step;
     return level_step_px(n, cams, labels, opt) >= 3.0 ? 4 : 2;
 }
@@ -300,8 +300,8 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
     ly.J = opt->labels_per_lane ? opt->labels_per_lane : default_labels_per_lane(ly.L);
     ly.wpg = opt->waves_per_group ? opt->waves_per_group : 4;
     ly.n_lblocks = (ly.L + 64 * ly.J - 1) / (64 * ly.J);
-    ly.tex_f32 = bit_depth > 11;
-    ly.px = choose_px(n, cams, labels, opt, ly.J, ly.tex_f32);
+    ly.tex_u16 = bit_depth > 11;
+    ly.px = choose_px(n, cams, labels, opt, ly.J);
     ly.f16 = opt->cost_dtype == IVDE_F16;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -322,7 +322,7 @@ Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *
         vl.row0 = ly.total_rows;
         ly.total_rows += S;
         vl.n_bands = (H + kBand - 1) / kBand;
-        vl.tex_bytes = (int64_t)(W + 2) * (H + 2) * (ly.tex_f32 ? 16 : 8);
+        vl.tex_bytes = (int64_t)(W + 2) * (H + 2) * 8;
         vl.off_tex = take((size_t)vl.tex_bytes + 16);
         vl.off_counts = take(sizeof(int32_t) * S);
         vl.off_offsets = take(sizeof(int32_t) * (S + 1));
@@ -542,7 +542,7 @@ ivde_status compose(int32_t n, const ivde_camera *cams, const ivde_image *views,
     P.bit_depth = views ? views[0].bit_depth : 8;
     P.chroma_shift = views ? views[0].chroma_shift : 0;
     P.norm = (float)(3.0 * (double)((1 << P.bit_depth) - 1));
-    P.tex_f32 = ly.tex_f32;
+    P.tex_u16 = ly.tex_u16;
     P.total_rows = ly.total_rows;
     P.views = reinterpret_cast<ViewDesc *>(ws_base + ly.off_views);
     P.pairs = reinterpret_cast<PairConst *>(ws_base + ly.off_pairs);
@@ -593,13 +593,13 @@ ivde_status enqueue_front(int32_t n, const ivde_camera *cams, const ivde_image *
     if (e != hipSuccess) return hip_fail(e, "step count reset");
     if (index_ready) {
         // the segment-id flag of the index build stays as it was
-        e = launch_refresh(dp, extents_of(ly), ly.tex_f32, s);
+        e = launch_refresh(dp, extents_of(ly), ly.tex_u16, s);
         if (e != hipSuccess) return hip_fail(e, "frame refresh");
         return IVDE_OK;
     }
     e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    e = launch_prepare(dp, extents_of(ly), ly.tex_f32, s, texels);
+    e = launch_prepare(dp, extents_of(ly), ly.tex_u16, s, texels);
     if (e != hipSuccess) return hip_fail(e, "segment index");
     if (worklist && (e = launch_worklist(dp, extents_of(ly), problem_index, tasks, s)) != hipSuccess)
         return hip_fail(e, "work list");
@@ -618,7 +618,7 @@ ivde_status enqueue_stats(int32_t n, const ivde_camera *cams, const ivde_image *
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     e = launch_fill_i32(reinterpret_cast<int32_t *>(ws + ly.off_flag), 0, 1, s);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    if (texels && (e = launch_pack(dp, extents_of(ly), ly.tex_f32, s)) != hipSuccess)
+    if (texels && (e = launch_pack(dp, extents_of(ly), ly.tex_u16, s)) != hipSuccess)
         return hip_fail(e, "texel packing");
     e = launch_segment_sums(dp, extents_of(ly), reinterpret_cast<unsigned long long *>(ws + ly.off_sums),
                             ly.total_rows, count_flat, tasks, s);
@@ -665,7 +665,7 @@ ivde_status enqueue_cost_volume(int32_t n, const ivde_camera *cams, const ivde_i
     if (opt->sweep_events[0] && opt->sweep_events[1] &&
         (e = hipEventRecord(static_cast<hipEvent_t>(opt->sweep_events[0]), s)) != hipSuccess)
         return hip_fail(e, "event record");
-    e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, ly.px, opt->sampling == IVDE_BILINEAR, ly.tex_f32, ly.f16, ly.wpg,
+    e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, ly.px, opt->sampling == IVDE_BILINEAR, ly.tex_u16, ly.f16, ly.wpg,
                      reinterpret_cast<int32_t *>(ws + ly.off_cursors), s);
     if (e != hipSuccess) return hip_fail(e, "sweep");
     if (opt->sweep_events[0] && opt->sweep_events[1] &&

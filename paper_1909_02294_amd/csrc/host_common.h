@@ -22,7 +22,7 @@ struct ViewLayout {
 
 // Byte offsets of everything one problem keeps in its workspace.
 struct Layout {
-    int n, L, J, wpg, n_lblocks, tex_f32, f16;
+    int n, L, J, wpg, n_lblocks, tex_u16, f16;
     int px;                            // pixels per wave step of the sweep (1 or 2)
     int max_w, max_h, max_s, max_bands;
     int64_t total_rows, n_tasks;

@@ -60,7 +60,7 @@ struct Problem {
     int32_t bit_depth;
     int32_t chroma_shift;
     float norm;                // 3 (2^b - 1)
-    int32_t tex_f32;           // texels are float4 (bit depth > 11) instead of half4
+    int32_t tex_u16;           // texel channels are 16-bit code values (bit depth > 11) instead of halves
     int64_t total_rows;
     ViewDesc *views;           // [n_views]
     PairConst *pairs;          // [n_views * n_views], [c * n + c2]
@@ -90,12 +90,12 @@ struct Extents {
     int max_w, max_h, max_s, max_bands;
 };
 // segment index (counts, offsets, boxes, pixel records) and, with pack, the texels
-hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s, bool pack = true);
+hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_u16, hipStream_t s, bool pack = true);
 // the bordered texel image of every view
-hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
+hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_u16, hipStream_t s);
 // a new frame over an index already built for the same segmentation:
 // repack the texels and refresh the records' colours
-hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s);
+hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_u16, hipStream_t s);
 hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem_index, Task *tasks,
                            hipStream_t s);
 // The sweep over tasks[0, n_tasks): enough resident groups to fill every CU
@@ -104,14 +104,14 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
 // px: pixels per wave step (2: the pixel-pair sweep, which exists for one
 // label per lane and half texels; 1: the one-pixel sweep).
 hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int px,
-                        int bilinear, int tex_f32, int f16out, int waves_per_group, int32_t *counters,
+                        int bilinear, int tex_u16, int f16out, int waves_per_group, int32_t *counters,
                         hipStream_t s);
 // cursors: kXcds zeroed counters, one per contiguous range of the task list
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
-                                   int32_t *cursors, int64_t max_tasks, int J, int px, int bilinear, int tex_f32,
+                                   int32_t *cursors, int64_t max_tasks, int J, int px, int bilinear, int tex_u16,
                                    int f16out, int waves_per_group, int n_groups, hipStream_t s);
 // Resident groups per CU of the persistent sweep for this launch shape.
-hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_f32, int f16out, int waves_per_group,
+hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_u16, int f16out, int waves_per_group,
                                       int *groups_per_cu);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_argmin(const void *cost, int f16, int64_t rows, int L, int32_t *out, hipStream_t s);
@@ -152,7 +152,7 @@ struct PaintViews {
 };
 hipError_t launch_paint_depth(const PaintViews &pv, int n_views, int max_pixels, const int32_t *labels, int L,
                               const float *level_depth, float *out, hipStream_t s);
-hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
+hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_u16,
                          float *m_out, int32_t *hit_out, hipStream_t s);
 hipError_t launch_window_energy(int64_t rows, int L, const float *m, const int32_t *hit, const int32_t *labelling,
                                 float K, float *out, hipStream_t s);

@@ -82,16 +82,18 @@ __global__ void k_index_init(const Problem *__restrict__ P)
     if (i < 2 * v.n_bands) v.band_count[i] = 0;
 }
 
-// Packed texels: (W + 2) x (H + 2) of {Y, Cb, Cr, 0}, chroma replicated to
-// full resolution (pixel (x, y) owns chroma (x >> k, y >> k)).  Texel
-// (X, Y) holds pixel (clamp(X - 1), clamp(Y - 1)): a one-texel border that
-// repeats the edge, so a bilinear sample up to one pixel outside the image
-// reads the edge value, which is the clamped sample.  A thread packs
+// Packed texels: (W + 2) x (H + 2) of {Y, Cb, Cr, 0} in 16-bit channels
+// (8 bytes a texel), chroma replicated to full resolution (pixel (x, y) owns
+// chroma (x >> k, y >> k)).  Channels are halves for bit depths up to 11
+// and the 16-bit code values themselves (U16) above, exact either way.
+// Texel (X, Y) holds pixel (clamp(X - 1), clamp(Y - 1)): a one-texel border
+// that repeats the edge, so a bilinear sample up to one pixel outside the
+// image reads the edge value, which is the clamped sample.  A thread packs
 // kPackRows texels of one column (rows blockDim.y apart), its loads issued
 // together.
 constexpr int kPackRows = 4;
 
-template <typename TexT>
+template <bool U16>
 __global__ __launch_bounds__(256) void k_pack(const Problem *__restrict__ P)
 {
     const ViewDesc *vd = ldu(&P->views) + blockIdx.z;
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void k_pack(const Problem *__restrict__ P)
     const int X = blockIdx.x * blockDim.x + threadIdx.x;
     if (X > W + 1) return;
     const Planes pl = planes_of(P, vd);
-    TexT *tex = static_cast<TexT *>(ldu(&vd->tex));
+    uint2 *tex = static_cast<uint2 *>(ldu(&vd->tex));
     const int64_t tp = ldu(&vd->tex_pitch);
     const int x = min(max(X - 1, 0), W - 1);
     const int Y0 = blockIdx.y * (blockDim.y * kPackRows) + threadIdx.y;
@@ -113,15 +115,16 @@ __global__ __launch_bounds__(256) void k_pack(const Problem *__restrict__ P)
     for (int q = 0; q < kPackRows; ++q) {
         const int Y = Y0 + q * (int)blockDim.y;
         if (Y > H + 1) break;
-        TexT *t = tex + (int64_t)Y * tp + X;
-        if constexpr (sizeof(TexT) == 8) {
-            uint2 w;
+        uint2 w;
+        if constexpr (U16) {
+            // code values below 2^16, held exactly by the FP32 colours
+            w.x = (uint32_t)c0[q] | ((uint32_t)c1[q] << 16);
+            w.y = (uint32_t)c2[q];
+        } else {
             w.x = __builtin_bit_cast(uint32_t, __floats2half2_rn(c0[q], c1[q]));
             w.y = __builtin_bit_cast(uint32_t, __floats2half2_rn(c2[q], 0.f));
-            stg(reinterpret_cast<uint2 *>(t), w);
-        } else {
-            stg(reinterpret_cast<float4 *>(t), make_float4(c0[q], c1[q], c2[q], 0.f));
         }
+        stg(tex + (int64_t)Y * tp + X, w);
     }
 }
 
@@ -438,24 +441,16 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
     return make_uint4(x.x, x.y, y.x, y.y);
 }
 
-// Target samples of one evaluation, as loaded.
-template <bool BIL, bool TEXF32>
+// Target samples of one evaluation, as loaded (8-byte texels).
+template <bool BIL>
 struct Sample;
 template <>
-struct Sample<true, false> {   // half texels (x0, y0), (x0 + 1, y0) and the row below
+struct Sample<true> {   // texels (x0, y0), (x0 + 1, y0) and the row below
     uint4 a, b;
 };
 template <>
-struct Sample<true, true> {
-    float4 a0, a1, b0, b1;
-};
-template <>
-struct Sample<false, false> {
+struct Sample<false> {
     uint2 a;
-};
-template <>
-struct Sample<false, true> {
-    float4 a;
 };
 
 struct Weights {
@@ -485,11 +480,11 @@ struct Target {
 // 2 and also in front of this target (no test).  Out-of-image
 // coordinates are clamped, so every load is in bounds; the buffer
 // descriptor bounds them again.
-template <bool BIL, bool TEXF32, int FRONT, bool STAGED = false>
+template <bool BIL, int FRONT, bool STAGED = false>
 __device__ __forceinline__ void project_issue(const Target &T, float qx, float qy, float qz, float w,
-                                              Sample<BIL, TEXF32> &smp, Weights &wt, bool &valid)
+                                              Sample<BIL> &smp, Weights &wt, bool &valid)
 {
-    constexpr int kTexB = TEXF32 ? 16 : 8;
+    constexpr int kTexB = 8;
     const float hx = fmaf(w, T.e0, qx);
     const float hy = fmaf(w, T.e1, qy);
     const float hz = fmaf(w, T.e2, qz);
@@ -509,7 +504,7 @@ __device__ __forceinline__ void project_issue(const Target &T, float qx, float q
         wt.w01 = ax - wt.w11;
         wt.w10 = ay - wt.w11;
         wt.w00 = (1.f - ax) - wt.w10;
-        if constexpr (STAGED && !TEXF32) {
+        if constexpr (STAGED) {
             // the footprint staged in LDS, rows of srowB bytes
             const uint32_t a = mad_u24(x0, (uint32_t)kTexB, mad_u24(y0, T.srowB, T.sbase));
             smp.a = lds_pair(a);
@@ -517,71 +512,39 @@ __device__ __forceinline__ void project_issue(const Target &T, float qx, float q
             return;
         }
         const int off = (int)(mad_u24(y0, T.tp, x0) * kTexB);
-        if constexpr (!TEXF32) {
-            smp.a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
-            smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
-        } else {
-            smp.a0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
-            smp.a1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, 0, 0));
-            smp.b0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
-            smp.b1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off + 16, (int)T.rowB, 0));
-        }
+        smp.a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
+        smp.b = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, (int)T.rowB, 0));
     } else {
         const float fx = floorf(u + 0.5f), fy = floorf(v + 0.5f);
         valid &= (fx >= 1.f) & (fx <= T.hi_x - kEdge) & (fy >= 1.f) & (fy <= T.hi_y - kEdge);
         const uint32_t xi = (uint32_t)(int)fx, yi = (uint32_t)(int)fy;
         const int off = valid ? (int)(mad_u24(yi, T.tp, xi) * kTexB) : 0;
-        if constexpr (!TEXF32)
-            smp.a = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(T.rs, off, 0, 0));
-        else
-            smp.a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(T.rs, off, 0, 0));
+        smp.a = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(T.rs, off, 0, 0));
     }
 }
 
 // |dY| + |dCb| + |dCr| of one evaluation in code values.
-template <bool BIL, bool TEXF32>
-__device__ __forceinline__ float consume(const Sample<BIL, TEXF32> &smp, const Weights &wt, float ry, float ru,
-                                         float rv)
+template <bool BIL, bool U16>
+__device__ __forceinline__ float consume(const Sample<BIL> &smp, const Weights &wt, float ry, float ru, float rv)
 {
     float tY, tU, tV;
     if constexpr (BIL) {
-        if constexpr (!TEXF32) {
-            tY = fmaf(h_lo(smp.a.x), wt.w00, -ry);
-            tU = fmaf(h_hi(smp.a.x), wt.w00, -ru);
-            tV = fmaf(h_lo(smp.a.y), wt.w00, -rv);
-            tY = fmaf(h_lo(smp.a.z), wt.w01, tY);
-            tU = fmaf(h_hi(smp.a.z), wt.w01, tU);
-            tV = fmaf(h_lo(smp.a.w), wt.w01, tV);
-            tY = fmaf(h_lo(smp.b.x), wt.w10, tY);
-            tU = fmaf(h_hi(smp.b.x), wt.w10, tU);
-            tV = fmaf(h_lo(smp.b.y), wt.w10, tV);
-            tY = fmaf(h_lo(smp.b.z), wt.w11, tY);
-            tU = fmaf(h_hi(smp.b.z), wt.w11, tU);
-            tV = fmaf(h_lo(smp.b.w), wt.w11, tV);
-        } else {
-            tY = fmaf(smp.a0.x, wt.w00, -ry);
-            tU = fmaf(smp.a0.y, wt.w00, -ru);
-            tV = fmaf(smp.a0.z, wt.w00, -rv);
-            tY = fmaf(smp.a1.x, wt.w01, tY);
-            tU = fmaf(smp.a1.y, wt.w01, tU);
-            tV = fmaf(smp.a1.z, wt.w01, tV);
-            tY = fmaf(smp.b0.x, wt.w10, tY);
-            tU = fmaf(smp.b0.y, wt.w10, tU);
-            tV = fmaf(smp.b0.z, wt.w10, tV);
-            tY = fmaf(smp.b1.x, wt.w11, tY);
-            tU = fmaf(smp.b1.y, wt.w11, tU);
-            tV = fmaf(smp.b1.z, wt.w11, tV);
-        }
+        tY = fmaf(ch_lo<U16>(smp.a.x), wt.w00, -ry);
+        tU = fmaf(ch_hi<U16>(smp.a.x), wt.w00, -ru);
+        tV = fmaf(ch_lo<U16>(smp.a.y), wt.w00, -rv);
+        tY = fmaf(ch_lo<U16>(smp.a.z), wt.w01, tY);
+        tU = fmaf(ch_hi<U16>(smp.a.z), wt.w01, tU);
+        tV = fmaf(ch_lo<U16>(smp.a.w), wt.w01, tV);
+        tY = fmaf(ch_lo<U16>(smp.b.x), wt.w10, tY);
+        tU = fmaf(ch_hi<U16>(smp.b.x), wt.w10, tU);
+        tV = fmaf(ch_lo<U16>(smp.b.y), wt.w10, tV);
+        tY = fmaf(ch_lo<U16>(smp.b.z), wt.w11, tY);
+        tU = fmaf(ch_hi<U16>(smp.b.z), wt.w11, tU);
+        tV = fmaf(ch_lo<U16>(smp.b.w), wt.w11, tV);
     } else {
-        if constexpr (!TEXF32) {
-            tY = h_lo(smp.a.x) - ry;
-            tU = h_hi(smp.a.x) - ru;
-            tV = h_lo(smp.a.y) - rv;
-        } else {
-            tY = smp.a.x - ry;
-            tU = smp.a.y - ru;
-            tV = smp.a.z - rv;
-        }
+        tY = ch_lo<U16>(smp.a.x) - ry;
+        tU = ch_hi<U16>(smp.a.x) - ru;
+        tV = ch_lo<U16>(smp.a.y) - rv;
     }
     return fabsf(tY) + fabsf(tU) + fabsf(tV);
 }
@@ -589,14 +552,14 @@ __device__ __forceinline__ float consume(const Sample<BIL, TEXF32> &smp, const W
 // PU pixels x J labels per step: all gathers of the step are issued before
 // the first is consumed, so a wave keeps PU J of them in flight.  The
 // accumulation order per label is the pixel order either way.
-template <int J, int PU, bool BIL, bool TEXF32, int FRONT, bool STAGED = false>
+template <int J, int PU, bool BIL, bool U16, int FRONT, bool STAGED = false>
 __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int i0, int i1, const float (&H)[9],
                                              const Target &T, const float (&sig)[J], float (&acc)[J],
                                              uint64_t (&acci)[J], int (&cnt)[J])
 {
     int i = i0;
     for (; i + PU <= i1; i += PU) {
-        Sample<BIL, TEXF32> smp[PU][J];
+        Sample<BIL> smp[PU][J];
         Weights wt[PU][J];
         bool val[PU][J];
         float ry[PU], ru[PU], rv[PU];
@@ -613,8 +576,7 @@ __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int 
             const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8]));
 #pragma unroll
             for (int j = 0; j < J; ++j)
-                project_issue<BIL, TEXF32, FRONT, STAGED>(T, qx, qy, qz, sig[j] * gp, smp[p][j], wt[p][j],
-                                                          val[p][j]);
+                project_issue<BIL, FRONT, STAGED>(T, qx, qy, qz, sig[j] * gp, smp[p][j], wt[p][j], val[p][j]);
         }
         // keep the scheduler from sinking the loads back next to their uses
         if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
@@ -622,7 +584,7 @@ __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int 
         for (int p = 0; p < PU; ++p) {
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const float d = consume<BIL, TEXF32>(smp[p][j], wt[p][j], ry[p], ru[p], rv[p]);
+                const float d = consume<BIL, U16>(smp[p][j], wt[p][j], ry[p], ru[p], rv[p]);
                 if constexpr (BIL) {
                     acc[j] += val[p][j] ? d : 0.f;
                 } else {
@@ -633,7 +595,7 @@ __device__ __forceinline__ void sweep_pixels(const float *__restrict__ pix, int 
             }
         }
     }
-    if constexpr (PU > 1) sweep_pixels<J, 1, BIL, TEXF32, FRONT, STAGED>(pix, i, i1, H, T, sig, acc, acci, cnt);
+    if constexpr (PU > 1) sweep_pixels<J, 1, BIL, U16, FRONT, STAGED>(pix, i, i1, H, T, sig, acc, acci, cnt);
 }
 
 // One task: labels [64 J b, 64 J (b + 1)) of row (view, seg).
@@ -699,10 +661,9 @@ __device__ __forceinline__ bool stage_footprint(const ViewDesc *vc, const ViewDe
     return true;
 }
 
-template <int J, bool BIL, bool TEXF32, bool F16OUT, int STAGE = 0>
+template <int J, bool BIL, bool U16, bool F16OUT, int STAGE = 0>
 __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const Task task, uint2 *stage = nullptr)
 {
-    constexpr int kTexB = TEXF32 ? 16 : 8;
     constexpr int PU = IVDE_INFLIGHT / J > 0 ? IVDE_INFLIGHT / J : 1;
     const int lane = lane_id();
     const int c = task.view, s = task.seg;
@@ -740,7 +701,7 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
         T.hi_x = (float)ldu(&vt->W) + kEdge;
         T.hi_y = (float)ldu(&vt->H) + kEdge;
         T.tp = (uint32_t)ldu(&vt->tex_pitch);
-        T.rowB = (int)T.tp * kTexB;
+        T.rowB = (int)T.tp * 8;
         const float *pc = reinterpret_cast<const float *>(pairs + c * n + c2);
         const f32x4 ha = ldu4(pc), hb = ldu4(pc + 4), hc = ldu4(pc + 8);
         const float H[9] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w, hc.x};
@@ -758,20 +719,20 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
             cnt[j] = 0;
         }
         bool staged = false;
-        if constexpr (STAGE > 0 && J == 1 && BIL && !TEXF32) {
+        if constexpr (STAGE > 0 && J == 1 && BIL && !U16) {
             if (front_all && ((front_targets >> c2) & 1u) && p1 > p0) {
                 const int l_lo = task.lblock * kWave, l_hi = min(l_lo + kWave - 1, L - 1);
                 staged = stage_footprint<J>(vc, vt, s, l_lo, l_hi, sigma + c * L, H, T, stage, STAGE);
-                if (staged) sweep_pixels<J, PU, BIL, TEXF32, 2, true>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+                if (staged) sweep_pixels<J, PU, BIL, U16, 2, true>(pix, p0, p1, H, T, sig, acc, acci, cnt);
             }
         }
         if (staged) {
         } else if (front_all && ((front_targets >> c2) & 1u))
-            sweep_pixels<J, PU, BIL, TEXF32, 2>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+            sweep_pixels<J, PU, BIL, U16, 2>(pix, p0, p1, H, T, sig, acc, acci, cnt);
         else if (front_all)
-            sweep_pixels<J, PU, BIL, TEXF32, 1>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+            sweep_pixels<J, PU, BIL, U16, 1>(pix, p0, p1, H, T, sig, acc, acci, cnt);
         else
-            sweep_pixels<J, PU, BIL, TEXF32, 0>(pix, p0, p1, H, T, sig, acc, acci, cnt);
+            sweep_pixels<J, PU, BIL, U16, 0>(pix, p0, p1, H, T, sig, acc, acci, cnt);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             if (cnt[j] > 0) {
@@ -801,7 +762,7 @@ __device__ __forceinline__ void sweep_task(const Problem *__restrict__ P, const 
 // the others, so no XCD idles while another has work (with one XCD per view
 // in a view-major task list, views whose gathers cost more no longer set
 // the kernel's end).
-template <int J, bool BIL, bool TEXF32, bool F16OUT, int STAGE = 0>
+template <int J, bool BIL, bool U16, bool F16OUT, int STAGE = 0>
 __device__ __forceinline__ void sweep_persistent_body(const Problem *__restrict__ probs,
                                                       const Task *__restrict__ tasks,
                                                       const int32_t *__restrict__ n_tasks,
@@ -825,33 +786,33 @@ __device__ __forceinline__ void sweep_persistent_body(const Problem *__restrict_
             t = uniform(__shfl(t, 0));
             if (t >= n) break;
             const Task task = ldu_task(tasks + lo + t);
-            sweep_task<J, BIL, TEXF32, F16OUT, STAGE>(probs + task.problem, task, stage);
+            sweep_task<J, BIL, U16, F16OUT, STAGE>(probs + task.problem, task, stage);
         }
     }
 }
 
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
+template <int J, bool BIL, bool U16, bool F16OUT>
 __global__ __launch_bounds__(256) void k_sweep_persistent(const Problem *__restrict__ probs,
                                                           const Task *__restrict__ tasks,
                                                           const int32_t *__restrict__ n_tasks,
                                                           int32_t *__restrict__ cursors, int64_t max_tasks)
 {
-    sweep_persistent_body<J, BIL, TEXF32, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
+    sweep_persistent_body<J, BIL, U16, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
 }
 
-// One label per lane with half texels fits 64 VGPRs; at 8 waves per SIMD it
-// hides gather latency best (measured on the 8-view 1080p workload).
-template <bool BIL, bool F16OUT>
+// One label per lane fits 64 VGPRs; at 8 waves per SIMD it hides gather
+// latency best (measured on the 8-view 1080p workload).
+template <bool BIL, bool F16OUT, bool U16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_persistent_j1(
     const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
     int32_t *__restrict__ cursors, int64_t max_tasks)
 {
 #if IVDE_STAGE_TEXELS > 0
     __shared__ uint2 stage[4][IVDE_STAGE_TEXELS];
-    sweep_persistent_body<1, BIL, false, F16OUT, IVDE_STAGE_TEXELS>(probs, tasks, n_tasks, cursors, max_tasks,
-                                                                    stage[threadIdx.x / kWave]);
+    sweep_persistent_body<1, BIL, U16, F16OUT, IVDE_STAGE_TEXELS>(probs, tasks, n_tasks, cursors, max_tasks,
+                                                                  stage[threadIdx.x / kWave]);
 #else
-    sweep_persistent_body<1, BIL, false, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
+    sweep_persistent_body<1, BIL, U16, F16OUT>(probs, tasks, n_tasks, cursors, max_tasks);
 #endif
 }
 
@@ -870,17 +831,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // the stage holds the projection base already divided by g . p~ (see
 // stage_projected), so a step forms h with three multiply-adds; otherwise
 // it holds {x, y, Y | Cb, Cr} and a step forms q = H p~ and g . p~ as the
-// one-pixel sweep does.  Colours are FP16 (exact for samples up to 11 bits).
+// one-pixel sweep does.  Reference colours use the texels' 16-bit channels
+// (halves up to 11 bits, code values above), exact either way.
 // The two halves' sums and counts meet through one cross-lane exchange per
 // (target, pass).
 constexpr int kPairStage = 256;   // records one wave stages at a time (16 B + 2 B each)
 
-__device__ __forceinline__ uint32_t pack_h2(float a, float b)
+// Two reference colours (code values) in the 16-bit channels the texels use.
+template <bool U16>
+__device__ __forceinline__ uint32_t pack_ch(float a, float b)
 {
-    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+    if constexpr (U16)
+        return (uint32_t)a | ((uint32_t)b << 16);
+    else
+        return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
 }
 
 // Records [i0, i0 + n) of the view into the stage (n <= kPairStage).
+template <bool U16>
 __device__ __forceinline__ void stage_records(const float *__restrict__ pix, int i0, int n, uint4 *st)
 {
     const int lane = lane_id();
@@ -891,8 +859,8 @@ __device__ __forceinline__ void stage_records(const float *__restrict__ pix, int
             const float *r = pix + 8 * (int64_t)(i0 + t);
             const float4 r0 = ldg(reinterpret_cast<const float4 *>(r));
             const float2 r1 = ldg(reinterpret_cast<const float2 *>(r + 4));
-            st[t] = make_uint4(__float_as_uint(r0.x), __float_as_uint(r0.y), pack_h2(r0.w, r1.x),
-                               pack_h2(r1.y, 0.f));
+            st[t] = make_uint4(__float_as_uint(r0.x), __float_as_uint(r0.y), pack_ch<U16>(r0.w, r1.x),
+                               pack_ch<U16>(r1.y, 0.f));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -916,6 +884,7 @@ __device__ __forceinline__ void stage_records(const float *__restrict__ pix, int
 // put every level's sample inside, as the sweep computes it.
 constexpr float kInside = 1.0f / 16.0f;
 
+template <bool U16>
 __device__ __forceinline__ bool stage_projected(const float *__restrict__ pix, int i0, int n, const float (&H)[9],
                                                 const Target &T, float sig_a, float sig_b, uint4 *st, uint16_t *cr)
 {
@@ -932,8 +901,9 @@ __device__ __forceinline__ bool stage_projected(const float *__restrict__ pix, i
             const float qx = fmaf(H[0], x, fmaf(H[1], y, H[2])) * rg;
             const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5])) * rg;
             const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8])) * rg;
-            st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz), pack_h2(r0.w, r1.x));
-            cr[t] = (uint16_t)pack_h2(r1.y, 0.f);
+            st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz),
+                               pack_ch<U16>(r0.w, r1.x));
+            cr[t] = (uint16_t)pack_ch<U16>(r1.y, 0.f);
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const float w = k ? sig_b : sig_a;
@@ -950,14 +920,14 @@ __device__ __forceinline__ bool stage_projected(const float *__restrict__ pix, i
 }
 
 // Projection and gathers of one (pixel, label) for the pixel-pair sweep: as
-// project_issue with half texels, but the bilinear fractions are returned
+// project_issue, but the bilinear fractions are returned
 // instead of the four weights, which consume_pair forms (the same
 // operations, later), so fewer registers stay live across the gathers.
 // FRONT 3: as 2, and the sample is known to lie inside the validity band
 // (stage_projected), so it is neither clamped nor tested.
 template <bool BIL, int FRONT>
 __device__ __forceinline__ void project_pair(const Target &T, float qx, float qy, float qz, float w,
-                                             Sample<BIL, false> &smp, float &ax, float &ay, bool &valid)
+                                             Sample<BIL> &smp, float &ax, float &ay, bool &valid)
 {
     const float hx = fmaf(w, T.e0, qx);
     const float hy = fmaf(w, T.e1, qy);
@@ -989,12 +959,11 @@ __device__ __forceinline__ void project_pair(const Target &T, float qx, float qy
     }
 }
 
-// |dY| + |dCb| + |dCr| of one evaluation against reference colours held
-// as FP16 (rz = Y | Cb, rw = Cr), with the weights formed from the
-// bilinear fractions as project_issue forms them.
-template <bool BIL>
-__device__ __forceinline__ float consume_pair(const Sample<BIL, false> &smp, float ax, float ay, uint32_t rz,
-                                              uint32_t rw)
+// |dY| + |dCb| + |dCr| of one evaluation against reference colours held in
+// the texels' 16-bit channels (rz = Y | Cb, rw = Cr), with the weights
+// formed from the bilinear fractions as project_issue forms them.
+template <bool BIL, bool U16>
+__device__ __forceinline__ float consume_pair(const Sample<BIL> &smp, float ax, float ay, uint32_t rz, uint32_t rw)
 {
     float tY, tU, tV;
     if constexpr (BIL) {
@@ -1003,22 +972,22 @@ __device__ __forceinline__ float consume_pair(const Sample<BIL, false> &smp, flo
         wt.w01 = ax - wt.w11;
         wt.w10 = ay - wt.w11;
         wt.w00 = (1.f - ax) - wt.w10;
-        tY = fmaf(h_lo(smp.a.x), wt.w00, -h_lo(rz));
-        tU = fmaf(h_hi(smp.a.x), wt.w00, -h_hi(rz));
-        tV = fmaf(h_lo(smp.a.y), wt.w00, -h_lo(rw));
-        tY = fmaf(h_lo(smp.a.z), wt.w01, tY);
-        tU = fmaf(h_hi(smp.a.z), wt.w01, tU);
-        tV = fmaf(h_lo(smp.a.w), wt.w01, tV);
-        tY = fmaf(h_lo(smp.b.x), wt.w10, tY);
-        tU = fmaf(h_hi(smp.b.x), wt.w10, tU);
-        tV = fmaf(h_lo(smp.b.y), wt.w10, tV);
-        tY = fmaf(h_lo(smp.b.z), wt.w11, tY);
-        tU = fmaf(h_hi(smp.b.z), wt.w11, tU);
-        tV = fmaf(h_lo(smp.b.w), wt.w11, tV);
+        tY = fmaf(ch_lo<U16>(smp.a.x), wt.w00, -ch_lo<U16>(rz));
+        tU = fmaf(ch_hi<U16>(smp.a.x), wt.w00, -ch_hi<U16>(rz));
+        tV = fmaf(ch_lo<U16>(smp.a.y), wt.w00, -ch_lo<U16>(rw));
+        tY = fmaf(ch_lo<U16>(smp.a.z), wt.w01, tY);
+        tU = fmaf(ch_hi<U16>(smp.a.z), wt.w01, tU);
+        tV = fmaf(ch_lo<U16>(smp.a.w), wt.w01, tV);
+        tY = fmaf(ch_lo<U16>(smp.b.x), wt.w10, tY);
+        tU = fmaf(ch_hi<U16>(smp.b.x), wt.w10, tU);
+        tV = fmaf(ch_lo<U16>(smp.b.y), wt.w10, tV);
+        tY = fmaf(ch_lo<U16>(smp.b.z), wt.w11, tY);
+        tU = fmaf(ch_hi<U16>(smp.b.z), wt.w11, tU);
+        tV = fmaf(ch_lo<U16>(smp.b.w), wt.w11, tV);
     } else {
-        tY = h_lo(smp.a.x) - h_lo(rz);
-        tU = h_hi(smp.a.x) - h_hi(rz);
-        tV = h_lo(smp.a.y) - h_lo(rw);
+        tY = ch_lo<U16>(smp.a.x) - ch_lo<U16>(rz);
+        tU = ch_hi<U16>(smp.a.x) - ch_hi<U16>(rz);
+        tV = ch_lo<U16>(smp.a.y) - ch_lo<U16>(rw);
     }
     return fabsf(tY) + fabsf(tU) + fabsf(tV);
 }
@@ -1027,14 +996,14 @@ __device__ __forceinline__ float consume_pair(const Sample<BIL, false> &smp, flo
 // either half at level sig): PU pairs per step with every gather issued
 // before the first is consumed, then the remaining pairs one at a time (the
 // last possibly with one pixel).
-template <int PU, bool BIL, int FRONT, int G>
+template <int PU, bool BIL, int FRONT, int G, bool U16>
 __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h, const float (&H)[9],
                                                    const float (&g)[3], const Target &T, float sig, float &acc,
                                                    uint64_t &acci, int &cnt)
 {
     int i = 0;
     for (; i + G * PU <= m; i += G * PU) {
-        Sample<BIL, false> smp[PU];
+        Sample<BIL> smp[PU];
         float ax[PU], ay[PU];
         bool val[PU];
         uint32_t rz[PU], rw[PU];
@@ -1053,7 +1022,7 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
         if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
-            const float d = consume_pair<BIL>(smp[u], ax[u], ay[u], rz[u], rw[u]);
+            const float d = consume_pair<BIL, U16>(smp[u], ax[u], ay[u], rz[u], rw[u]);
             if constexpr (BIL)
                 acc += val[u] ? d : 0.f;
             else
@@ -1070,12 +1039,12 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
         const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5]));
         const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8]));
         const float gp = fmaf(g[0], x, fmaf(g[1], y, g[2]));
-        Sample<BIL, false> smp;
+        Sample<BIL> smp;
         float ax, ay;
         bool val;
         project_pair<BIL, FRONT>(T, qx, qy, qz, sig * gp, smp, ax, ay, val);
         val &= here;
-        const float d = consume_pair<BIL>(smp, ax, ay, r.z, r.w);
+        const float d = consume_pair<BIL, U16>(smp, ax, ay, r.z, r.w);
         if constexpr (BIL)
             acc += val ? d : 0.f;
         else
@@ -1088,14 +1057,14 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
 // proven in front of every level point, at one pass (lane k of either half
 // at level sig): as sweep_pair_records with h = q' + sig e; FRONT 3 when
 // every sample of the chunk lies inside the validity band.
-template <int PU, bool BIL, int FRONT, int G>
+template <int PU, bool BIL, int FRONT, int G, bool U16>
 __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint16_t *cr, int m, int h,
                                                      const Target &T, float sig, float &acc, uint64_t &acci,
                                                      int &cnt)
 {
     int i = 0;
     for (; i + G * PU <= m; i += G * PU) {
-        Sample<BIL, false> smp[PU];
+        Sample<BIL> smp[PU];
         float ax[PU], ay[PU];
         bool val[PU];
         uint32_t rz[PU], rw[PU];
@@ -1110,7 +1079,7 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
         if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
-            const float d = consume_pair<BIL>(smp[u], ax[u], ay[u], rz[u], rw[u]);
+            const float d = consume_pair<BIL, U16>(smp[u], ax[u], ay[u], rz[u], rw[u]);
             if constexpr (BIL)
                 acc += val[u] ? d : 0.f;
             else
@@ -1123,13 +1092,13 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
         const bool here = j < m;
         const int jj = here ? j : m - 1;
         const uint4 r = st[jj];
-        Sample<BIL, false> smp;
+        Sample<BIL> smp;
         float ax, ay;
         bool val;
         project_pair<BIL, FRONT>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp, ax,
                                  ay, val);
         val &= here;
-        const float d = consume_pair<BIL>(smp, ax, ay, r.w, cr[jj]);
+        const float d = consume_pair<BIL, U16>(smp, ax, ay, r.w, cr[jj]);
         if constexpr (BIL)
             acc += val ? d : 0.f;
         else
@@ -1170,7 +1139,7 @@ struct PairSteps {
 // G pixels per wave step (2: pairs, 4: quads): lane group h = lane / (64 / G)
 // takes records h, h + G, ...; lane k of a group takes level
 // 64 b + (64 / G) q + k in pass q.
-template <bool BIL, bool F16OUT, int G>
+template <bool BIL, bool F16OUT, int G, bool U16>
 __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
                                                  uint16_t *cr, PairSteps &ns)
 {
@@ -1242,28 +1211,28 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
             ns.all += steps;
             if (front == 2) {
                 ns.projected += steps;
-                const bool inside = stage_projected(pix, p0 + b0, m, H, T, sig_a, sig_b, st, cr);
+                const bool inside = stage_projected<U16>(pix, p0 + b0, m, H, T, sig_a, sig_b, st, cr);
                 if (IVDE_PAIR_INSIDE && inside) {
                     ns.inside += steps;
 #pragma unroll
                     for (int q = 0; q < G; ++q)
                         if (q < passes)
-                            sweep_pair_projected<PU, BIL, 3, G>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                            sweep_pair_projected<PU, BIL, 3, G, U16>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
                 } else {
 #pragma unroll
                     for (int q = 0; q < G; ++q)
                         if (q < passes)
-                            sweep_pair_projected<PU, BIL, 2, G>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
+                            sweep_pair_projected<PU, BIL, 2, G, U16>(st, cr, m, h, T, sig[q], acc[q], acci[q], cnt[q]);
                 }
             } else {
-                stage_records(pix, p0 + b0, m, st);
+                stage_records<U16>(pix, p0 + b0, m, st);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
                     if (q >= passes) continue;
                     if (front == 1)
-                        sweep_pair_records<PU, BIL, 1, G>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
+                        sweep_pair_records<PU, BIL, 1, G, U16>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
                     else
-                        sweep_pair_records<PU, BIL, 0, G>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
+                        sweep_pair_records<PU, BIL, 0, G, U16>(st, m, h, H, g, T, sig[q], acc[q], acci[q], cnt[q]);
                 }
             }
         }
@@ -1302,7 +1271,7 @@ __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, 
     }
 }
 
-template <bool BIL, bool F16OUT, int G>
+template <bool BIL, bool F16OUT, int G, bool U16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     G == 4 ? IVDE_QUAD_WAVES_PER_SIMD : IVDE_PAIR_WAVES_PER_SIMD, G == 4 ? IVDE_QUAD_WAVES_PER_SIMD : IVDE_PAIR_WAVES_PER_SIMD))) void k_sweep_pairs(
     const Problem *__restrict__ probs, const Task *__restrict__ tasks, const int32_t *__restrict__ n_tasks,
@@ -1342,7 +1311,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
                 flush();
                 cur = task.problem;
             }
-            sweep_task_pairs<BIL, F16OUT, G>(probs + task.problem, task, st, cr, ns);
+            sweep_task_pairs<BIL, F16OUT, G, U16>(probs + task.problem, task, st, cr, ns);
         }
     }
     flush();
@@ -1499,19 +1468,19 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
+hipError_t launch_pack(const Problem *dprob, const Extents &ext, int tex_u16, hipStream_t s)
 {
     dim3 blk(64, 4);
     const int rows = 4 * kPackRows;
     dim3 grd((unsigned)((ext.max_w + 2 + 63) / 64), (unsigned)((ext.max_h + 2 + rows - 1) / rows), (unsigned)ext.n_views);
-    if (tex_f32)
-        hipLaunchKernelGGL(k_pack<float4>, grd, blk, 0, s, dprob);
+    if (tex_u16)
+        hipLaunchKernelGGL(k_pack<true>, grd, blk, 0, s, dprob);
     else
-        hipLaunchKernelGGL(k_pack<uint2>, grd, blk, 0, s, dprob);
+        hipLaunchKernelGGL(k_pack<false>, grd, blk, 0, s, dprob);
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s, bool pack)
+hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_u16, hipStream_t s, bool pack)
 {
     const unsigned nv = (unsigned)ext.n_views;
     {
@@ -1519,7 +1488,7 @@ hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32,
         hipLaunchKernelGGL(k_index_init, dim3((unsigned)((n + 255) / 256), nv), dim3(256), 0, s, dprob);
     }
     if (pack) {
-        const hipError_t e = launch_pack(dprob, ext, tex_f32, s);
+        const hipError_t e = launch_pack(dprob, ext, tex_u16, s);
         if (e != hipSuccess) return e;
     }
     {
@@ -1532,11 +1501,11 @@ hipError_t launch_prepare(const Problem *dprob, const Extents &ext, int tex_f32,
     return hipGetLastError();
 }
 
-hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_f32, hipStream_t s)
+hipError_t launch_refresh(const Problem *dprob, const Extents &ext, int tex_u16, hipStream_t s)
 {
     const unsigned nv = (unsigned)ext.n_views;
     {
-        const hipError_t e = launch_pack(dprob, ext, tex_f32, s);
+        const hipError_t e = launch_pack(dprob, ext, tex_u16, s);
         if (e != hipSuccess) return e;
     }
     const int64_t px = (int64_t)ext.max_w * ext.max_h;
@@ -1560,22 +1529,22 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
 // records, then the 2-byte Cr halves of the projected form).
 static size_t pair_stage_bytes(int wpg) { return (size_t)wpg * kPairStage * (sizeof(uint4) + sizeof(uint16_t)); }
 
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
+template <int J, bool BIL, bool U16, bool F16OUT>
 static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursors,
                              int64_t max_tasks, int px, int wpg, int n_groups, hipStream_t s)
 {
-    if constexpr (J == 1 && !TEXF32) {
+    if constexpr (J == 1) {
         if (px == 4)
-            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 4>), dim3((unsigned)n_groups), dim3(64 * wpg),
+            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 4, U16>), dim3((unsigned)n_groups), dim3(64 * wpg),
                                pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
         else if (px == 2)
-            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 2>), dim3((unsigned)n_groups), dim3(64 * wpg),
+            hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 2, U16>), dim3((unsigned)n_groups), dim3(64 * wpg),
                                pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
         else
-            hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0, s,
-                               dprobs, tasks, n_tasks, cursors, max_tasks);
+            hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT, U16>), dim3((unsigned)n_groups), dim3(64 * wpg), 0,
+                               s, dprobs, tasks, n_tasks, cursors, max_tasks);
     } else
-        hipLaunchKernelGGL((k_sweep_persistent<J, BIL, TEXF32, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0,
+        hipLaunchKernelGGL((k_sweep_persistent<J, BIL, U16, F16OUT>), dim3((unsigned)n_groups), dim3(64 * wpg), 0,
                            s, dprobs, tasks, n_tasks, cursors, max_tasks);
     return hipGetLastError();
 }
@@ -1583,43 +1552,44 @@ static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int
 #define IVDE_DISPATCH_FLAGS(FN, J, ...)                                                      \
     do {                                                                                     \
         if (bilinear) {                                                                      \
-            if (tex_f32) {                                                                   \
+            if (tex_u16) {                                                                   \
                 return f16out ? FN<J, true, true, true>(__VA_ARGS__) : FN<J, true, true, false>(__VA_ARGS__); \
             }                                                                                \
             return f16out ? FN<J, true, false, true>(__VA_ARGS__) : FN<J, true, false, false>(__VA_ARGS__); \
         }                                                                                    \
-        if (tex_f32) {                                                                       \
+        if (tex_u16) {                                                                       \
             return f16out ? FN<J, false, true, true>(__VA_ARGS__) : FN<J, false, true, false>(__VA_ARGS__); \
         }                                                                                    \
         return f16out ? FN<J, false, false, true>(__VA_ARGS__) : FN<J, false, false, false>(__VA_ARGS__); \
     } while (0)
 
-template <int J, bool BIL, bool TEXF32, bool F16OUT>
+template <int J, bool BIL, bool U16, bool F16OUT>
 static hipError_t occ(int px, int wpg, int *per_cu)
 {
-    if constexpr (J == 1 && !TEXF32) {
+    if constexpr (J == 1) {
         if (px == 4)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 4>, 64 * wpg,
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 4, U16>, 64 * wpg,
                                                                 pair_stage_bytes(wpg));
         if (px == 2)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 2>, 64 * wpg,
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 2, U16>, 64 * wpg,
                                                                 pair_stage_bytes(wpg));
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent_j1<BIL, F16OUT>, 64 * wpg, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent_j1<BIL, F16OUT, U16>, 64 * wpg,
+                                                            0);
     } else
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<J, BIL, TEXF32, F16OUT>,
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<J, BIL, U16, F16OUT>,
                                                             64 * wpg, 0);
 }
 
-hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_f32, int f16out, int wpg, int *per_cu)
+hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_u16, int f16out, int wpg, int *per_cu)
 {
     const int f16 = f16out;
 #define IVDE_OCC(JJ)                                                                                   \
     do {                                                                                              \
         if (bilinear) {                                                                               \
-            if (tex_f32) return f16 ? occ<JJ, true, true, true>(px, wpg, per_cu) : occ<JJ, true, true, false>(px, wpg, per_cu); \
+            if (tex_u16) return f16 ? occ<JJ, true, true, true>(px, wpg, per_cu) : occ<JJ, true, true, false>(px, wpg, per_cu); \
             return f16 ? occ<JJ, true, false, true>(px, wpg, per_cu) : occ<JJ, true, false, false>(px, wpg, per_cu); \
         }                                                                                             \
-        if (tex_f32) return f16 ? occ<JJ, false, true, true>(px, wpg, per_cu) : occ<JJ, false, true, false>(px, wpg, per_cu); \
+        if (tex_u16) return f16 ? occ<JJ, false, true, true>(px, wpg, per_cu) : occ<JJ, false, true, false>(px, wpg, per_cu); \
         return f16 ? occ<JJ, false, false, true>(px, wpg, per_cu) : occ<JJ, false, false, false>(px, wpg, per_cu); \
     } while (0)
     switch (J) {
@@ -1633,7 +1603,7 @@ hipError_t sweep_persistent_occupancy(int J, int px, int bilinear, int tex_f32, 
 }
 
 hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks_dev,
-                                   int32_t *cursors, int64_t max_tasks, int J, int px, int bilinear, int tex_f32,
+                                   int32_t *cursors, int64_t max_tasks, int J, int px, int bilinear, int tex_u16,
                                    int f16out, int wpg, int n_groups, hipStream_t s)
 {
     switch (J) {
@@ -1646,7 +1616,7 @@ hipError_t launch_sweep_persistent(const Problem *dprobs, const Task *tasks, con
 }
 
 hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_tasks, int J, int px, int bilinear,
-                        int tex_f32, int f16out, int wpg, int32_t *counters, hipStream_t s)
+                        int tex_u16, int f16out, int wpg, int32_t *counters, hipStream_t s)
 {
     if (n_tasks <= 0) return hipSuccess;
     if (n_tasks > 0x7fffffff) return hipErrorInvalidValue;
@@ -1654,11 +1624,11 @@ hipError_t launch_sweep(const Problem *dprobs, const Task *tasks, int64_t n_task
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = sweep_persistent_occupancy(J, px, bilinear, tex_f32, f16out, wpg, &per_cu)) != hipSuccess) return e;
+    if ((e = sweep_persistent_occupancy(J, px, bilinear, tex_u16, f16out, wpg, &per_cu)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sweep_counters, dim3(1), dim3(64), 0, s, counters, (int32_t)n_tasks);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int n_groups = std::max(1, cus) * std::max(1, per_cu);
-    return launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, n_tasks, J, px, bilinear, tex_f32,
+    return launch_sweep_persistent(dprobs, tasks, counters + kXcds, counters, n_tasks, J, px, bilinear, tex_u16,
                                    f16out, wpg, n_groups, s);
 }
 

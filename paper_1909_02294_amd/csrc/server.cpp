@@ -405,12 +405,12 @@ ivde_status ivde_server::start(Request &r, Slot &sl, Rig &rig)
     const Layout &ly = r.ly;
     Task *tasks = reinterpret_cast<Task *>(ws + ly.off_tasks);
     // the first frame (or one with another texel format) builds the index
-    const bool index_ready = rig.index_tex == ly.tex_f32;
+    const bool index_ready = rig.index_tex == ly.tex_u16;
     rig.index_tex = -1;
     ivde_status st = enqueue_front(rig.n, rig.cams.data(), r.views.data(), rig.segs.data(), &rig.labels, &rig.opt, ly,
                                    ws, rig.cost, 0, tasks, s, index_ready);
     if (st != IVDE_OK) return st;
-    rig.index_tex = ly.tex_f32;
+    rig.index_tex = ly.tex_u16;
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
     const int bil = rig.opt.sampling == IVDE_BILINEAR;
     char *extra = arena_base + r.work_off;
@@ -432,7 +432,7 @@ ivde_status ivde_server::start(Request &r, Slot &sl, Rig &rig)
         const int64_t pieces = chunk_evals > 0 ? (evals + chunk_evals - 1) / chunk_evals : 1;
         r.chunk_tasks = pieces > 1 && ly.n_tasks > 1 ? (ly.n_tasks + pieces - 1) / pieces : 0;
         if (r.chunk_tasks > 0) return pump(r, sl, rig);
-        if ((e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, ly.px, bil, ly.tex_f32, ly.f16, ly.wpg, counters + 8, s)) !=
+        if ((e = launch_sweep(dp, tasks, ly.n_tasks, ly.J, ly.px, bil, ly.tex_u16, ly.f16, ly.wpg, counters + 8, s)) !=
             hipSuccess)
             return hip_fail(e, "serve sweep");
     } else {
@@ -452,11 +452,11 @@ ivde_status ivde_server::start(Request &r, Slot &sl, Rig &rig)
         if ((e = launch_compact_tasks(dp, tasks, ly.n_tasks, mask, changed, counters, s)) != hipSuccess)
             return hip_fail(e, "serve compaction");
         int per_cu = 0, cus = 0;
-        if ((e = sweep_persistent_occupancy(ly.J, ly.px, bil, ly.tex_f32, ly.f16, ly.wpg, &per_cu)) != hipSuccess)
+        if ((e = sweep_persistent_occupancy(ly.J, ly.px, bil, ly.tex_u16, ly.f16, ly.wpg, &per_cu)) != hipSuccess)
             return hip_fail(e, "occupancy");
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess)
             return hip_fail(e, "device attribute");
-        if ((e = launch_sweep_persistent(dp, changed, counters, counters + 8, ly.n_tasks, ly.J, ly.px, bil, ly.tex_f32, ly.f16,
+        if ((e = launch_sweep_persistent(dp, changed, counters, counters + 8, ly.n_tasks, ly.J, ly.px, bil, ly.tex_u16, ly.f16,
                                          ly.wpg, std::max(1, per_cu) * std::max(1, cus), s)) != hipSuccess)
             return hip_fail(e, "serve sweep");
         if ((e = hipMemcpyAsync(sl.count_host, counters, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
@@ -476,7 +476,7 @@ ivde_status ivde_server::pump(Request &r, Slot &sl, Rig &rig)
     const Task *tasks = reinterpret_cast<const Task *>(rig.ws + ly.off_tasks);
     int32_t *counters = reinterpret_cast<int32_t *>(arena_base + r.work_off);
     const int64_t n = std::min(r.chunk_tasks, ly.n_tasks - r.chunk_next);
-    hipError_t e = launch_sweep(dp, tasks + r.chunk_next, n, ly.J, ly.px, rig.opt.sampling == IVDE_BILINEAR, ly.tex_f32,
+    hipError_t e = launch_sweep(dp, tasks + r.chunk_next, n, ly.J, ly.px, rig.opt.sampling == IVDE_BILINEAR, ly.tex_u16,
                                 ly.f16, ly.wpg, counters + 8, sl.stream);
     if (e != hipSuccess) return hip_fail(e, "serve sweep");
     r.chunk_next += n;

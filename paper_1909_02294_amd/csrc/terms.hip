@@ -235,20 +235,13 @@ __global__ void k_row_tasks(const Problem *__restrict__ P, Task *__restrict__ ta
 }
 
 // ------------------------------------------------------------------ window matching core
-template <bool TEXF32>
+template <bool U16>
 __device__ __forceinline__ void texel_at(const void *tex, uint32_t tp, int X, int Y, float &y, float &u, float &v)
 {
-    if constexpr (TEXF32) {
-        const float4 t = static_cast<const float4 *>(tex)[(int64_t)Y * tp + X];
-        y = t.x;
-        u = t.y;
-        v = t.z;
-    } else {
-        const uint2 t = static_cast<const uint2 *>(tex)[(int64_t)Y * tp + X];
-        y = h_lo(t.x);
-        u = h_hi(t.x);
-        v = h_lo(t.y);
-    }
+    const uint2 t = static_cast<const uint2 *>(tex)[(int64_t)Y * tp + X];
+    y = ch_lo<U16>(t.x);
+    u = ch_hi<U16>(t.x);
+    v = ch_lo<U16>(t.y);
 }
 
 // The paper's matching core at the segment centre (Sec. III-C, Eq. (4))
@@ -260,12 +253,12 @@ __device__ __forceinline__ void texel_at(const void *tex, uint32_t tp, int X, in
 // R > 0 fixes the radius at compile time: the source window (the same for
 // every lane) is read once per wave and all target taps are issued before
 // the first is used.  R == 0 takes any radius at run time.
-template <bool TEXF32, int R>
+template <bool U16, int R>
 __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, const Task *__restrict__ tasks,
                                                 int64_t n_tasks, int radius, float *__restrict__ m_out,
                                                 int32_t *__restrict__ hit_out)
 {
-    constexpr int kTexB = TEXF32 ? 16 : 8;
+    constexpr int kTexB = 8;
     constexpr int kSide = 2 * R + 1;
     constexpr int kTaps = R > 0 ? kSide * kSide : 1;
     const int lane = lane_id();
@@ -295,7 +288,7 @@ __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, c
             for (int dy = 0; dy < kSide; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < kSide; ++dx)
-                    texel_at<TEXF32>(stex, stp, min(max(cx + dx - R, 0), Wc - 1) + 1,
+                    texel_at<U16>(stex, stp, min(max(cx + dx - R, 0), Wc - 1) + 1,
                                      min(max(cy + dy - R, 0), Hc - 1) + 1, sy[dy * kSide + dx], su[dy * kSide + dx],
                                      sv[dy * kSide + dx]);
         }
@@ -334,16 +327,7 @@ __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, c
                         colo[k] = (min(max(tx + k - R, 0), W2 - 1) + 1) * kTexB;
                         rowo[k] = (min(max(ty + k - R, 0), H2 - 1) + 1) * (int)ttp * kTexB;
                     }
-                    if constexpr (TEXF32) {
-                        float4 tv[kTaps];
-#pragma unroll
-                        for (int k = 0; k < kTaps; ++k)
-                            tv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                                   rs, rowo[k / kSide] + colo[k % kSide], 0, 0));
-#pragma unroll
-                        for (int k = 0; k < kTaps; ++k)
-                            sum += fabsf(sy[k] - tv[k].x) + fabsf(su[k] - tv[k].y) + fabsf(sv[k] - tv[k].z);
-                    } else if constexpr (R == 1) {
+                    if constexpr (R == 1) {
                         // the one-texel border repeats the edge pixels, so the
                         // taps of a row are the three texels from (tx, ty + k),
                         // and no clamp is needed: one 16-byte and one 8-byte load
@@ -358,8 +342,8 @@ __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, c
                         }
 #pragma unroll
                         for (int k = 0; k < kTaps; ++k)
-                            sum += fabsf(sy[k] - h_lo(tv[k].x)) + fabsf(su[k] - h_hi(tv[k].x)) +
-                                   fabsf(sv[k] - h_lo(tv[k].y));
+                            sum += fabsf(sy[k] - ch_lo<U16>(tv[k].x)) + fabsf(su[k] - ch_hi<U16>(tv[k].x)) +
+                                   fabsf(sv[k] - ch_lo<U16>(tv[k].y));
                     } else {
                         uint2 tv[kTaps];
 #pragma unroll
@@ -368,16 +352,16 @@ __global__ __launch_bounds__(256) void k_window(const Problem *__restrict__ P, c
                                                                   rs, rowo[k / kSide] + colo[k % kSide], 0, 0));
 #pragma unroll
                         for (int k = 0; k < kTaps; ++k)
-                            sum += fabsf(sy[k] - h_lo(tv[k].x)) + fabsf(su[k] - h_hi(tv[k].x)) +
-                                   fabsf(sv[k] - h_lo(tv[k].y));
+                            sum += fabsf(sy[k] - ch_lo<U16>(tv[k].x)) + fabsf(su[k] - ch_hi<U16>(tv[k].x)) +
+                                   fabsf(sv[k] - ch_lo<U16>(tv[k].y));
                     }
                 } else {
                     for (int dy = -radius; dy <= radius; ++dy)
                         for (int dx = -radius; dx <= radius; ++dx) {
                             float ay, au, av, by, bu, bv;
-                            texel_at<TEXF32>(stex, stp, min(max(cx + dx, 0), Wc - 1) + 1,
+                            texel_at<U16>(stex, stp, min(max(cx + dx, 0), Wc - 1) + 1,
                                              min(max(cy + dy, 0), Hc - 1) + 1, ay, au, av);
-                            texel_at<TEXF32>(ttex, ttp, min(max(tx + dx, 0), W2 - 1) + 1,
+                            texel_at<U16>(ttex, ttp, min(max(tx + dx, 0), W2 - 1) + 1,
                                              min(max(ty + dy, 0), H2 - 1) + 1, by, bu, bv);
                             sum += fabsf(ay - by) + fabsf(au - bu) + fabsf(av - bv);
                         }
@@ -782,14 +766,14 @@ hipError_t launch_copy_rows_where(int64_t rows, int row_bytes, const uint8_t *so
     return hipGetLastError();
 }
 
-hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_f32,
+hipError_t launch_window(const Problem *dprob, const Task *tasks, int64_t n_tasks, int radius, int tex_u16,
                          float *m_out, int32_t *hit_out, hipStream_t s)
 {
     if (n_tasks <= 0) return hipSuccess;
     const int64_t blocks = (n_tasks + 3) / 4;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 g((unsigned)blocks), b(256);
-    if (tex_f32) {
+    if (tex_u16) {
         if (radius == 1)
             hipLaunchKernelGGL((k_window<true, 1>), g, b, 0, s, dprob, tasks, n_tasks, radius, m_out, hit_out);
         else

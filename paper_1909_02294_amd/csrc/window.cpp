@@ -68,7 +68,7 @@ ivde_status ivde_window_cost(int32_t n_views, const ivde_camera *cams, const ivd
     st = enqueue_stats(n_views, cams, views, segs, labels, &o, ly, ws, tasks, nullptr, s);
     if (st != IVDE_OK) return st;
     const Problem *dp = reinterpret_cast<const Problem *>(ws + ly.off_problem);
-    hipError_t e = launch_window(dp, tasks, ly.n_tasks, radius, ly.tex_f32, m_out, hit_out, s);
+    hipError_t e = launch_window(dp, tasks, ly.n_tasks, radius, ly.tex_u16, m_out, hit_out, s);
     if (e != hipSuccess) return hip_fail(e, "window matching");
     return IVDE_OK;
 }

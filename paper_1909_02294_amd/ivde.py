@@ -615,8 +615,8 @@ def autotune(dv: DeviceViews, lr: LabelRange, opt: Options, reps=2, stream=None)
 
 def shape_class(dv: DeviceViews, lr: LabelRange, opt: Options) -> str:
     """The class of problems that share a tuned launch shape: what the
-    sweep's speed depends on.  Sampling, storage type, texel format (images
-    up to 11 bits pack into FP16 texels), levels rounded up to a 64-level
+    sweep's speed depends on.  Sampling, storage type, texel encoding (FP16
+    channels up to 11 bits, 16-bit code values above), levels rounded up to a 64-level
     block, pixels per segment to the nearest power of two (per-task overhead
     against per-pixel work), and targets per view."""
     npx = sum(c.width * c.height for c in dv.cams)

@@ -104,8 +104,9 @@ def test_sweep_steps_needs_a_workspace(lib):
 
 def test_sweep_shape_query(lib):
     """The launch shape the plain call takes: the pixel-pair sweep by default
-    (one label per lane, half texels), the one-pixel sweep where asked for,
-    with more labels per lane, or with FP32 texels (12 bits and more)."""
+    (one label per lane, at any bit depth: FP16 texel channels up to 11 bits,
+    16-bit code values above), the one-pixel sweep where asked for or with
+    more labels per lane."""
     n, w, h, S = 3, 40, 30, 17
     lr = ivde.label_range(1.0, 5.0, 256)
 
@@ -119,12 +120,14 @@ def test_sweep_shape_query(lib):
     assert shape(ivde.options(ivde.BILINEAR, ivde.F32)) == (1, 4, 2)
     assert shape(ivde.options(ivde.NEAREST, ivde.F16)) == (1, 4, 2)
     assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=8) == (1, 4, 2)
-    assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=12) == (1, 4, 1)
+    assert shape(ivde.options(ivde.BILINEAR, ivde.F32), bits=12) == (1, 4, 2)
+    assert shape(ivde.options(ivde.NEAREST, ivde.F32), bits=16) == (1, 4, 2)
     assert shape(ivde.options(pixels_per_step=1)) == (1, 4, 1)
     assert shape(ivde.options(pixels_per_step=4)) == (1, 4, 4)
     assert shape(ivde.options(labels_per_lane=2, waves_per_group=2)) == (2, 2, 1)
     assert shape(ivde.options(labels_per_lane=2, pixels_per_step=2)) == (2, 4, 1)
-    assert shape(ivde.options(pixels_per_step=4), bits=12) == (1, 4, 1)
+    assert shape(ivde.options(pixels_per_step=4), bits=12) == (1, 4, 4)
+    assert shape(ivde.options(pixels_per_step=1), bits=16) == (1, 4, 1)
     # few levels over the same depth range land far apart: four pixels per step
     lr_far = ivde.label_range(1.0, 5.0, 16)
     j, wpg, px = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

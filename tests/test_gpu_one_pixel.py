@@ -2,7 +2,7 @@
 sweep (pixels_per_step = 1: one pixel at 64 levels per wave step, pixel
 records through the scalar unit).  The pixel-pair sweep is the default
 wherever it exists, so without this module the one-pixel form would only
-run for FP32 texels (12 bits and more) and more labels per lane; both
+run with more labels per lane; both
 forms compute the same quantity and are held to the same bars against the
 FP64 oracle."""
 import pytest

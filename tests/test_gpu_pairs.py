@@ -67,6 +67,9 @@ def test_pairs_nearest_rectified_equals_one_pixel_sweep(npx):
     dict(n_views=4, width=31, height=17, n_seg=12, L=65, bilinear=True, rotated=True, bit_depth=10),
     dict(n_views=5, width=24, height=16, n_seg=9, L=300, rotated=True, bilinear=True),
     dict(n_views=3, width=40, height=23, n_seg=2, L=40, rotated=True, bilinear=True, bit_depth=11),
+    dict(n_views=3, width=40, height=23, n_seg=20, L=129, rotated=True, bit_depth=12, chroma_shift=1, bilinear=True),
+    dict(n_views=3, width=40, height=23, n_seg=20, L=33, rotated=True, bit_depth=16),
+    dict(n_views=3, width=40, height=23, n_seg=3, L=70, rotated=True, bit_depth=16, bilinear=True),
 ])
 @pytest.mark.parametrize("npx", [2, 4])
 def test_pairs_tiny_cases(case, npx):
@@ -74,6 +77,35 @@ def test_pairs_tiny_cases(case, npx):
     ns = P.tiny_problem(22, **case)
     G, _ = run_gpu(ns, pixels_per_step=npx)
     compare(G, run_oracle(ns), label=str(case))
+
+
+@pytest.mark.parametrize("bits", [12, 16])
+@pytest.mark.parametrize("npx", [2, 4])
+def test_pairs_high_bit_depth(bits, npx):
+    """12- and 16-bit content, whose code values FP16 cannot hold (it holds
+    integers exactly only up to 2^11): texel channels and staged reference
+    colours are then the 16-bit code values themselves.  Bilinear on an arc
+    rig against the oracle and the one-pixel sweep; nearest on a rectified
+    rig whose disparities stay off half pixels (so the sampled texels do not
+    hang on the projection's last bit) bitwise equal to the one-pixel sweep
+    and to the oracle's integer sums, with segments over one stage."""
+    _case(f"{npx} px arc {bits} bits")
+    wl = synth.make_small_arc(seed=5, n_segments=40, num_labels=70, bit_depth=bits)
+    ys = np.concatenate([y.ravel() for y in wl.Y]).astype(np.int64)
+    assert ys.max() > 2048 and ((ys > 2048) & (ys % 2 == 1)).any()
+    G, lab = run_gpu(wl, pixels_per_step=npx)
+    r = compare(G, run_oracle(wl), label=f"arc {bits} bits")
+    assert r["max_err"] <= 1e-4, r
+    assert np.array_equal(lab, np.argmin(G, 1))
+    G1, _ = run_gpu(wl, pixels_per_step=1)
+    assert np.abs(G - G1).max() <= 1e-5
+    wn = P.tiny_problem(31, n_views=3, width=64, height=40, n_seg=5, L=70, bit_depth=bits)
+    assert max(int(y.max()) for y in wn.Y) > 2048
+    Gn, _ = run_gpu(wn, pixels_per_step=npx)
+    Gn1, _ = run_gpu(wn, pixels_per_step=1)
+    assert np.array_equal(Gn, Gn1)
+    r = compare(Gn, run_oracle(wn), label=f"rectified {bits} bits nearest")
+    assert r["max_err"] <= 1e-6, r
 
 
 @pytest.mark.parametrize("ref", ["rig", 0])
