@@ -528,6 +528,9 @@ def main():
     ap.add_argument("--shape-labels", default="128,256", help="shapes: level counts")
     ap.add_argument("--no-tune", action="store_true", help="shapes: the default launch shape only")
     ap.add_argument("--compare-px", action="store_true", help="shapes: also time the pixel-pair sweep")
+    ap.add_argument("--bit-depth", type=int, default=10,
+                    help="shapes: sample bit depth of the scene (8-16; texel channels are FP16 up to 11 bits, "
+                         "16-bit code values above)")
     ap.add_argument("--pixels-per-step", type=int, default=0,
                     help="1 one-pixel sweep, 2 or 4 pixels per wave step; 0 the library's choice")
     ap.add_argument("--tune-cache", default=None,

@@ -392,8 +392,9 @@ def bench_served(args):
 # ---------------------------------------------------------------- shapes
 def bench_shapes(args):
     """Sweep rate of the plain single-frame call by shape class: the 8-view
-    1920x1080 arc scene segmented into 5000, 10000, 20000 and 40000 segments
-    per view (the batching workload's range) at 128 and 256 levels, each
+    1920x1080 arc scene (10-bit, or --bit-depth) segmented into 5000, 10000,
+    20000 and 40000 segments per view (the batching workload's range) at 128
+    and 256 levels, each
     with the launch shape the autotuner picks for it (cached per shape
     class).  Explains per-frame rates inside a batch."""
     import torch
@@ -405,7 +406,8 @@ def bench_shapes(args):
     lab_list = [int(x) for x in args.shape_labels.split(",")]
     for S in seg_list:
         t0 = time.perf_counter()
-        wl = synth.make_arc_workload(f"shapes-S{S}", synth.SEED_BATCH + 5, n_segments=S, num_labels=256)
+        wl = synth.make_arc_workload(f"shapes-S{S}", synth.SEED_BATCH + 5, n_segments=S, num_labels=256,
+                                     bit_depth=args.bit_depth)
         dv = ivde.DeviceViews.from_workload(wl)
         _log(f"S={S}: generated in {time.perf_counter() - t0:.1f} s, {dv.rows} rows")
         for L in lab_list:
@@ -451,7 +453,7 @@ def bench_shapes(args):
                                           f"{res['tuned']['waves_per_group']}: {res['tuned']['sweep_ms']:.2f} ms)"))
             rows.append(row)
         del dv
-    return {"mode": "shapes", "workload": "8-view 1920x1080 YUV420 10-bit arc rig, bilinear, FP32 costs",
+    return {"mode": "shapes", "workload": f"8-view 1920x1080 YUV420 {args.bit_depth}-bit arc rig, bilinear, FP32 costs",
             "timing": f"median of {args.steps} event-timed sweeps per shape", "rows": rows}
 
 
