@@ -15,6 +15,7 @@
 // fault).  Per-row results are produced entirely inside one wave in a fixed
 // order, so single-frame, batched and served calls give bitwise equal costs.
 #include <algorithm>
+#include <type_traits>
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -835,7 +836,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // (halves up to 11 bits, code values above), exact either way.
 // The two halves' sums and counts meet through one cross-lane exchange per
 // (target, pass).
-constexpr int kPairStage = 256;   // records one wave stages at a time (16 B + 2 B each)
+constexpr int kPairStage = 256;   // records one wave stages at a time (16 B + 2 B, or 16 B + 8 B, each)
+
+// What the stage keeps beside each 16-byte projected record: Cr as an FP16
+// channel, or, with 16-bit code values, Cb and Cr as FP32 (the record's
+// fourth word then holds Y as FP32), so that the sweep converts no
+// reference colour per step.
+template <bool U16>
+using PairSide = std::conditional_t<U16, uint2, uint16_t>;
 
 // Two reference colours (code values) in the 16-bit channels the texels use.
 template <bool U16>
@@ -873,7 +881,8 @@ __device__ __forceinline__ void stage_records(const float *__restrict__ pix, int
 // (non-zero there, since the level point has finite positive depth) gives
 // q' + sigma e with q' = q / (g . p~), which projects to the same pixel, and
 // the target's validity needs no sign test.  The stage holds {q'x, q'y,
-// q'z, Y | Cb} and the Cr half beside it, in cr.
+// q'z, Y | Cb} and the Cr channel beside it, in cr; with 16-bit code values
+// {q'x, q'y, q'z, Y} and {Cb, Cr}, all FP32.
 //
 // Returns true (wave-uniform) when every staged record's samples at levels
 // sig_a .. sig_b lie inside the validity band.  The level points of one
@@ -886,7 +895,8 @@ constexpr float kInside = 1.0f / 16.0f;
 
 template <bool U16>
 __device__ __forceinline__ bool stage_projected(const float *__restrict__ pix, int i0, int n, const float (&H)[9],
-                                                const Target &T, float sig_a, float sig_b, uint4 *st, uint16_t *cr)
+                                                const Target &T, float sig_a, float sig_b, uint4 *st,
+                                                PairSide<U16> *cr)
 {
     const int lane = lane_id();
     bool outside = false;
@@ -901,9 +911,15 @@ __device__ __forceinline__ bool stage_projected(const float *__restrict__ pix, i
             const float qx = fmaf(H[0], x, fmaf(H[1], y, H[2])) * rg;
             const float qy = fmaf(H[3], x, fmaf(H[4], y, H[5])) * rg;
             const float qz = fmaf(H[6], x, fmaf(H[7], y, H[8])) * rg;
-            st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz),
-                               pack_ch<U16>(r0.w, r1.x));
-            cr[t] = (uint16_t)pack_ch<U16>(r1.y, 0.f);
+            if constexpr (U16) {
+                st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz),
+                                   __float_as_uint(r0.w));
+                cr[t] = make_uint2(__float_as_uint(r1.x), __float_as_uint(r1.y));
+            } else {
+                st[t] = make_uint4(__float_as_uint(qx), __float_as_uint(qy), __float_as_uint(qz),
+                                   pack_ch<false>(r0.w, r1.x));
+                cr[t] = (uint16_t)pack_ch<false>(r1.y, 0.f);
+            }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const float w = k ? sig_b : sig_a;
@@ -959,11 +975,12 @@ __device__ __forceinline__ void project_pair(const Target &T, float qx, float qy
     }
 }
 
-// |dY| + |dCb| + |dCr| of one evaluation against reference colours held in
-// the texels' 16-bit channels (rz = Y | Cb, rw = Cr), with the weights
-// formed from the bilinear fractions as project_issue forms them.
+// |dY| + |dCb| + |dCr| of one evaluation against reference colours
+// (ry, ru, rv), with the weights formed from the bilinear fractions as
+// project_issue forms them.
 template <bool BIL, bool U16>
-__device__ __forceinline__ float consume_pair(const Sample<BIL> &smp, float ax, float ay, uint32_t rz, uint32_t rw)
+__device__ __forceinline__ float consume_pair(const Sample<BIL> &smp, float ax, float ay, float ry, float ru,
+                                              float rv)
 {
     float tY, tU, tV;
     if constexpr (BIL) {
@@ -972,9 +989,9 @@ __device__ __forceinline__ float consume_pair(const Sample<BIL> &smp, float ax, 
         wt.w01 = ax - wt.w11;
         wt.w10 = ay - wt.w11;
         wt.w00 = (1.f - ax) - wt.w10;
-        tY = fmaf(ch_lo<U16>(smp.a.x), wt.w00, -ch_lo<U16>(rz));
-        tU = fmaf(ch_hi<U16>(smp.a.x), wt.w00, -ch_hi<U16>(rz));
-        tV = fmaf(ch_lo<U16>(smp.a.y), wt.w00, -ch_lo<U16>(rw));
+        tY = fmaf(ch_lo<U16>(smp.a.x), wt.w00, -ry);
+        tU = fmaf(ch_hi<U16>(smp.a.x), wt.w00, -ru);
+        tV = fmaf(ch_lo<U16>(smp.a.y), wt.w00, -rv);
         tY = fmaf(ch_lo<U16>(smp.a.z), wt.w01, tY);
         tU = fmaf(ch_hi<U16>(smp.a.z), wt.w01, tU);
         tV = fmaf(ch_lo<U16>(smp.a.w), wt.w01, tV);
@@ -985,11 +1002,19 @@ __device__ __forceinline__ float consume_pair(const Sample<BIL> &smp, float ax, 
         tU = fmaf(ch_hi<U16>(smp.b.z), wt.w11, tU);
         tV = fmaf(ch_lo<U16>(smp.b.w), wt.w11, tV);
     } else {
-        tY = ch_lo<U16>(smp.a.x) - ch_lo<U16>(rz);
-        tU = ch_hi<U16>(smp.a.x) - ch_hi<U16>(rz);
-        tV = ch_lo<U16>(smp.a.y) - ch_lo<U16>(rw);
+        tY = ch_lo<U16>(smp.a.x) - ry;
+        tU = ch_hi<U16>(smp.a.x) - ru;
+        tV = ch_lo<U16>(smp.a.y) - rv;
     }
     return fabsf(tY) + fabsf(tU) + fabsf(tV);
+}
+
+// The same against reference colours packed in the texels' 16-bit channels
+// (rz = Y | Cb, rw = Cr).
+template <bool BIL, bool U16>
+__device__ __forceinline__ float consume_pair(const Sample<BIL> &smp, float ax, float ay, uint32_t rz, uint32_t rw)
+{
+    return consume_pair<BIL, U16>(smp, ax, ay, ch_lo<U16>(rz), ch_hi<U16>(rz), ch_lo<U16>(rw));
 }
 
 // Pairs of staged records [0, m) towards one target at one pass (lane k of
@@ -1053,12 +1078,25 @@ __device__ __forceinline__ void sweep_pair_records(const uint4 *st, int m, int h
     }
 }
 
+// One evaluation against a projected record's colours: the record's fourth
+// word and what the stage keeps beside it (PairSide).
+template <bool BIL, bool U16>
+__device__ __forceinline__ float consume_projected(const Sample<BIL> &smp, float ax, float ay, uint32_t rw4,
+                                                   PairSide<U16> side)
+{
+    if constexpr (U16)
+        return consume_pair<BIL, true>(smp, ax, ay, __uint_as_float(rw4), __uint_as_float(side.x),
+                                       __uint_as_float(side.y));
+    else
+        return consume_pair<BIL, false>(smp, ax, ay, rw4, (uint32_t)side);
+}
+
 // Pairs of projected records [0, m) (stage_projected) towards a target
 // proven in front of every level point, at one pass (lane k of either half
 // at level sig): as sweep_pair_records with h = q' + sig e; FRONT 3 when
 // every sample of the chunk lies inside the validity band.
 template <int PU, bool BIL, int FRONT, int G, bool U16>
-__device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint16_t *cr, int m, int h,
+__device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const PairSide<U16> *cr, int m, int h,
                                                      const Target &T, float sig, float &acc, uint64_t &acci,
                                                      int &cnt)
 {
@@ -1067,7 +1105,8 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
         Sample<BIL> smp[PU];
         float ax[PU], ay[PU];
         bool val[PU];
-        uint32_t rz[PU], rw[PU];
+        uint32_t rz[PU];
+        PairSide<U16> rw[PU];
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             const uint4 r = st[i + G * u + h];
@@ -1079,7 +1118,7 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
         if constexpr (PU > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
-            const float d = consume_pair<BIL, U16>(smp[u], ax[u], ay[u], rz[u], rw[u]);
+            const float d = consume_projected<BIL, U16>(smp[u], ax[u], ay[u], rz[u], rw[u]);
             if constexpr (BIL)
                 acc += val[u] ? d : 0.f;
             else
@@ -1098,7 +1137,7 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const uint
         project_pair<BIL, FRONT>(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), sig, smp, ax,
                                  ay, val);
         val &= here;
-        const float d = consume_pair<BIL, U16>(smp, ax, ay, r.w, cr[jj]);
+        const float d = consume_projected<BIL, U16>(smp, ax, ay, r.w, cr[jj]);
         if constexpr (BIL)
             acc += val ? d : 0.f;
         else
@@ -1141,7 +1180,7 @@ struct PairSteps {
 // 64 b + (64 / G) q + k in pass q.
 template <bool BIL, bool F16OUT, int G, bool U16>
 __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
-                                                 uint16_t *cr, PairSteps &ns)
+                                                 PairSide<U16> *cr, PairSteps &ns)
 {
     constexpr int PU = IVDE_PAIR_INFLIGHT;
     constexpr int PW = kWave / G;   // lanes per group = levels per pass
@@ -1280,7 +1319,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     extern __shared__ uint4 pair_stage[];
     const int wave = (int)(threadIdx.x / kWave), wpg = (int)(blockDim.x / kWave);
     uint4 *st = pair_stage + wave * kPairStage;
-    uint16_t *cr = reinterpret_cast<uint16_t *>(pair_stage + wpg * kPairStage) + wave * kPairStage;
+    PairSide<U16> *cr = reinterpret_cast<PairSide<U16> *>(pair_stage + wpg * kPairStage) + wave * kPairStage;
     const int lane = lane_id();
     const int64_t limit = min((int64_t)ldu(n_tasks), max_tasks);
     // per-XCD ranges and work stealing as in sweep_persistent_body
@@ -1526,8 +1565,11 @@ hipError_t launch_worklist(const Problem *dprob, const Extents &ext, int problem
 }
 
 // Dynamic LDS of the pixel-pair sweep: one record stage per wave (16-byte
-// records, then the 2-byte Cr halves of the projected form).
-static size_t pair_stage_bytes(int wpg) { return (size_t)wpg * kPairStage * (sizeof(uint4) + sizeof(uint16_t)); }
+// records, then what the projected form keeps beside each, PairSide).
+static size_t pair_stage_bytes(int wpg, bool u16)
+{
+    return (size_t)wpg * kPairStage * (sizeof(uint4) + (u16 ? sizeof(uint2) : sizeof(uint16_t)));
+}
 
 template <int J, bool BIL, bool U16, bool F16OUT>
 static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int32_t *n_tasks, int32_t *cursors,
@@ -1536,10 +1578,10 @@ static hipError_t sweep_pers(const Problem *dprobs, const Task *tasks, const int
     if constexpr (J == 1) {
         if (px == 4)
             hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 4, U16>), dim3((unsigned)n_groups), dim3(64 * wpg),
-                               pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
+                               pair_stage_bytes(wpg, U16), s, dprobs, tasks, n_tasks, cursors, max_tasks);
         else if (px == 2)
             hipLaunchKernelGGL((k_sweep_pairs<BIL, F16OUT, 2, U16>), dim3((unsigned)n_groups), dim3(64 * wpg),
-                               pair_stage_bytes(wpg), s, dprobs, tasks, n_tasks, cursors, max_tasks);
+                               pair_stage_bytes(wpg, U16), s, dprobs, tasks, n_tasks, cursors, max_tasks);
         else
             hipLaunchKernelGGL((k_sweep_persistent_j1<BIL, F16OUT, U16>), dim3((unsigned)n_groups), dim3(64 * wpg), 0,
                                s, dprobs, tasks, n_tasks, cursors, max_tasks);
@@ -1569,10 +1611,10 @@ static hipError_t occ(int px, int wpg, int *per_cu)
     if constexpr (J == 1) {
         if (px == 4)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 4, U16>, 64 * wpg,
-                                                                pair_stage_bytes(wpg));
+                                                                pair_stage_bytes(wpg, U16));
         if (px == 2)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_pairs<BIL, F16OUT, 2, U16>, 64 * wpg,
-                                                                pair_stage_bytes(wpg));
+                                                                pair_stage_bytes(wpg, U16));
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent_j1<BIL, F16OUT, U16>, 64 * wpg,
                                                             0);
     } else

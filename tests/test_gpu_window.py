@@ -89,6 +89,7 @@ def test_hand_case_on_gpu():
 
 @pytest.mark.parametrize("seed,rotated,chroma,bits,radius", [
     (1, False, 0, 8, 1), (2, True, 1, 10, 1), (3, True, 0, 8, 2), (4, True, 1, 12, 1), (5, False, 1, 10, 0),
+    (6, True, 0, 16, 1), (7, True, 1, 16, 2),
 ])
 def test_window_tiny(seed, rotated, chroma, bits, radius):
     _case(f"window tiny {seed}")
