@@ -28,7 +28,7 @@ def _case(name):
     print(f"[case] {name}", flush=True)
 
 
-def _small_frames(n, seed=100):
+def _small_frames(n, seed=100, bits=10):
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
@@ -36,7 +36,8 @@ def _small_frames(n, seed=100):
         L = int(rng.choice([24, 64, 70, 130]))
         nv = int(rng.integers(2, 5))
         out.append(synth.make_small_arc(seed=seed + i, n_views=nv, width=int(rng.integers(60, 140)),
-                                        height=int(rng.integers(40, 90)), n_segments=S, num_labels=L))
+                                        height=int(rng.integers(40, 90)), n_segments=S, num_labels=L,
+                                        bit_depth=bits))
     return out
 
 
@@ -95,6 +96,38 @@ def test_batched_mixed_label_counts_other_shapes():
         for f, r in zip(frames, ref):
             assert torch.equal(f[2], r)
         b.close()
+
+
+@pytest.mark.parametrize("bits", [12, 16])
+def test_batched_high_bit_depth(bits):
+    """Frames of 12- or 16-bit content (texels of 16-bit code values) in one
+    batch with the default launch shape, so each frame's pixels per step is
+    the library's choice for it: eager and graph replays bitwise equal to
+    each frame's plain call, one frame against the oracle."""
+    _case(f"batched {bits} bits")
+    wls = _small_frames(4, seed=500 + bits, bits=bits)
+    opt = ivde.options(ivde.BILINEAR, ivde.F32)
+    ref, frames, forms = [], [], set()
+    for wl in wls:
+        dv, lr, C = _plain(wl, opt)
+        forms.add(ivde.sweep_shape(dv, lr, opt)[2])
+        ref.append(C.clone())
+        frames.append((dv, lr, torch.full_like(C, -7.0), torch.full((C.shape[0],), -1, dtype=torch.int32,
+                                                                    device="cuda")))
+    assert forms <= {2, 4} and forms, forms
+    b = ivde.Batch(frames, opt)
+    for use_graph in (False, True, True):
+        for _, _, cost, lab in frames:
+            cost.fill_(-7.0)
+            lab.fill_(-1)
+        torch.cuda.synchronize()
+        b.run(stream=torch.cuda.Stream(), use_graph=use_graph)
+        torch.cuda.synchronize()
+        for (dv, lr, cost, lab), r in zip(frames, ref):
+            assert torch.equal(cost, r), f"graph={use_graph}"
+            assert torch.equal(lab, ivde.argmin(r)), f"graph={use_graph}"
+    b.close()
+    compare(ref[1].double().cpu().numpy(), run_oracle(wls[1]), label=f"batched {bits}-bit frame 1")
 
 
 @pytest.mark.timeout(1200)
@@ -262,9 +295,9 @@ def test_precision_4k_full_size():
 
 
 # ---------------------------------------------------------------- serving
-def _rig_sequence(seed, n_views, width, height, n_seg, L, n_frames):
+def _rig_sequence(seed, n_views, width, height, n_seg, L, n_frames, bits=10):
     wl = synth.make_small_arc(seed=seed, n_views=n_views, width=width, height=height, n_segments=n_seg,
-                              num_labels=L)
+                              num_labels=L, bit_depth=bits)
     frames = synth.make_sequence(wl, n_frames, seed=seed + 1)
     return wl, frames
 
@@ -292,9 +325,10 @@ class _Rig:
         return srv.submit(self.id, self.images[i].c_images, self.masks[i], self.out[i], self.lab[i])
 
 
-def test_served_frames_match_oracle_and_carry_rows():
-    _case("served vs oracle")
-    wl, frames = _rig_sequence(40, 4, 144, 80, 120, 64, 4)
+@pytest.mark.parametrize("bits", [10, 16])
+def test_served_frames_match_oracle_and_carry_rows(bits):
+    _case(f"served vs oracle, {bits} bits")
+    wl, frames = _rig_sequence(40, 4, 144, 80, 120, 64, 4, bits=bits)
     srv = ivde.Server(2 << 30, max_slots=2)
     rig = _Rig(srv, wl, frames, ivde.F32)
     stats = [srv.wait(rig.submit(srv, i)) for i in range(len(frames))]
