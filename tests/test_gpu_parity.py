@@ -169,6 +169,24 @@ def test_arc_1080p_full_volume():
     print(f"arc 1080p full volume: {r}, entries above 1e-3: {n_big}, largest {worst:.3g}", flush=True)
 
 
+@pytest.mark.parametrize("bits", [12, 16])
+def test_arc_1080p_high_bit_depth_sampled_rows(bits):
+    """The 8-view 1920x1080 arc scene rendered at 12 or 16 bits (texels of
+    16-bit code values), 20000 segments, 256 labels, bilinear, FP32, in the
+    default launch shape: 4000 seeded rows against the oracle at the mean,
+    sentinel and strict-argmin bars, every entry off by more than 1e-3
+    explained by a sample at the bilinear validity edge."""
+    _print_case(f"arc 1080p {bits}-bit sampled rows")
+    wl = synth.make_arc_workload(f"arc-8x1920x1080-{bits}bit", synth.SEED_ARC_1080P, bit_depth=bits)
+    G, lab = run_gpu(wl)
+    assert np.array_equal(lab, np.argmin(G, 1))
+    rows = np.sort(np.random.default_rng(40 + bits).choice(G.shape[0], 4000, replace=False))
+    O = run_oracle(wl, rows=rows)
+    r = compare(G[rows], O, label=f"arc 1080p {bits}-bit")
+    n_big, worst = assert_large_errors_explained(wl, G[rows], O, rows=rows, label=f"arc 1080p {bits}-bit")
+    print(f"arc 1080p {bits}-bit rows: {r}, entries above 1e-3: {n_big}, largest {worst:.3g}", flush=True)
+
+
 @pytest.mark.parametrize("bilinear", [False, True])
 def test_thirty_two_views(bilinear):
     """The largest rig the library takes: 32 views of a converging arc,
