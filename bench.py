@@ -101,6 +101,7 @@ _CLASS_OF = [("v_fma_f32", 0), ("v_fmac_f32", 1), ("v_mul_f32", 2), ("v_add_f32_
              ("v_sub_f32", 4), ("v_mov_b32", 5), ("v_fma_mix_f32", 7), ("v_med3_f32", 8), ("v_fract_f32", 9),
              ("v_cvt_", 10), ("v_cmp_", 11), ("v_cndmask_b32", 12), ("v_rcp_f32", 13), ("v_mad_u32_u24", 14),
              ("v_lshlrev_b32", 15), ("v_addc_co_u32", 16), ("v_add_u32", 17)]
+_CLASS_OF.insert(10, ("v_cvt_f32_u32_sdwa", 18))      # before the other conversions
 _HALF_RATE_DEFAULT = 7
 
 
@@ -127,21 +128,27 @@ def calibrate():
     return {"valu": classes, "gather": {"cycles_per_load_per_cu": cyc.value, "clock_ghz": ghz.value}}
 
 
-SWEEP_FORMS = {1: "k_sweep_persistent_j1 (bilinear, half texels, FP32 store; one pixel at 64 levels per wave step)",
-               2: "k_sweep_pairs (bilinear, half texels, FP32 store; two pixels at 32 levels per wave step, records "
+SWEEP_FORMS = {1: "k_sweep_persistent_j1 (bilinear, {tex}, FP32 store; one pixel at 64 levels per wave step)",
+               2: "k_sweep_pairs (bilinear, {tex}, FP32 store; two pixels at 32 levels per wave step, records "
                   "staged in LDS)",
-               4: "k_sweep_pairs (bilinear, half texels, FP32 store; four pixels at 16 levels per wave step, records "
+               4: "k_sweep_pairs (bilinear, {tex}, FP32 store; four pixels at 16 levels per wave step, records "
                   "staged in LDS)"}
 
 
-def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None):
+def texel_encoding(bit_depth: int) -> str:
+    return "texels of 16-bit code values" if bit_depth > 11 else "half texels"
+
+
+def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None, bit_depth=10):
     """The sweep's rooflines: VALU issue and texture gathers.  Each loop's
     instruction mix is recorded by the build from the kernel's assembly and
     priced with the calibrated issue costs; for the pixel-pair sweep the
     loops are weighted by the wave steps the kernel counted in each (steps =
     (all, on projected records, inside the validity band), from
-    ivde_workspace_sweep_steps; two or four pixels per step).  The binding unit is the one nearer its
-    ceiling."""
+    ivde_workspace_sweep_steps; two or four pixels per step).  Above 11 bits
+    the loops are those of the kernel for texels of 16-bit code values.  The
+    binding unit is the one nearer its ceiling."""
+    enc = "16" if bit_depth > 11 else ""
     from paper_1909_02294_amd import build as _b
     with open(_b.MIX_JSON) as fh:
         forms = json.load(fh)["forms"]
@@ -160,14 +167,15 @@ def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None):
         return cyc / mix["wave_steps_per_iteration"], mix["valu_instructions"] / mix["wave_steps_per_iteration"], classes
 
     if px == 1:
-        cyc, ins, classes = loop_cycles(forms["one_pixel"])
-        by_loop = {"one_pixel": evals / 64.0}
-        loops = {"one_pixel": classes}
-        simd_cycles = by_loop["one_pixel"] * cyc
-        instructions = by_loop["one_pixel"] * ins
+        name = "one_pixel" + enc
+        cyc, ins, classes = loop_cycles(forms[name])
+        by_loop = {name: evals / 64.0}
+        loops = {name: classes}
+        simd_cycles = by_loop[name] * cyc
+        instructions = by_loop[name] * ins
     else:
         all_, proj, inside = steps
-        pre = "pairs_" if px == 2 else "quads_"
+        pre = ("pairs" if px == 2 else "quads") + enc + "_"
         by_loop = {pre + "inside": inside, pre + "tested": proj - inside, pre + "records": all_ - proj}
         simd_cycles = instructions = 0.0
         loops = {}
@@ -199,7 +207,7 @@ def sweep_roofline(evals, sweep_s, calib, counters, px, steps=None):
         "bound": "gather" if primary is gather else "alu",
         "achieved": primary["achieved"], "peak": primary["peak"], "unit": primary["unit"], "frac": primary["frac"],
         "traffic": counters["hbm_bytes_per_launch"] if counters else None,
-        "kernel": SWEEP_FORMS[px],
+        "kernel": SWEEP_FORMS[px].format(tex=texel_encoding(bit_depth)),
         "what": primary["what"],
         "evals_per_launch": evals,
         "wave_steps": {k: int(v) for k, v in by_loop.items()},
@@ -262,8 +270,9 @@ def bench_plain(args):
     from paper_1909_02294_amd import ivde, synth
 
     t0 = time.perf_counter()
-    wl = synth.make_arc_1080p()
-    print(f"[bench] generated {wl.name} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    wl = synth.make_arc_1080p(bit_depth=args.bit_depth)
+    print(f"[bench] generated {wl.name} ({wl.bit_depth} bits) in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
     base = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=args.labels_per_lane,
@@ -310,7 +319,7 @@ def bench_plain(args):
     J, wpg, px = ivde.sweep_shape(dv, lr, base)
     if J == 1:
         steps = ivde.sweep_steps(ws, stream) if px in (2, 4) else None
-        roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters, px, steps)
+        roofline, classes = sweep_roofline(evals, sweep_avg_s, calib, counters, px, steps, wl.bit_depth)
     else:
         roofline, classes = {"note": f"no instruction model for {J} labels per lane"}, {}
     roofline["launch_shape"] = {"labels_per_lane": J, "waves_per_group": wpg, "pixels_per_step": px}
@@ -328,8 +337,8 @@ def bench_plain(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "8-view 1920x1080 YUV420 10-bit arc rig, 20000 weighted Voronoi segments per view (log-area sigma 0.5), "
-                        "256 inverse-depth labels over [1.5, 10] m, bilinear, FP32 cost volume",
+            "workload": f"8-view 1920x1080 YUV420 {wl.bit_depth}-bit arc rig, 20000 weighted Voronoi segments per view "
+                        "(log-area sigma 0.5), 256 inverse-depth labels over [1.5, 10] m, bilinear, FP32 cost volume",
             "views": wl.n_views, "width": 1920, "height": 1080, "segments": int(sum(wl.S)),
             "labels": wl.num_labels, "targets": "all other views", "evals_per_step": evals,
             "seed": wl.seed, "workload_sha": wl_sha, "log_area_sigma": wl.info["area_sigma"],
@@ -529,8 +538,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="shapes: the default launch shape only")
     ap.add_argument("--compare-px", action="store_true", help="shapes: also time the pixel-pair sweep")
     ap.add_argument("--bit-depth", type=int, default=10,
-                    help="shapes: sample bit depth of the scene (8-16; texel channels are FP16 up to 11 bits, "
-                         "16-bit code values above)")
+                    help="plain, shapes: sample bit depth of the 8-view 1080p scene (8-16; texel channels are FP16 "
+                         "up to 11 bits, 16-bit code values above); the headline is 10")
     ap.add_argument("--pixels-per-step", type=int, default=0,
                     help="1 one-pixel sweep, 2 or 4 pixels per wave step; 0 the library's choice")
     ap.add_argument("--tune-cache", default=None,

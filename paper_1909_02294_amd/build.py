@@ -92,6 +92,10 @@ SWEEP_SYMBOLS = {
     "one_pixel": "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
     "pairs": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi2ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
     "quads": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi4ELb0EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    # texels of 16-bit code values (12- to 16-bit content)
+    "one_pixel16": "_ZN4ivde12_GLOBAL__N_121k_sweep_persistent_j1ILb1ELb0ELb1EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "pairs16": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi2ELb1EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
+    "quads16": "_ZN4ivde12_GLOBAL__N_113k_sweep_pairsILb1ELb0ELi4ELb1EEEvPKNS_7ProblemEPKNS_4TaskEPKiPil",
 }
 
 
@@ -128,8 +132,10 @@ def sweep_mix(verbose: bool = False) -> dict:
     per wave step of two pixels at 32 levels): pairs_inside on projected
     records of chunks inside the validity band (no per-sample tests),
     pairs_tested on projected records with the band test, pairs_records on
-    {x, y} records with the sign tests.  Written next to the library for the
-    benchmark's issue model."""
+    {x, y} records with the sign tests; quads_* the same loops of the
+    four-pixel sweep; and each of these again, suffixed 16, for texels of
+    16-bit code values (one_pixel16, pairs16_*, quads16_*).  Written next to
+    the library for the benchmark's issue model."""
     import json
 
     with tempfile.TemporaryDirectory() as td:
@@ -147,7 +153,18 @@ def sweep_mix(verbose: bool = False) -> dict:
                          lambda ops, g: g == 6 and "ds_read_u16" in ops and "v_med3_f32" in ops, 3),
         "pairs_records": (SWEEP_SYMBOLS["pairs"], lambda ops, g: g == 6 and "ds_read_u16" not in ops, 3),
     }
-    for form in ("inside", "tested", "records"):   # four pixels per step: the same loops
+    # 16-bit code values: projected records read FP32 Cb, Cr beside the record
+    side16 = lambda ops: "ds_read_b64" in ops or "ds_read2_b64" in ops  # noqa: E731
+    # (the two-pixel kernel for them keeps two pairs in flight: 4 gathers per
+    # 2 wave steps; its four-pixel kernel three, as with halves)
+    for sym, pre, g_it in ((SWEEP_SYMBOLS["pairs16"], "pairs16_", 4), (SWEEP_SYMBOLS["quads16"], "quads16_", 6)):
+        steps = g_it // 2                          # two gathers per wave step
+        wanted[pre + "inside"] = (sym, lambda ops, g, n=g_it: g == n and side16(ops) and "v_med3_f32" not in ops,
+                                  steps)
+        wanted[pre + "tested"] = (sym, lambda ops, g, n=g_it: g == n and side16(ops) and "v_med3_f32" in ops, steps)
+        wanted[pre + "records"] = (sym, lambda ops, g, n=g_it: g == n and not side16(ops), steps)
+    wanted["one_pixel16"] = (SWEEP_SYMBOLS["one_pixel16"], lambda ops, g: g == 8, 4)
+    for form in ("inside", "tested", "records"):   # four pixels per step with halves: the pair loops
         sym, pick, steps = wanted["pairs_" + form]
         wanted["quads_" + form] = (SWEEP_SYMBOLS["quads"], pick, steps)
     forms = {}

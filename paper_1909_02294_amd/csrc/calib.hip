@@ -44,6 +44,9 @@ __device__ __forceinline__ void op(float &a, uint32_t &u, uint64_t m, float b, f
         asm volatile("v_addc_co_u32_e64 %0, %1, %0, %2, %3" : "+v"(u), "=s"(cy) : "v"(k), "s"(m));
         asm volatile("" ::"s"(cy));
     } else if constexpr (OP == 17) asm volatile("v_add_u32 %0, %0, %1" : "+v"(u) : "v"(k));
+    else if constexpr (OP == 18)   // the high 16-bit word of u to FP32 (texels of 16-bit code values)
+        asm volatile("v_cvt_f32_u32_sdwa %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1"
+                     : "=v"(a) : "v"(u));
 }
 
 template <int OP>
@@ -148,6 +151,7 @@ hipError_t launch_class(int cls, const Buffers &b, int iters, hipStream_t s)
     case 15: return launch_issue<15>(b, iters, s);
     case 16: return launch_issue<16>(b, iters, s);
     case 17: return launch_issue<17>(b, iters, s);
+    case 18: return launch_issue<18>(b, iters, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -155,8 +159,8 @@ hipError_t launch_class(int cls, const Buffers &b, int iters, hipStream_t s)
 const char *const kNames[] = {"v_fma_f32", "v_fmac_f32", "v_mul_f32", "v_add_f32", "v_sub_f32", "v_mov_b32",
                               "v_add_f32_abs", "v_fma_mix_f32", "v_med3_f32", "v_fract_f32", "v_cvt_i32_f32",
                               "v_cmp_f32", "v_cndmask_b32", "v_rcp_f32", "v_mad_u32_u24", "v_lshlrev_b32",
-                              "v_addc_co_u32", "v_add_u32"};
-constexpr int kClasses = 18;
+                              "v_addc_co_u32", "v_add_u32", "v_cvt_f32_u32_sdwa"};
+constexpr int kClasses = 19;
 
 }  // namespace
 

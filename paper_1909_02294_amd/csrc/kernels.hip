@@ -1157,6 +1157,11 @@ __device__ __forceinline__ void sweep_pair_projected(const uint4 *st, const Pair
 #ifndef IVDE_PAIR_INFLIGHT
 #define IVDE_PAIR_INFLIGHT 3
 #endif
+// With texels of 16-bit code values the two-pixel sweep keeps two pairs in
+// flight (75 VGPRs at six waves): 3-4% faster than three at 256 and 512
+// levels on the 8-view 1080p arc scene at 12 bits; the four-pixel sweep
+// keeps three (two were 2% slower at 128 levels), as do both with halves.
+#define IVDE_PAIR16_INFLIGHT 2
 #define IVDE_PAIR_WAVES_PER_SIMD 6
 // Four pixels per step keep four passes' sums, counts and levels live: at
 // six waves per SIMD they spilled 68 bytes outside the pixel loops; at five
@@ -1182,7 +1187,7 @@ template <bool BIL, bool F16OUT, int G, bool U16>
 __device__ __forceinline__ void sweep_task_pairs(const Problem *__restrict__ P, const Task task, uint4 *st,
                                                  PairSide<U16> *cr, PairSteps &ns)
 {
-    constexpr int PU = IVDE_PAIR_INFLIGHT;
+    constexpr int PU = (U16 && G == 2) ? IVDE_PAIR16_INFLIGHT : IVDE_PAIR_INFLIGHT;
     constexpr int PW = kWave / G;   // lanes per group = levels per pass
     const int lane = lane_id();
     const int h = lane / PW, k = lane % PW;
