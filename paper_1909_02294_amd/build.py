@@ -124,7 +124,7 @@ def _loops(text: str, symbol: str):
 
 def sweep_mix(verbose: bool = False) -> dict:
     """Instruction counts of the sweep's hot loops, from the gfx950 assembly
-    of this build (the bilinear FP32-store kernels; each loop's unrolled
+    of the library as compiled (the bilinear FP32-store kernels; each loop's unrolled
     copy, the one with the fewest compares where the kernel has several):
     one_pixel, the one-pixel sweep's four-pixel loop for targets proven in
     front of every level point (8 gathers, one wave step per pixel); and the
