@@ -271,8 +271,12 @@ def bench_plain(args):
 
     t0 = time.perf_counter()
     wl = synth.make_arc_1080p(bit_depth=args.bit_depth)
-    print(f"[bench] generated {wl.name} ({wl.bit_depth} bits) in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
+    if args.segment_ids == "random":
+        # the same segmentation with each view's ids in a seeded random order
+        rng = np.random.default_rng(7)
+        wl.seg = [rng.permutation(S)[np.asarray(m)].astype(np.int32) for S, m in zip(wl.S, wl.seg)]
+    print(f"[bench] generated {wl.name} ({wl.bit_depth} bits, {args.segment_ids} segment ids) in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dv = ivde.DeviceViews.from_workload(wl)
     lr = ivde.label_range(wl.z_near, wl.z_far, wl.num_labels)
     base = ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=args.labels_per_lane,
@@ -338,7 +342,8 @@ def bench_plain(args):
         "data": "synthetic",
         "config": {
             "workload": f"8-view 1920x1080 YUV420 {wl.bit_depth}-bit arc rig, 20000 weighted Voronoi segments per view "
-                        "(log-area sigma 0.5), 256 inverse-depth labels over [1.5, 10] m, bilinear, FP32 cost volume",
+                        "(log-area sigma 0.5), 256 inverse-depth labels over [1.5, 10] m, bilinear, FP32 cost volume" +
+                        (", segment ids randomly permuted per view" if args.segment_ids == "random" else ""),
             "views": wl.n_views, "width": 1920, "height": 1080, "segments": int(sum(wl.S)),
             "labels": wl.num_labels, "targets": "all other views", "evals_per_step": evals,
             "seed": wl.seed, "workload_sha": wl_sha, "log_area_sigma": wl.info["area_sigma"],
@@ -537,6 +542,9 @@ def main():
     ap.add_argument("--shape-labels", default="128,256", help="shapes: level counts")
     ap.add_argument("--no-tune", action="store_true", help="shapes: the default launch shape only")
     ap.add_argument("--compare-px", action="store_true", help="shapes: also time the pixel-pair sweep")
+    ap.add_argument("--segment-ids", choices=["raster", "random"], default="raster",
+                    help="plain: segment ids in raster order of their seed cells (as grid-seeded superpixels number "
+                         "them; the headline) or the same segmentation with each view's ids randomly permuted")
     ap.add_argument("--bit-depth", type=int, default=10,
                     help="plain, shapes: sample bit depth of the 8-view 1080p scene (8-16; texel channels are FP16 "
                          "up to 11 bits, 16-bit code values above); the headline is 10")
