@@ -169,6 +169,27 @@ def test_arc_1080p_full_volume():
     print(f"arc 1080p full volume: {r}, entries above 1e-3: {n_big}, largest {worst:.3g}", flush=True)
 
 
+@pytest.mark.parametrize("npx", [1, 2, 4])
+def test_segment_id_permutation_permutes_rows(npx):
+    """Renumbering a view's segments (the same segmentation) moves its rows
+    and changes nothing else: each segment's pixels are summed in raster
+    order whatever its id, and tasks are independent, so the permuted
+    volume is the original one with its rows permuted, bit for bit."""
+    import copy
+
+    _print_case(f"segment id permutation, {npx} px")
+    wl = synth.make_small_arc(seed=9, n_segments=60, num_labels=40)
+    G, _ = run_gpu(wl, pixels_per_step=npx)
+    rng = np.random.default_rng(3)
+    perms = [rng.permutation(S) for S in wl.S]
+    wp = copy.copy(wl)
+    wp.seg = [p[np.asarray(m)].astype(np.int32) for p, m in zip(perms, wl.seg)]
+    Gp, _ = run_gpu(wp, pixels_per_step=npx)
+    off = np.concatenate([[0], np.cumsum(wl.S)])
+    for c, p in enumerate(perms):
+        assert np.array_equal(Gp[off[c] + p], G[off[c]:off[c + 1]]), f"view {c}"
+
+
 @pytest.mark.parametrize("bits", [12, 16])
 def test_arc_1080p_high_bit_depth_sampled_rows(bits):
     """The 8-view 1920x1080 arc scene rendered at 12 or 16 bits (texels of
