@@ -628,7 +628,7 @@ def shape_class(dv: DeviceViews, lr: LabelRange, opt: Options) -> str:
     else:
         tg = dv.n - 1
     return (f"{'bil' if opt.sampling == BILINEAR else 'nn'}-{'f16' if opt.cost_dtype == F16 else 'f32'}"
-            f"-tex{'16' if dv.bit_depth <= 11 else '32'}-L{(lr.num_labels + 63) // 64 * 64}"
+            f"-tex{'f16' if dv.bit_depth <= 11 else 'u16'}-L{(lr.num_labels + 63) // 64 * 64}"
             f"-px{2 ** int(round(math.log2(max(px, 1.0))))}-t{tg}")
 
 

@@ -19,15 +19,17 @@ def test_shape_class_keys():
     lr = ivde.label_range(1.5, 10.0, 256)
     o = ivde.options(ivde.BILINEAR, ivde.F32)
     # 103.7 pixels per segment rounds to 128; 7 targets per view
-    assert ivde.shape_class(_dv(), lr, o) == "bil-f32-tex16-L256-px128-t7"
+    assert ivde.shape_class(_dv(), lr, o) == "bil-f32-texf16-L256-px128-t7"
     # 40000 segments: 51.8 pixels -> 64; 5000: 414.7 -> 512
     assert ivde.shape_class(_dv(S=40000), lr, o).endswith("-px64-t7")
     assert ivde.shape_class(_dv(S=5000), lr, o).endswith("-px512-t7")
     # levels round up to 64-level blocks; 250 and 256 share a class, 130 does not
     assert ivde.shape_class(_dv(), ivde.label_range(1.5, 10.0, 250), o) == ivde.shape_class(_dv(), lr, o)
     assert "-L192-" in ivde.shape_class(_dv(), ivde.label_range(1.5, 10.0, 130), o)
-    # texel format, storage, sampling and targets split classes
-    assert "-tex32-" in ivde.shape_class(_dv(bits=12), lr, o)
+    # texel encoding (FP16 channels up to 11 bits, 16-bit code values above), storage, sampling and
+    # targets split classes
+    assert "-texu16-" in ivde.shape_class(_dv(bits=12), lr, o)
+    assert "-texf16-" in ivde.shape_class(_dv(bits=11), lr, o)
     assert ivde.shape_class(_dv(), lr, ivde.options(ivde.NEAREST, ivde.F16)).startswith("nn-f16-")
     assert ivde.shape_class(_dv(), lr, ivde.options(targets=ivde.TARGETS_NEAREST_LR)).endswith("-t2")
 
@@ -47,9 +49,9 @@ def test_cached_class_is_not_timed_again(tmp_path, monkeypatch):
     best, table = ivde.autotune_cached(_dv(), lr, o, str(path))
     assert (best.labels_per_lane, best.waves_per_group) == (2, 4) and table is not None
     stored = json.loads(path.read_text())
-    assert stored["bil-f32-tex16-L256-px128-t7"]["labels_per_lane"] == 2
-    assert stored["bil-f32-tex16-L256-px128-t7"]["pixels_per_step"] == 1
-    assert "1x4x2" in stored["bil-f32-tex16-L256-px128-t7"]["us"]
+    assert stored["bil-f32-texf16-L256-px128-t7"]["labels_per_lane"] == 2
+    assert stored["bil-f32-texf16-L256-px128-t7"]["pixels_per_step"] == 1
+    assert "1x4x2" in stored["bil-f32-texf16-L256-px128-t7"]["us"]
     # same class (another segment count that rounds alike, 250 levels): from the file
     best2, table2 = ivde.autotune_cached(_dv(S=21000), ivde.label_range(1.5, 10.0, 250), o, str(path))
     assert table2 is None and (best2.labels_per_lane, best2.waves_per_group) == (2, 4)
