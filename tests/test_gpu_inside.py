@@ -1,6 +1,7 @@
-"""GPU test of the pixel-pair sweep's untested loop: chunks of projected
-records whose every sample was shown to lie inside the validity band run
-without the per-sample clamp and tests.  The measurement build
+"""GPU test of the pixel-pair sweep's untested loop, with FP16 and with
+16-bit code-value texels: chunks of projected records whose every sample
+was shown to lie inside the validity band run without the per-sample clamp
+and tests.  The measurement build
 libivde_tested.so runs the tested loop on those chunks as well; both builds
 must give bitwise the same cost volume, on rigs where many chunks take the
 untested loop (its step count shows it) and many do not."""
@@ -26,7 +27,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CASES = [("small_arc", dict(seed=41, n_views=4, width=160, height=96, n_segments=150, num_labels=70)),
          ("small_arc", dict(seed=42, n_views=6, width=480, height=270, n_segments=2500, num_labels=128)),
          ("small_arc", dict(seed=43, n_views=3, width=200, height=120, n_segments=9, num_labels=33)),
-         ("arc_1080p", {})]
+         ("arc_1080p", {}),
+         # texels of 16-bit code values: the same loops in the kernels for that encoding
+         ("small_arc", dict(seed=44, n_views=4, width=320, height=180, n_segments=600, num_labels=100,
+                            bit_depth=16)),
+         ("arc_1080p", dict(bit_depth=12))]
 FORMS = [("bil", "F32"), ("nn", "F32"), ("bil", "F16")]
 
 _CHILD = r"""
@@ -50,7 +55,7 @@ def workload(case):
     key = json.dumps(case)
     if key not in _WL:
         gen, kw = case
-        _WL[key] = synth.make_small_arc(**kw) if gen == "small_arc" else synth.make_arc_1080p()
+        _WL[key] = synth.make_small_arc(**kw) if gen == "small_arc" else synth.make_arc_1080p(**kw)
     return _WL[key]
 
 
