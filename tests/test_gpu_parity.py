@@ -48,14 +48,17 @@ def test_small_arc_bilinear_420(seed):
     assert r["max_err"] <= 1e-4, r
 
 
-@pytest.mark.parametrize("labels_per_lane,waves,px", [(1, 1, 2), (1, 2, 2), (1, 1, 1), (2, 2, 1), (4, 4, 1),
-                                                      (8, 1, 1)])
-def test_launch_shapes_give_identical_results(labels_per_lane, waves, px):
+@pytest.mark.parametrize("bits", [10, 16])
+@pytest.mark.parametrize("labels_per_lane,waves,px", [(1, 1, 2), (1, 2, 2), (1, 1, 4), (1, 1, 1), (2, 2, 1),
+                                                      (4, 4, 1), (8, 1, 1)])
+def test_launch_shapes_give_identical_results(labels_per_lane, waves, px, bits):
     """Within one sweep form (pixels per wave step) the launch shape never
     changes a result: each shape against one label per lane at 4 waves per
-    group (more labels per lane run the one-pixel form)."""
-    _print_case(f"launch shape J={labels_per_lane} wpg={waves} px={px}")
-    wl = P.synth.make_small_arc(seed=9, n_views=3, width=97, height=61, n_segments=60, num_labels=130)
+    group (more labels per lane run the one-pixel form), with FP16 and with
+    16-bit code-value texels."""
+    _print_case(f"launch shape J={labels_per_lane} wpg={waves} px={px} bits={bits}")
+    wl = P.synth.make_small_arc(seed=9, n_views=3, width=97, height=61, n_segments=60, num_labels=130,
+                                bit_depth=bits)
     G0, _ = run_gpu(wl, labels_per_lane=1, waves_per_group=4, pixels_per_step=px)
     G1, _ = run_gpu(wl, labels_per_lane=labels_per_lane, waves_per_group=waves, pixels_per_step=px)
     assert np.array_equal(G0, G1)
