@@ -94,6 +94,13 @@ def test_size_query(lib):
     lib.ivde_cost_volume_size(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
                               ctypes.byref(ivde.options(ivde.BILINEAR, ivde.F16)), 10, ctypes.byref(cb), None)
     assert cb.value == n * S * L * 2
+    # texels are 8 bytes at every bit depth (FP16 channels up to 11 bits, 16-bit code values above)
+    for bits in (8, 11, 12, 16):
+        wb2 = ctypes.c_size_t()
+        assert lib.ivde_cost_volume_size(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
+                                         ctypes.byref(ivde.options(ivde.BILINEAR, ivde.F32)), bits, None,
+                                         ctypes.byref(wb2)) == ivde.IVDE_OK
+        assert wb2.value == wb.value, bits
 
 
 def test_sweep_steps_needs_a_workspace(lib):
