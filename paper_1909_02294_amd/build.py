@@ -153,8 +153,10 @@ def sweep_mix(verbose: bool = False) -> dict:
                          lambda ops, g: g == 6 and "ds_read_u16" in ops and "v_med3_f32" in ops, 3),
         "pairs_records": (SWEEP_SYMBOLS["pairs"], lambda ops, g: g == 6 and "ds_read_u16" not in ops, 3),
     }
-    # 16-bit code values: projected records read FP32 Cb, Cr beside the record
-    side16 = lambda ops: "ds_read_b64" in ops or "ds_read2_b64" in ops  # noqa: E731
+    def side16(ops):
+        """16-bit code values: projected records read FP32 Cb, Cr beside the record."""
+        return "ds_read_b64" in ops or "ds_read2_b64" in ops
+
     # (the two-pixel kernel for them keeps two pairs in flight: 4 gathers per
     # 2 wave steps; its four-pixel kernel three, as with halves)
     for sym, pre, g_it in ((SWEEP_SYMBOLS["pairs16"], "pairs16_", 4), (SWEEP_SYMBOLS["quads16"], "quads16_", 6)):
