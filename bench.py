@@ -545,6 +545,8 @@ def main():
     ap.add_argument("--segment-ids", choices=["raster", "random"], default="raster",
                     help="plain: segment ids in raster order of their seed cells (as grid-seeded superpixels number "
                          "them; the headline) or the same segmentation with each view's ids randomly permuted")
+    ap.add_argument("--sampling", choices=["bilinear", "nearest"], default="bilinear",
+                    help="shapes: target sampling (the headline is bilinear)")
     ap.add_argument("--bit-depth", type=int, default=10,
                     help="plain, shapes: sample bit depth of the 8-view 1080p scene (8-16; texel channels are FP16 "
                          "up to 11 bits, 16-bit code values above); the headline is 10")

@@ -133,8 +133,8 @@ typedef struct {
  * for one label per lane, elsewhere the one-pixel sweep runs; 1 asks for
  * the one-pixel sweep, 0 picks the
  * default: four pixels where neighbouring levels land at least 3 px apart
- * (FP64 mean over each view's image centre projected into its targets),
- * else two.  The sweeps compute the same quantity but add a segment's
+ * (6 px with nearest sampling; FP64 mean over each view's image centre
+ * projected into its targets), else two.  The sweeps compute the same quantity but add a segment's
  * pixels in different orders and, towards targets proven in front of every
  * level point, the multi-pixel sweeps form a sample's projection from H p~
  * divided by g . p~: their FP32 results may differ in the last bits, and a

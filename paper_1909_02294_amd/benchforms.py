@@ -400,6 +400,7 @@ def bench_shapes(args):
     import torch
 
     rows = []
+    samp = ivde.NEAREST if args.sampling == "nearest" else ivde.BILINEAR
     cache = args.tune_cache
     stream = torch.cuda.current_stream()
     seg_list = [int(x) for x in args.shape_segments.split(",")]
@@ -412,7 +413,7 @@ def bench_shapes(args):
         _log(f"S={S}: generated in {time.perf_counter() - t0:.1f} s, {dv.rows} rows")
         for L in lab_list:
             lr = ivde.label_range(wl.z_near, wl.z_far, L)
-            base = ivde.options(ivde.BILINEAR, ivde.F32, pixels_per_step=args.pixels_per_step)
+            base = ivde.options(samp, ivde.F32, pixels_per_step=args.pixels_per_step)
             if args.no_tune:
                 tuned, table = base, None
             else:
@@ -422,13 +423,13 @@ def bench_shapes(args):
             if not args.no_tune:
                 variants.append(("tuned", tuned))
             if args.compare_px:
-                variants.append(("one", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=1)))
-                variants.append(("pairs", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=2)))
-                variants.append(("quads", ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=1, pixels_per_step=4)))
+                variants.append(("one", ivde.options(samp, ivde.F32, labels_per_lane=1, pixels_per_step=1)))
+                variants.append(("pairs", ivde.options(samp, ivde.F32, labels_per_lane=1, pixels_per_step=2)))
+                variants.append(("quads", ivde.options(samp, ivde.F32, labels_per_lane=1, pixels_per_step=4)))
             for name, o in variants:
                 ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                       for _ in range(args.steps)]
-                opts = [ivde.options(ivde.BILINEAR, ivde.F32, labels_per_lane=o.labels_per_lane,
+                opts = [ivde.options(samp, ivde.F32, labels_per_lane=o.labels_per_lane,
                                      waves_per_group=o.waves_per_group, sweep_events=e,
                                      pixels_per_step=o.pixels_per_step) for e in ev]
                 C, ws = ivde.cost_volume(dv, lr, opts[0])
@@ -453,7 +454,8 @@ def bench_shapes(args):
                                           f"{res['tuned']['waves_per_group']}: {res['tuned']['sweep_ms']:.2f} ms)"))
             rows.append(row)
         del dv
-    return {"mode": "shapes", "workload": f"8-view 1920x1080 YUV420 {args.bit_depth}-bit arc rig, bilinear, FP32 costs",
+    return {"mode": "shapes", "workload": f"8-view 1920x1080 YUV420 {args.bit_depth}-bit arc rig, {args.sampling}, "
+                                          "FP32 costs",
             "timing": f"median of {args.steps} event-timed sweeps per shape", "rows": rows}
 
 

@@ -269,8 +269,8 @@ static double level_step_px(int32_t n, const ivde_camera *cams, const ivde_label
     return cnt ? sum / cnt / (L - 1) : 0.0;
 }
 
-// Pixels per wave step of the sweep (one label per lane, half texels; the
-// one-pixel sweep elsewhere).  Two pixels at 32 levels per step (pairs) or
+// Pixels per wave step of the sweep (one label per lane; the one-pixel sweep
+// elsewhere).  Two pixels at 32 levels per step (pairs) or
 // four at 16 (quads) shorten the epipolar stretch every gather spans; towards
 // targets proven in front of every level point each sample's projection is
 // three multiply-adds on a staged record.  On the 8-view 1080p arc rig
@@ -282,13 +282,18 @@ static double level_step_px(int32_t n, const ivde_camera *cams, const ivde_label
 // close (256 levels, 2 px: 28.8-31.2 against 28.2-28.6 ms; 512 levels:
 // 54.4-59.6 against 53.7-54.4 ms): each pass then has four times the
 // groups' ragged tails and a quarter of the levels.  So: quads from 3 px
-// between neighbouring levels at the image centres, pairs below.
+// between neighbouring levels at the image centres, pairs below.  Nearest
+// sampling reads one texel per sample instead of four, so the shorter
+// stretch pays only further apart: on the same rig (20,000 segments) pairs
+// took 10.5 against 11.3 ms at 128 levels (4 px) and quads 6.6 against 7.4
+// ms at 64 (8 px); there quads start at 6 px.
 static int choose_px(int32_t n, const ivde_camera *cams, const ivde_label_range *labels, const ivde_options *opt,
                      int J)
 {
     if (J != 1) return 1;
     if (opt->pixels_per_step) return opt->pixels_per_step;
-    return level_step_px(n, cams, labels, opt) >= 3.0 ? 4 : 2;
+    const double quads_from = opt->sampling == IVDE_NEAREST ? 6.0 : 3.0;
+    return level_step_px(n, cams, labels, opt) >= quads_from ? 4 : 2;
 }
 
 Layout plan_layout(int32_t n, const ivde_camera *cams, const ivde_segmentation *segs, const ivde_label_range *labels,

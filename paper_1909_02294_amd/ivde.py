@@ -270,7 +270,8 @@ def options(sampling=BILINEAR, cost_dtype=F32, targets=TARGETS_ALL, target_mask=
     """sweep_events: optional pair of torch.cuda.Event(enable_timing=True),
     recorded by the library around its sweep kernel; pixels_per_step: 1 for
     the one-pixel sweep, 2 or 4 pixels per wave step, 0 the library's
-    choice (4 where neighbouring levels land 3 px or more apart, else 2)."""
+    choice (4 where neighbouring levels land 3 px or more apart, 6 px with
+    nearest sampling, else 2)."""
     o = Options(int(sampling), int(cost_dtype), int(targets), None, int(labels_per_lane), int(waves_per_group))
     o.pixels_per_step = int(pixels_per_step)
     if sweep_events is not None:

@@ -142,6 +142,23 @@ def test_sweep_shape_query(lib):
                                 ctypes.byref(ivde.options()), 10, ctypes.byref(j), ctypes.byref(wpg),
                                 ctypes.byref(px)) == ivde.IVDE_OK
     assert px.value == 4
+
+    # over level counts, four pixels where levels land far apart and two where close; nearest
+    # sampling (one texel per sample) needs twice the spacing (6 px against 3 px)
+    def px_for(L, samp):
+        lr_l = ivde.label_range(1.0, 5.0, L)
+        p = ctypes.c_int32()
+        assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr_l),
+                                    ctypes.byref(ivde.options(samp, ivde.F32)), 10, None, None,
+                                    ctypes.byref(p)) == ivde.IVDE_OK
+        return p.value
+
+    Ls = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 128, 256]
+    bil = [px_for(L, ivde.BILINEAR) for L in Ls]
+    nn = [px_for(L, ivde.NEAREST) for L in Ls]
+    for seq in (bil, nn):
+        assert seq[0] == 4 and seq[-1] == 2 and seq == sorted(seq, reverse=True), seq
+    assert all(b >= a for a, b in zip(nn, bil)) and nn != bil, (bil, nn)
     # outputs may be NULL; argument errors as for the size query
     assert lib.ivde_sweep_shape(n, _cams(n, w, h), _segs(n, S, w, h), ctypes.byref(lr),
                                 ctypes.byref(ivde.options()), 10, None, None, None) == ivde.IVDE_OK
